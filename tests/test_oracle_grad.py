@@ -1,0 +1,175 @@
+"""Pins for the oracle's analytic gradient (Supplementary D backward pass).
+
+* central finite differences (h = 1e-4) of the oracle's own FP64 forward, in
+  the smooth threshold mode where the map is differentiable;
+* an independent dense formulation written with torch float64 ops
+  (all-pairs alpha matrix, exclusive cumulative product for transmittance,
+  torch.fft for the angular spectrum) differentiated by autograd;
+* the per-parameter amplitude and phase formulas printed in Supplementary D.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import binning
+from scenegen import Optics, Scene, identity_camera, make_gaussians, make_targets, yaw_cameras
+
+torch.set_default_dtype(torch.float64)
+
+
+def _small_problem(n=30, H=40, W=48, seed=21, log_scale_mean=-2.8):
+    sc = make_gaussians(n, 2, seed, log_scale_mean=log_scale_mean, log_scale_std=0.3)
+    sc = Scene(*(a.astype(np.float64) for a in sc.arrays()))
+    cams = yaw_cameras((0.0, 8.0), (0.0, 0.0, 2.0), W, H, f=64)
+    opt = Optics((639e-9, 473e-9), (0.5e-3, 1.5e-3), 8e-6, 2, 2)
+    tg = make_targets((2, 2, 2, H, W), seed + 1)
+    return sc, cams, opt, tg
+
+
+def _loss(sc, cams, opt, tg, thr):
+    return oracle.forward(sc, cams, opt, thr, targets=tg)["loss"]
+
+
+def test_gradient_matches_central_differences():
+    sc, cams, opt, tg = _small_problem()
+    thr = oracle.SMOOTH
+    st = oracle.forward(sc, cams, opt, thr, targets=tg)
+    # depth keys must not swap under a perturbation of h (a depth moves by at most h)
+    for v in st["views"]:
+        k = np.sort(v["proj"].t[:, 2])
+        assert np.min(np.diff(k)) > 2.5e-4
+    grads = oracle.backward(st)
+    rng = np.random.default_rng(0)
+    names = ("means", "log_scales", "quats", "opacity", "amp", "phase")
+    h = 1e-4
+    checked = 0
+    for name in names:
+        arr = getattr(sc, name)
+        flat = arr.reshape(-1)
+        picks = rng.choice(flat.size, size=min(flat.size, 8), replace=False)
+        for i in picks:
+            old = flat[i]
+            flat[i] = old + h
+            lp = _loss(sc, cams, opt, tg, thr)
+            flat[i] = old - h
+            lm = _loss(sc, cams, opt, tg, thr)
+            flat[i] = old
+            fd = (lp - lm) / (2 * h)
+            an = grads[name].reshape(-1)[i]
+            scale = max(abs(fd), 1e-3 * np.max(np.abs(grads[name])), 1e-12)
+            assert abs(an - fd) <= 2e-5 * scale, (name, i, an, fd)
+            checked += 1
+    assert checked >= 40
+
+
+def _torch_dense_loss(params, sc, cams, opt, tg, thr):
+    """Independent dense formulation: every pixel against every Gaussian."""
+    means, log_scales, quats, opacity, amp, phase = params
+    total = 0.0
+    n_el = 0
+    for b, cam in enumerate(cams):
+        fp = binning.fp32_footprint(sc.means, sc.log_scales, sc.quats, cam, k_sigma=thr.k_sigma)
+        vis = torch.as_tensor(fp["visible"])
+        order = np.lexsort((np.arange(sc.n), fp["key"].astype(np.int64)))
+        q = quats / torch.linalg.norm(quats, dim=1, keepdim=True)
+        w, x, y, z = q.unbind(1)
+        R = torch.stack([
+            torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+            torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+            torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1),
+        ], 1)
+        S = torch.diag_embed(torch.exp(log_scales))
+        RS = R @ S
+        Sigma = RS @ RS.transpose(1, 2)
+        Wc = torch.as_tensor(np.asarray(cam.R, np.float64))
+        tcam = means @ Wc.T + torch.as_tensor(np.asarray(cam.t, np.float64))
+        fx, fy = float(np.float32(cam.fx)), float(np.float32(cam.fy))
+        cx, cy = float(np.float32(cam.cx)), float(np.float32(cam.cy))
+        tx, ty, tz = tcam.unbind(1)
+        zero = torch.zeros_like(tz)
+        J = torch.stack([torch.stack([fx / tz, zero, -fx * tx / tz ** 2], -1),
+                         torch.stack([zero, fy / tz, -fy * ty / tz ** 2], -1)], 1)
+        JW = J @ Wc
+        cov = JW @ Sigma @ JW.transpose(1, 2)
+        conic = torch.linalg.inv(cov)
+        mu = torch.stack([fx * tx / tz + cx, fy * ty / tz + cy], -1)
+        H, Wd = cam.height, cam.width
+        py, px = torch.meshgrid(torch.arange(H) + 0.5, torch.arange(Wd) + 0.5, indexing="ij")
+        pix = torch.stack([px.reshape(-1), py.reshape(-1)], -1)
+        d = pix[:, None, :] - mu[None]
+        power = 0.5 * torch.einsum("pgi,gij,pgj->pg", d, conic, d)
+        rect = torch.as_tensor(fp["rect"])
+        inrect = ((pix[:, None, 0] >= rect[None, :, 0] + 0.5) & (pix[:, None, 0] <= rect[None, :, 1] + 0.5)
+                  & (pix[:, None, 1] >= rect[None, :, 2] + 0.5) & (pix[:, None, 1] <= rect[None, :, 3] + 0.5))
+        oG = opacity[None] * torch.exp(-power)
+        a = torch.where(oG > thr.alpha_max, torch.full_like(oG, thr.alpha_max), oG)
+        sup = inrect & vis[None] & (power <= 0.5 * thr.k_sigma ** 2) & (a >= thr.alpha_min)
+        a = torch.where(sup, a, torch.zeros_like(a))
+        a = a[:, order]
+        T = torch.cumprod(torch.cat([torch.ones_like(a[:, :1]), 1 - a[:, :-1]], 1), 1)
+        v = torch.polar(amp, phase)[order]                      # [G, L]
+        U = torch.einsum("pg,gl->lp", (a * T).to(v.dtype), v).reshape(-1, H, Wd)
+        for li, lam in enumerate(opt.wavelengths):
+            P = torch.zeros((2 * H, 2 * Wd), dtype=U.dtype)
+            P[:H, :Wd] = U[li]
+            fy_ = torch.fft.fftfreq(2 * H, d=opt.pitch)[:, None]
+            fx_ = torch.fft.fftfreq(2 * Wd, d=opt.pitch)[None, :]
+            for ki, zz in enumerate(opt.distances):
+                Hz = torch.as_tensor(oracle.transfer_function(2 * H, 2 * Wd, opt.pitch, lam, zz, opt.band_limit))
+                u = torch.fft.ifft2(Hz * torch.fft.fft2(P))[:H, :Wd]
+                I = u.real ** 2 + u.imag ** 2
+                total = total + torch.sum((I - torch.as_tensor(tg[b, li, ki], dtype=torch.float64)) ** 2)
+                n_el += I.numel()
+    return total / n_el
+
+
+@pytest.mark.parametrize("mode", ["smooth", "default"])
+def test_gradient_matches_torch_dense_autograd(mode):
+    sc, cams, opt, tg = _small_problem(n=25, H=32, W=40, seed=31)
+    if mode == "smooth":
+        thr = oracle.SMOOTH
+    else:
+        # default support test and alpha clamp (some opacities clamp at alpha_max);
+        # the dense form has no early stop, so the scene must never reach T_min
+        thr = oracle.DEFAULT
+        sc.opacity[:6] = 0.9995
+    st = oracle.forward(sc, cams, opt, thr, targets=tg)
+    if mode == "default":
+        assert min(v["res"].T_final.min() for v in st["views"]) > thr.t_min
+        clamped = [np.any(sc.opacity[g] * 1.0 > thr.alpha_max) for g in range(6)]
+        assert any(clamped)
+    grads = oracle.backward(st)
+    params = [torch.tensor(a, requires_grad=True) for a in sc.arrays()]
+    loss = _torch_dense_loss(params, sc, cams, opt, tg, thr)
+    assert abs(loss.item() - st["loss"]) < 1e-12 * abs(st["loss"])
+    loss.backward()
+    for name, p in zip(("means", "log_scales", "quats", "opacity", "amp", "phase"), params):
+        ref = p.grad.numpy()
+        err = np.linalg.norm(grads[name] - ref) / np.linalg.norm(ref)
+        assert err < 1e-9, (name, err)
+
+
+def test_amplitude_and_phase_formulas_single_gaussian():
+    """dL/dc = a T (cos(phi) dL/dRe + sin(phi) dL/dIm);
+    dL/dphi = a T c (-sin(phi) dL/dRe + cos(phi) dL/dIm)   (Supplementary D)."""
+    cam = identity_camera(24, 24, f=300)
+    sc = Scene(np.array([[0.0, 0.0, 2.0]]), np.full((1, 3), math.log(0.05)), np.array([[1.0, 0, 0, 0]]),
+               np.array([0.7]), np.array([[0.8]]), np.array([[0.9]]))
+    thr = oracle.DEFAULT
+    p = oracle.project(sc.means, sc.log_scales, sc.quats, sc.amp, sc.phase, cam)
+    fp = oracle.fp32_footprint(sc.means, sc.log_scales, sc.quats, cam)
+    r = oracle.render_field(p, sc.opacity, fp, 24, 24, thr)
+    rng = np.random.default_rng(4)
+    G = rng.normal(size=(1, 24, 24)) + 1j * rng.normal(size=(1, 24, 24))
+    d_mu, d_conic, d_op, d_v = oracle.render_field_backward(p, sc.opacity, fp, r, G, thr)
+    from oracle.projection import project_backward
+    g = project_backward(p, sc.quats, sc.amp, sc.phase, cam, d_mu, d_conic, d_op, d_v)
+    aT = np.abs(r.U[0]) / 0.8           # a * T with T = 1 for the only Gaussian
+    c, ph = 0.8, 0.9
+    dc = np.sum(aT * (math.cos(ph) * G[0].real + math.sin(ph) * G[0].imag))
+    dphi = np.sum(aT * c * (-math.sin(ph) * G[0].real + math.cos(ph) * G[0].imag))
+    assert abs(g["amp"][0, 0] - dc) < 1e-12 * max(1, abs(dc))
+    assert abs(g["phase"][0, 0] - dphi) < 1e-12 * max(1, abs(dphi))
