@@ -1,0 +1,197 @@
+#!/usr/bin/env python
+"""Throughput of the complex-hologram hot path on one MI355X.
+
+A step is one pass of the whole path over one batch: projection and culling,
+tile binning and sort, complex compositing, band-limited ASM propagation to
+every plane, |u|^2, the MSE against seeded targets, and the full backward to
+the Gaussian parameters.  The default workload is 100,000 Gaussians rendered
+at 1080 x 1920 for three wavelengths and propagated to four planes (one view
+per step).  Inputs are synthetic and resident in HBM before timing starts.
+
+Prints one JSON line (see the keys below).  ``--gpus N`` with N > 1 is not
+supported: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
+
+
+def kernel_bytes(name, B, L, K, H, W, pH, pW, train):
+    """Algorithmic HBM bytes of one launch of each propagation kernel."""
+    c = 8  # complex64
+    table = {
+        "rows_forward": B * L * H * (W + pW) * c,
+        "cols_forward": B * L * (H * pW + K * H * pW) * c,
+        "rows_inverse": B * L * K * H * (pW * c + (pW * c + W * 4 if train else W * 4)),
+        "cols_adjoint": B * L * (K * H * pW + H * pW) * c,
+        "rows_adjoint_out": B * L * H * (pW + W) * c,
+    }
+    return table.get(name)
+
+
+def cpu_baseline(w, seed=0):
+    """Time the CPU oracle on a bounded sample of the workload.
+
+    Sample: the projection plus the compositing forward and backward of all
+    Gaussians and all wavelengths restricted to the central 1/16 of the frame
+    (a 270 x 480 window, the densest part of the image), plus one full-size
+    propagation and its adjoint for one (wavelength, plane) pair.  The frame
+    time is extrapolated as 16 x window + (L x K) x propagation pair.
+    """
+    import numpy as np
+    import oracle
+    from oracle.projection import project_backward
+
+    sc, cam, opt = w.scene, w.cameras[0], w.optics
+    H, W = cam.height, cam.width
+    thr = oracle.DEFAULT
+    win = (H * 3 // 8, H * 5 // 8, W * 3 // 8, W * 5 // 8)
+    frac = ((win[1] - win[0]) * (win[3] - win[2])) / float(H * W)
+    t0 = time.perf_counter()
+    p = oracle.project(sc.means, sc.log_scales, sc.quats, sc.amp, sc.phase, cam)
+    fp = oracle.fp32_footprint(sc.means, sc.log_scales, sc.quats, cam, k_sigma=thr.k_sigma)
+    res = oracle.render_field(p, sc.opacity, fp, W, H, thr, window=win)
+    rng = np.random.default_rng(seed)
+    G = np.zeros_like(res.U)
+    G[:, win[0]:win[1], win[2]:win[3]] = rng.normal(size=(sc.n_lambda, win[1] - win[0], win[3] - win[2]))
+    d = oracle.render_field_backward(p, sc.opacity, fp, res, G, thr, window=win)
+    project_backward(p, sc.quats, sc.amp, sc.phase, cam, *d)
+    t_raster = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    u = oracle.propagate(res.U[0], opt.wavelengths[0], opt.distances[0], opt.pitch, opt.pad, opt.band_limit)
+    oracle.propagate_adjoint(u, opt.wavelengths[0], opt.distances[0], opt.pitch, opt.pad, opt.band_limit)
+    t_asm = time.perf_counter() - t0
+    n_pairs = len(opt.wavelengths) * len(opt.distances)
+    t_frame = t_raster / frac + n_pairs * t_asm
+    return {
+        "value": 1.0 / t_frame, "unit": "frames/s", "cores": 1, "kind": "oracle",
+        "sample": (f"FP64 NumPy oracle, single thread: compositing fwd+bwd of all {sc.n} Gaussians x "
+                   f"{sc.n_lambda} wavelengths on the central {win[1] - win[0]}x{win[3] - win[2]} window "
+                   f"({t_raster:.1f} s, scaled x{1 / frac:.0f}) + one full-size propagation and adjoint "
+                   f"({t_asm:.1f} s, scaled x{n_pairs}); estimated {t_frame:.0f} s per frame"),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-table", action="store_true", help="also print the per-kernel table to stderr")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one GPU "
+              "(the path shards by views across GPUs, see the design notes)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2506_08350_amd import _lib, api
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = scenegen.make_workload("c3")          # c2 is the same scene and optics without the loss
+    sc, cams, opt = w.scene, w.cameras, w.optics
+    B, L, K = len(cams), sc.n_lambda, len(opt.distances)
+    H, W = cams[0].height, cams[0].width
+    pH, pW = opt.pad * H, opt.pad * W
+    train = args.workload == "c3"
+    o = api.Optics(opt.wavelengths, opt.distances, opt.pitch, opt.pad, opt.band_limit)
+    params = {k: torch.from_numpy(a).cuda() for k, a in zip(api.PARAM_NAMES, sc.arrays())}
+    cam_t = api.pack_cameras(cams)
+    target = torch.from_numpy(w.targets).cuda()
+
+    # size the pair list from one eager forward
+    r = api.Renderer(H, W, o, n_views=B, max_gaussians=sc.n, max_pairs=1 << 26)
+    r.forward(params, cam_t, want_field=False, want_intensity=False)
+    st, need = r.read_status()
+    cap = int(need * 1.25) + 4096
+    del r
+    r = api.Renderer(H, W, o, n_views=B, max_gaussians=sc.n, max_pairs=cap)
+
+    def step():
+        if train:
+            r.train_step(params, cam_t, target)
+        else:
+            r.forward(params, cam_t, want_field=False, want_intensity=True)
+
+    for _ in range(args.warmup):
+        step()
+    st, need = r.read_status()
+    if st != 0:
+        raise RuntimeError(f"pair list overflow: {need} > {cap}")
+    torch.cuda.synchronize()
+    r.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r.timing(False)
+    kt = r.timing_report()
+    ms = (t1 - t0) * 1000.0 / args.steps
+    value = B * 1000.0 / ms
+
+    # forward-only rate (intensities out), same scene and optics
+    fwd_ms = None
+    if train:
+        for _ in range(2):
+            r.forward(params, cam_t, want_field=False, want_intensity=True)
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        for _ in range(args.steps):
+            r.forward(params, cam_t, want_field=False, want_intensity=True)
+        torch.cuda.synchronize()
+        fwd_ms = (time.perf_counter() - f0) * 1000.0 / args.steps
+
+    # dominant propagation kernel against the HBM roofline
+    per_launch = {n: (c, tot / c) for n, (c, tot) in kt.items()}
+    asm = {n: v for n, v in per_launch.items() if kernel_bytes(n, B, L, K, H, W, pH, pW, train) is not None}
+    dom = max(asm, key=lambda n: asm[n][0] * asm[n][1])
+    dom_ms = asm[dom][1]
+    dom_bytes = kernel_bytes(dom, B, L, K, H, W, pH, pW, train)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_ms": round(dom_ms, 4), "algorithmic_bytes": dom_bytes}
+    if args.kernel_table:
+        tot = sum(c * m for c, m in per_launch.values())
+        for n, (c, m) in sorted(per_launch.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+            b = kernel_bytes(n, B, L, K, H, W, pH, pW, train)
+            bw = f"{b / (m * 1e-3) / 1e9:8.1f} GB/s" if b else ""
+            print(f"{n:18s} {c:4d} x {m:8.4f} ms  {100 * c * m / tot:5.1f}%  {bw}", file=sys.stderr)
+
+    line = {
+        "metric": "hologram frames/s (splat+ASM, fwd+bwd) 1080p x 3 wavelengths x 4 planes",
+        "value": round(value, 3), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c3_fwd_bwd_1080p_3l_4z_100k" if train else "c2_fwd_1080p_3l_4z_100k",
+                   "gaussians": sc.n, "height": H, "width": W, "wavelengths": L, "planes": K,
+                   "views_per_step": B, "pad": opt.pad, "pairs": int(need), "parallelism": "single-gpu"},
+        "fwd_frames_per_s": round(1000.0 / fwd_ms * B, 3) if fwd_ms else None,
+        "fwd_ms": round(fwd_ms, 4) if fwd_ms else None,
+        "roofline": roofline,
+        "kernels_ms_per_step": {n: round(c * m / args.steps, 4) for n, (c, m) in per_launch.items()},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

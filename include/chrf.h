@@ -1,0 +1,235 @@
+/*
+ * chrf.h -- C ABI of the MI355X (gfx950) complex-hologram renderer.
+ *
+ * The library renders complex-valued 3D Gaussians into a complex field and
+ * propagates it to several planes with the band-limited angular spectrum
+ * method, then returns |u|^2 per plane; it also runs the analytic backward of
+ * that map.  The calls follow the problem statement of the paper
+ * (Complex-Valued Holographic Radiance Fields, Sec. 3 "Hologram Plane, Camera
+ * and Problem Definition"): Gaussians k = (c, x, R, S, alpha, phi) (Sec. 4.1,
+ * Eq. 9), a camera with pitch and resolution, wavelengths and propagation
+ * distances in; the complex field U and the intensities I_l = |u_l|^2
+ * (Eq. 16) out.
+ *
+ * Conventions shared by every call
+ * - All array arguments are device pointers to caller-owned memory (for
+ *   example torch tensors), FP32, C-contiguous, unless a comment says "host".
+ *   Complex arrays are interleaved (re, im) float pairs.
+ * - Every call is asynchronous on the given HIP stream (NULL = the null
+ *   stream) and does not synchronise, except chrf_read_status.
+ * - Argument checks happen before anything is enqueued; a failing check
+ *   returns a negative status and enqueues nothing.  chrf_last_error() then
+ *   describes the failure.  No C++ exception crosses this interface.
+ * - A plan is not thread-safe; use one plan per stream.  Workspace contents
+ *   written by chrf_forward stay valid for chrf_backward until the next
+ *   chrf_forward on the same plan and workspace.
+ */
+#ifndef CHRF_H_
+#define CHRF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum chrf_status {
+  CHRF_OK = 0,
+  CHRF_EINVAL = -1,        /* bad argument (null pointer, size, option) */
+  CHRF_ENOMEM = -2,        /* host or device allocation failed */
+  CHRF_EHIP = -3,          /* a HIP runtime call failed */
+  CHRF_ECAPACITY = -4,     /* the tile-pair list overflowed its capacity */
+  CHRF_EUNSUPPORTED = -5   /* shape or option this build does not handle */
+} chrf_status;
+
+typedef struct chrf_ctx chrf_ctx;   /* one per device: twiddle tables */
+typedef struct chrf_plan chrf_plan; /* shapes, optics, options, workspace layout */
+
+/*
+ * Pinhole camera (Sec. 3: pose r and the hologram plane it carries; the
+ * Euler-angle pose is converted to R, t by the caller).  x_cam = R x + t with
+ * camera axes x right, y down, z forward; the projection of Eq. 8 is
+ * mu = (fx x_cam/z_cam + cx, fy y_cam/z_cam + cy) in pixels, the centre of
+ * pixel (row r, column c) being (c + 0.5, r + 0.5).  Gaussians with
+ * z_cam <= z_near are culled.  80 bytes; passed as a device array [n_views].
+ */
+typedef struct chrf_camera {
+  float R[9]; /* row-major */
+  float t[3];
+  float fx, fy, cx, cy;
+  float z_near;
+  float reserved[3];
+} chrf_camera;
+
+/*
+ * Complex Gaussians (Eq. 9 without the plane logits: this build renders one
+ * plane, rho = 1).  Device arrays:
+ *   means [n,3]; log_scales [n,3] (S = diag(exp(s))); quats [n,4] as
+ *   (w, x, y, z) of any nonzero norm (normalised inside); opacity [n] already
+ *   activated, in (0,1); amp [n, n_lambda] (c, the wave amplitude); phase
+ *   [n, n_lambda] in radians (phi).
+ */
+typedef struct chrf_gaussians {
+  int32_t n;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity;
+  const float* amp;
+  const float* phase;
+} chrf_gaussians;
+
+/* Gradients, same shapes as chrf_gaussians; every array is overwritten. */
+typedef struct chrf_grads {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity;
+  float* amp;
+  float* phase;
+} chrf_grads;
+
+/*
+ * Plan description (host struct).
+ *   height x width     field size (n_y x n_x of Sec. 3), both <= 4096
+ *   n_views            cameras rendered per call (batch)
+ *   n_lambda           wavelengths, 1..4
+ *   n_planes           propagation distances K, 1..64
+ *   max_gaussians      largest n accepted by this plan
+ *   max_pairs          capacity of the (tile, Gaussian) list over all views;
+ *                      0 selects 128 * n_views * max_gaussians, capped at 2^28
+ *   pad_factor         1 or 2: the propagation grid is pad_factor times the
+ *                      field in each dimension (zero padding, top-left)
+ *   band_limit         1: cut f^2 > 1/lambda^2 (Eq. 7); 2: also the sampling
+ *                      band limit |f_x| <= 1/(lambda sqrt((2 df_x z)^2 + 1)),
+ *                      likewise in y, with df = 1/(padded size * pitch)
+ *   pitch              pixel pitch in metres (Delta x of Sec. 3)
+ *   wavelengths        metres, n_lambda entries
+ *   distances          metres, signed, n_planes entries (Eqs. 14 and 16)
+ *   k_sigma            support half-width in standard deviations (3)
+ *   alpha_min, alpha_max, t_min   compositing thresholds (1/255, 0.99, 1e-4):
+ *                      a Gaussian contributes where a >= alpha_min; a is
+ *                      clamped at alpha_max; a pixel stops after T < t_min
+ *   tile_w, tile_h     raster tile, multiples of 8 with tile_w*tile_h <= 256
+ *                      (0, 0 selects 16 x 16, the tile of Sec. 4.2)
+ *   cols_per_block     columns per workgroup in the column FFT passes
+ *                      (0 = choose from the LDS size)
+ */
+typedef struct chrf_plan_desc {
+  int32_t height, width;
+  int32_t n_views, n_lambda, n_planes;
+  int32_t max_gaussians;
+  int64_t max_pairs;
+  int32_t pad_factor;
+  int32_t band_limit;
+  double pitch;
+  double wavelengths[4];
+  double distances[64];
+  float k_sigma, alpha_min, alpha_max, t_min;
+  int32_t tile_w, tile_h;
+  int32_t cols_per_block;
+  int32_t reserved[7];
+} chrf_plan_desc;
+
+/* Named regions of the workspace, for inspection by tests and tools. */
+typedef enum chrf_region {
+  CHRF_REGION_PAIR_KEYS = 0,   /* uint32 [max_pairs]: view * n_tiles + tile, sorted */
+  CHRF_REGION_PAIR_VALUES = 1, /* uint32 [max_pairs]: view * max_gaussians + gaussian */
+  CHRF_REGION_TILE_RANGES = 2, /* uint32 [n_views * n_tiles][2]: [start, end) */
+  CHRF_REGION_STATUS = 3,      /* uint64 [0] pairs needed, uint32 [2] overflow flag */
+  CHRF_REGION_T_FINAL = 4,     /* float [n_views][H][W] transmittance after compositing */
+  CHRF_REGION_LAST = 5,        /* uint32 [n_views][H][W] last included pair + 1 */
+  CHRF_REGION_FIELD = 6,       /* complex [n_views][n_lambda][H][W] rendered field */
+  CHRF_REGION_GRAD_FIELD = 7,  /* complex [n_views][n_lambda][H][W] dL/dU after backward */
+  CHRF_REGION_COUNT
+} chrf_region;
+
+/* Create a context on HIP device `device`; *out receives it.  Errors:
+ * CHRF_EINVAL (null out), CHRF_EHIP (device unusable), CHRF_ENOMEM. */
+chrf_status chrf_create(int device, chrf_ctx** out);
+/* Release a context and its device tables; plans made from it must be destroyed first. */
+void chrf_destroy(chrf_ctx* ctx);
+/* Text of the last failure on this thread (static storage; never NULL). */
+const char* chrf_last_error(void);
+/* Library version string. */
+const char* chrf_version(void);
+
+/* Validate desc and build a plan (host object + small device tables).
+ * Errors: CHRF_EINVAL, CHRF_EUNSUPPORTED (size/radix/LDS limits), CHRF_EHIP, CHRF_ENOMEM. */
+chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_plan** out);
+void chrf_plan_destroy(chrf_plan* plan);
+/* Bytes of device workspace the caller must allocate (256-byte aligned start). */
+size_t chrf_plan_workspace_bytes(const chrf_plan* plan);
+/* Offset and size in bytes of a region inside the workspace. */
+chrf_status chrf_plan_region(const chrf_plan* plan, int region, size_t* offset, size_t* bytes);
+
+/*
+ * Forward pass: project and cull (Eqs. 2-4, 8), bin into tiles and sort by
+ * depth (Algorithm 2), composite front to back (Eqs. 10, 13 with one plane),
+ * propagate every wavelength to every distance (Eqs. 7, 14, 16).
+ *   cams            device [n_views] chrf_camera
+ *   workspace       device, chrf_plan_workspace_bytes() bytes
+ *   field_out       complex [n_views][n_lambda][H][W] or NULL
+ *   prop_out        complex [n_views][n_lambda][n_planes][H][W] or NULL (u)
+ *   intensity_out   float   [n_views][n_lambda][n_planes][H][W] or NULL (|u|^2)
+ *   target          float   same shape as intensity, or NULL; when given,
+ *                   loss_out (device float scalar) receives the MSE over all
+ *                   elements (Eq. 17 with a mean) and the workspace is
+ *                   prepared for chrf_backward with dL_dI = NULL.
+ * A pair-list overflow is not reported here (no synchronisation); outputs are
+ * then incomplete but every access stays in bounds, and chrf_read_status
+ * reports CHRF_ECAPACITY.
+ */
+chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_camera* cams, void* workspace,
+                         float* field_out, float* prop_out, float* intensity_out, const float* target,
+                         float* loss_out, void* hip_stream);
+
+/*
+ * Backward pass (Supplementary D): gradients of the loss w.r.t. every
+ * Gaussian parameter, summed over views.
+ *   dL_dI      float [n_views][n_lambda][n_planes][H][W] or NULL.  NULL means:
+ *              use the MSE of the last chrf_forward that had a target.
+ *   prop       complex u saved from chrf_forward (prop_out); required when
+ *              dL_dI is given
+ *   dL_dprop   complex, same shape as prop, or NULL
+ *   dL_dfield  complex [n_views][n_lambda][H][W] or NULL
+ *   grad_scale device float scalar multiplying all of the above, or NULL (1)
+ *   out        gradients (overwritten)
+ */
+chrf_status chrf_backward(chrf_plan* plan, const chrf_gaussians* g, const chrf_camera* cams, void* workspace,
+                          const float* dL_dI, const float* prop, const float* dL_dprop, const float* dL_dfield,
+                          const float* grad_scale, const chrf_grads* out, void* hip_stream);
+
+/*
+ * Propagation only (Eqs. 14/16 on a given field): field [n_views][n_lambda][H][W]
+ * complex -> prop_out (complex, may be NULL) and intensity_out (may be NULL).
+ */
+chrf_status chrf_propagate(chrf_plan* plan, const float* field, void* workspace, float* prop_out,
+                           float* intensity_out, void* hip_stream);
+/*
+ * Adjoint of chrf_propagate's field -> prop map:
+ * grad_prop [n_views][n_lambda][n_planes][H][W] complex -> grad_field
+ * [n_views][n_lambda][H][W] complex (sum over planes of the conjugate-transfer
+ * propagation).
+ */
+chrf_status chrf_propagate_adjoint(chrf_plan* plan, const float* grad_prop, void* workspace, float* grad_field,
+                                   void* hip_stream);
+
+/* Synchronise the stream and report the last forward's pair-list status:
+ * CHRF_OK, or CHRF_ECAPACITY with *pairs_needed set. */
+chrf_status chrf_read_status(chrf_plan* plan, void* workspace, int64_t* pairs_needed, void* hip_stream);
+
+/*
+ * Per-kernel timing with HIP events recorded on the launch stream.  While
+ * enabled, every launch is bracketed by events; chrf_timing_report
+ * synchronises, writes "name count total_ms" lines into buf (NUL-terminated,
+ * truncated to size) and clears the records.
+ */
+chrf_status chrf_timing_enable(chrf_plan* plan, int enable);
+chrf_status chrf_timing_report(chrf_plan* plan, char* buf, size_t size);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHRF_H_ */

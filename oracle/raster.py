@@ -45,8 +45,13 @@ class RasterResult:
     n_contrib: np.ndarray  # [H,W] number of included Gaussians
 
 
-def _support(g, proj, opacity, rect, thr):
+def _support(g, proj, opacity, rect, thr, window=None):
     c0, c1, r0, r1 = (int(v) for v in rect[g])
+    if window is not None:   # restrict the pixel loop to rows [wr0, wr1) x columns [wc0, wc1)
+        wr0, wr1, wc0, wc1 = window
+        c0, c1, r0, r1 = max(c0, wc0), min(c1, wc1 - 1), max(r0, wr0), min(r1, wr1 - 1)
+        if c0 > c1 or r0 > r1:
+            return None
     px = np.arange(c0, c1 + 1, dtype=np.float64) + 0.5
     py = np.arange(r0, r1 + 1, dtype=np.float64) + 0.5
     dx = px[None, :] - proj.mu[g, 0]
@@ -67,7 +72,9 @@ def depth_order(footprint):
     return vis[np.lexsort((vis, keys))]
 
 
-def render_field(proj, opacity, footprint, width, height, thr) -> RasterResult:
+def render_field(proj, opacity, footprint, width, height, thr, window=None) -> RasterResult:
+    """Composite every pixel (or only those in ``window`` = (r0, r1, c0, c1),
+    half-open, the rest staying at U = 0, T = 1)."""
     L = proj.v.shape[1]
     U = np.zeros((L, height, width), np.complex128)
     T = np.ones((height, width))
@@ -77,7 +84,10 @@ def render_field(proj, opacity, footprint, width, height, thr) -> RasterResult:
     order = depth_order(footprint)
     rect = footprint["rect"]
     for pos, g in enumerate(order):
-        sl, _, _, _, _, a, _, sup = _support(g, proj, opacity, rect, thr)
+        sp = _support(g, proj, opacity, rect, thr, window)
+        if sp is None:
+            continue
+        sl, _, _, _, _, a, _, sup = sp
         inc = sup & active[sl]
         if not inc.any():
             continue
@@ -92,8 +102,8 @@ def render_field(proj, opacity, footprint, width, height, thr) -> RasterResult:
     return RasterResult(U, T, last, order, ncon)
 
 
-def render_field_backward(proj, opacity, footprint, res: RasterResult, G_U, thr):
-    """Per-Gaussian 2D gradients for one view.
+def render_field_backward(proj, opacity, footprint, res: RasterResult, G_U, thr, window=None):
+    """Per-Gaussian 2D gradients for one view (over ``window`` only, if given).
 
     G_U: [L,H,W] complex gradient of the loss w.r.t. the rendered field.
     Returns d_mu [N,2], d_conic [N,3], d_opacity [N], d_v [N,L] complex.
@@ -108,7 +118,10 @@ def render_field_backward(proj, opacity, footprint, res: RasterResult, G_U, thr)
     rect = footprint["rect"]
     for pos in range(len(res.order) - 1, -1, -1):
         g = res.order[pos]
-        sl, dx, dy, power, G, a, clamped, sup = _support(g, proj, opacity, rect, thr)
+        sp = _support(g, proj, opacity, rect, thr, window)
+        if sp is None:
+            continue
+        sl, dx, dy, power, G, a, clamped, sup = sp
         inc = sup & (pos <= res.last[sl])
         if not inc.any():
             continue

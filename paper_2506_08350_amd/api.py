@@ -1,0 +1,219 @@
+"""PyTorch-facing wrapper of the C ABI: device memory, streams and autograd.
+
+Every step of the hot path runs in the HIP library; this module only
+allocates tensors, passes their pointers and the current HIP stream, and
+wires chrf_backward into torch.autograd.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import check
+
+PARAM_NAMES = ("means", "log_scales", "quats", "opacity", "amp", "phase")
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def pack_cameras(cameras, device="cuda") -> torch.Tensor:
+    """Device tensor [n_views, 20] of chrf_camera records from objects with
+    attributes R (3x3), t (3), fx, fy, cx, cy and optionally z_near."""
+    rows = []
+    for c in cameras:
+        r = torch.zeros(20, dtype=torch.float32)
+        r[0:9] = torch.as_tensor(c.R, dtype=torch.float32).reshape(9)
+        r[9:12] = torch.as_tensor(c.t, dtype=torch.float32).reshape(3)
+        r[12:17] = torch.tensor([c.fx, c.fy, c.cx, c.cy, getattr(c, "z_near", 0.01)], dtype=torch.float32)
+        rows.append(r)
+    return torch.stack(rows).to(device)
+
+
+@dataclass
+class Optics:
+    wavelengths: tuple
+    distances: tuple
+    pitch: float
+    pad: int = 2
+    band_limit: int = 2
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.lib = _lib.load()
+        h = C.c_void_p()
+        check(self.lib.chrf_create(device, C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.chrf_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+
+_default_ctx = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+class Renderer:
+    """One plan (shapes, optics, thresholds) plus its device workspace."""
+
+    def __init__(self, height, width, optics: Optics, n_views=1, max_gaussians=1, n_lambda=None,
+                 max_pairs=0, k_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
+                 tile=(16, 16), cols_per_block=0, device=0):
+        self.ctx = context(device)
+        self.lib = self.ctx.lib
+        d = _lib.PlanDesc()
+        d.height, d.width = int(height), int(width)
+        d.n_views = int(n_views)
+        d.n_lambda = int(n_lambda if n_lambda is not None else len(optics.wavelengths))
+        d.n_planes = len(optics.distances)
+        d.max_gaussians = int(max_gaussians)
+        d.max_pairs = int(max_pairs)
+        d.pad_factor = int(optics.pad)
+        d.band_limit = int(optics.band_limit)
+        d.pitch = float(optics.pitch)
+        for i, lam in enumerate(optics.wavelengths):
+            d.wavelengths[i] = float(lam)
+        for i, z in enumerate(optics.distances):
+            d.distances[i] = float(z)
+        d.k_sigma, d.alpha_min, d.alpha_max, d.t_min = k_sigma, alpha_min, alpha_max, t_min
+        d.tile_w, d.tile_h = int(tile[0]), int(tile[1])
+        d.cols_per_block = int(cols_per_block)
+        self.desc = d
+        h = C.c_void_p()
+        check(self.lib.chrf_plan_create(self.ctx.handle, C.byref(d), C.byref(h)))
+        self.plan = h
+        self.optics = optics
+        self.H, self.W, self.B = d.height, d.width, d.n_views
+        self.L, self.K = d.n_lambda, d.n_planes
+        self.max_gaussians = d.max_gaussians
+        nbytes = int(self.lib.chrf_plan_workspace_bytes(self.plan))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{device}")
+        self.device = torch.device(f"cuda:{device}")
+
+    def __del__(self):
+        if getattr(self, "plan", None) is not None and self.plan.value:
+            self.lib.chrf_plan_destroy(self.plan)
+            self.plan = C.c_void_p()
+
+    # ---- inspection ----
+    def region(self, region: int, dtype=torch.uint8):
+        off, nb = C.c_size_t(), C.c_size_t()
+        check(self.lib.chrf_plan_region(self.plan, region, C.byref(off), C.byref(nb)))
+        raw = self.workspace[off.value: off.value + nb.value]
+        return raw.view(dtype)
+
+    def read_status(self):
+        need = C.c_int64()
+        st = self.lib.chrf_read_status(self.plan, _ptr(self.workspace), C.byref(need), _stream())
+        return st, need.value
+
+    def timing(self, enable: bool):
+        check(self.lib.chrf_timing_enable(self.plan, 1 if enable else 0))
+
+    def timing_report(self) -> dict:
+        buf = C.create_string_buffer(1 << 16)
+        check(self.lib.chrf_timing_report(self.plan, buf, len(buf)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, count, ms = line.split()
+            out[name] = (int(count), float(ms))
+        return out
+
+    # ---- calls ----
+    def _gauss(self, p):
+        g = _lib.Gaussians()
+        g.n = int(p["means"].shape[0])
+        for k in PARAM_NAMES:
+            t = p[k]
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous(), k
+            setattr(g, k, t.data_ptr())
+        return g
+
+    def forward(self, params: dict, cams: torch.Tensor, want_field=True, want_prop=False, want_intensity=True,
+                target=None):
+        B, L, K, H, W = self.B, self.L, self.K, self.H, self.W
+        dev = self.device
+        field = torch.empty((B, L, H, W, 2), dtype=torch.float32, device=dev) if want_field else None
+        prop = torch.empty((B, L, K, H, W, 2), dtype=torch.float32, device=dev) if want_prop else None
+        inten = torch.empty((B, L, K, H, W), dtype=torch.float32, device=dev) if want_intensity else None
+        loss = torch.empty((), dtype=torch.float32, device=dev) if target is not None else None
+        if target is not None:
+            assert target.shape == (B, L, K, H, W) and target.is_contiguous()
+        g = self._gauss(params)
+        check(self.lib.chrf_forward(self.plan, C.byref(g), _ptr(cams), _ptr(self.workspace), _ptr(field),
+                                    _ptr(prop), _ptr(inten), _ptr(target), _ptr(loss), _stream()))
+        return {"field": field, "prop": prop, "intensity": inten, "loss": loss}
+
+    def backward(self, params: dict, cams: torch.Tensor, dL_dI=None, prop=None, dL_dprop=None, dL_dfield=None,
+                 grad_scale=None):
+        grads = {k: torch.empty_like(params[k]) for k in PARAM_NAMES}
+        gr = _lib.Grads(*[grads[k].data_ptr() for k in PARAM_NAMES])
+        g = self._gauss(params)
+        check(self.lib.chrf_backward(self.plan, C.byref(g), _ptr(cams), _ptr(self.workspace), _ptr(dL_dI),
+                                     _ptr(prop), _ptr(dL_dprop), _ptr(dL_dfield), _ptr(grad_scale),
+                                     C.byref(gr), _stream()))
+        return grads
+
+    def train_step(self, params: dict, cams: torch.Tensor, target: torch.Tensor, want_intensity=False):
+        """Forward with the fused MSE loss, then the backward: (loss, grads)."""
+        out = self.forward(params, cams, want_field=False, want_prop=False, want_intensity=want_intensity,
+                           target=target)
+        grads = self.backward(params, cams)
+        return out["loss"], grads, out
+
+    def propagate(self, field: torch.Tensor, want_prop=True, want_intensity=True):
+        B, L, K, H, W = self.B, self.L, self.K, self.H, self.W
+        prop = torch.empty((B, L, K, H, W, 2), dtype=torch.float32, device=self.device) if want_prop else None
+        inten = torch.empty((B, L, K, H, W), dtype=torch.float32, device=self.device) if want_intensity else None
+        check(self.lib.chrf_propagate(self.plan, _ptr(field), _ptr(self.workspace), _ptr(prop), _ptr(inten),
+                                      _stream()))
+        return prop, inten
+
+    def propagate_adjoint(self, grad_prop: torch.Tensor):
+        out = torch.empty((self.B, self.L, self.H, self.W, 2), dtype=torch.float32, device=self.device)
+        check(self.lib.chrf_propagate_adjoint(self.plan, _ptr(grad_prop), _ptr(self.workspace), _ptr(out),
+                                              _stream()))
+        return out
+
+
+class HologramFunction(torch.autograd.Function):
+    """Intensities [B, L, K, H, W] of the propagated complex field, differentiable
+    w.r.t. all six Gaussian parameter tensors through the library's backward."""
+
+    @staticmethod
+    def forward(ctx, renderer: Renderer, cams, means, log_scales, quats, opacity, amp, phase):
+        params = dict(zip(PARAM_NAMES, (means, log_scales, quats, opacity, amp, phase)))
+        params = {k: v.detach().contiguous() for k, v in params.items()}
+        out = renderer.forward(params, cams, want_field=False, want_prop=True, want_intensity=True)
+        ctx.renderer = renderer
+        ctx.cams = cams
+        ctx.params = params
+        ctx.save_for_backward(out["prop"])
+        return out["intensity"]
+
+    @staticmethod
+    def backward(ctx, dI):
+        (prop,) = ctx.saved_tensors
+        grads = ctx.renderer.backward(ctx.params, ctx.cams, dL_dI=dI.contiguous(), prop=prop)
+        return (None, None) + tuple(grads[k] for k in PARAM_NAMES)
+
+
+def render_intensity(renderer: Renderer, cams, means, log_scales, quats, opacity, amp, phase):
+    return HologramFunction.apply(renderer, cams, means, log_scales, quats, opacity, amp, phase)

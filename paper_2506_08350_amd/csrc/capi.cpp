@@ -1,0 +1,645 @@
+// C-ABI layer: contexts, plans, workspace layout and the launch sequences of
+// the forward and backward passes.  All GPU work is enqueued on the caller's
+// stream; nothing here synchronises except chrf_read_status / timing reports.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/chrf.h"
+#include "internal.h"
+
+using namespace chrf;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+chrf_status fail(chrf_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                              \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) return fail(CHRF_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+enum Reg {
+  R_V, R_G0, R_G1, R_RECT, R_GKEY, R_GKEY_ALT, R_GVAL, R_GVAL_ALT, R_GCOUNT, R_CNT_SORTED, R_OFFSETS, R_SCAN_TMP,
+  R_HIST, R_PKEY, R_PKEY_ALT, R_PVAL, R_PVAL_ALT, R_RANGES, R_STATUS, R_TFINAL, R_LAST, R_FIELD, R_X1, R_Y,
+  R_GRAD_FIELD, R_GRAD2D, R_LOSS_PARTIAL, R_NUM
+};
+
+struct TimingRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct chrf_ctx {
+  int device = 0;
+  int lds_per_block = 65536;
+  std::map<int, cpx*> twiddles;
+  std::mutex mu;
+};
+
+struct chrf_plan {
+  chrf_ctx* ctx = nullptr;
+  chrf_plan_desc d{};
+  int B = 0, H = 0, W = 0, L = 0, K = 0, N = 0;
+  int pH = 0, pW = 0;
+  int tiles_x = 0, tiles_y = 0, n_tiles = 0;
+  int64_t cap = 0;
+  int cols_per_block = 0;
+  int g2 = 0;
+  int gsort_bits = 0, psort_bits = 0;
+  bool gsort_alt = false, psort_alt = false;
+  FftDesc frow{}, fcol{};
+  HParam* hp_dev = nullptr;
+  size_t off[R_NUM] = {}, bytes[R_NUM] = {};
+  size_t ws_bytes = 0;
+  bool fused_ready = false;
+  bool timing = false;
+  std::vector<TimingRec> trec;
+  std::vector<hipEvent_t> ev_pool;
+};
+
+namespace {
+
+template <typename T>
+T* at(const chrf_plan* p, void* ws, int r) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + p->off[r]);
+}
+
+hipEvent_t take_event(chrf_plan* p) {
+  if (!p->ev_pool.empty()) {
+    hipEvent_t e = p->ev_pool.back();
+    p->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Runs `launch` and, when timing is on, brackets it with events on stream s.
+template <typename F>
+chrf_status timed(chrf_plan* p, const char* name, hipStream_t s, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (p->timing) {
+    a = take_event(p);
+    b = take_event(p);
+    if (a && b) hipEventRecord(a, s);
+  }
+  hipError_t e = launch();
+  if (e != hipSuccess) return fail(CHRF_EHIP, std::string(name) + ": " + hipGetErrorString(e));
+  if (p->timing && a && b) {
+    hipEventRecord(b, s);
+    p->trec.push_back({name, a, b});
+  }
+  return CHRF_OK;
+}
+
+#define RUN(name, expr)                                                     \
+  do {                                                                      \
+    chrf_status st_ = timed(plan, name, s, [&]() -> hipError_t { return (expr); }); \
+    if (st_ != CHRF_OK) return st_;                                         \
+  } while (0)
+
+int bits_for(int64_t max_key) {
+  int b = 0;
+  while (b < 63 && ((int64_t)1 << b) <= max_key) ++b;
+  return b;
+}
+
+chrf_status get_twiddles(chrf_ctx* ctx, int n, const cpx** out) {
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  auto it = ctx->twiddles.find(n);
+  if (it != ctx->twiddles.end()) {
+    *out = it->second;
+    return CHRF_OK;
+  }
+  std::vector<cpx> h(n);
+  for (int m = 0; m < n; ++m) {
+    const double a = -2.0 * M_PI * (double)m / (double)n;
+    h[m] = cpx{(float)std::cos(a), (float)std::sin(a)};
+  }
+  cpx* d = nullptr;
+  HIP_TRY(hipMalloc(&d, sizeof(cpx) * n));
+  HIP_TRY(hipMemcpy(d, h.data(), sizeof(cpx) * n, hipMemcpyHostToDevice));
+  ctx->twiddles[n] = d;
+  *out = d;
+  return CHRF_OK;
+}
+
+chrf_status make_fft(chrf_ctx* ctx, int n, FftDesc* fd) {
+  fd->n = n;
+  fd->nstages = fft_plan_radices(n, fd->radix);
+  if (fd->nstages == 0 && n != 1) return fail(CHRF_EUNSUPPORTED, "FFT length " + std::to_string(n) + " is not 2^a 3^b 5^c");
+  return get_twiddles(ctx, n, &fd->tw);
+}
+
+AsmGeom geom(const chrf_plan* p) {
+  AsmGeom g{};
+  g.H = p->H;
+  g.W = p->W;
+  g.pH = p->pH;
+  g.pW = p->pW;
+  g.n_bl = p->B * p->L;
+  g.n_lambda = p->L;
+  g.K = p->K;
+  g.band_mode = p->d.band_limit;
+  g.ax = (float)(1.0 / (p->pW * p->d.pitch));
+  g.ay = (float)(1.0 / (p->pH * p->d.pitch));
+  g.norm = (float)(1.0 / ((double)p->pH * (double)p->pW));
+  g.hp = p->hp_dev;
+  return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* chrf_last_error(void) { return g_err.c_str(); }
+const char* chrf_version(void) { return "chrf 0.1 gfx950"; }
+
+chrf_status chrf_create(int device, chrf_ctx** out) {
+  if (!out) return fail(CHRF_EINVAL, "chrf_create: out is NULL");
+  *out = nullptr;
+  int count = 0;
+  HIP_TRY(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(CHRF_EINVAL, "chrf_create: no such device");
+  HIP_TRY(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  chrf_ctx* c = new (std::nothrow) chrf_ctx();
+  if (!c) return fail(CHRF_ENOMEM, "chrf_create: out of host memory");
+  c->device = device;
+  c->lds_per_block = (int)prop.sharedMemPerBlock;
+  if (c->lds_per_block > 65536) {
+    // Opt in to the full LDS for the FFT passes; if the runtime refuses,
+    // clear its sticky error and stay within 64 KiB.
+    if (asm_allow_lds(c->lds_per_block) != hipSuccess) {
+      (void)hipGetLastError();
+      c->lds_per_block = 65536;
+    }
+  }
+  *out = c;
+  return CHRF_OK;
+}
+
+void chrf_destroy(chrf_ctx* ctx) {
+  if (!ctx) return;
+  for (auto& kv : ctx->twiddles) hipFree(kv.second);
+  delete ctx;
+}
+
+chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_plan** out) {
+  if (!ctx || !desc || !out) return fail(CHRF_EINVAL, "chrf_plan_create: NULL argument");
+  *out = nullptr;
+  const chrf_plan_desc& d = *desc;
+  if (d.height <= 0 || d.width <= 0 || d.height > 4096 || d.width > 4096)
+    return fail(CHRF_EINVAL, "plan: height and width must be in 1..4096");
+  if (d.n_views <= 0 || d.n_views > 256) return fail(CHRF_EINVAL, "plan: n_views must be in 1..256");
+  if (d.n_lambda < 1 || d.n_lambda > kMaxLambda) return fail(CHRF_EINVAL, "plan: n_lambda must be in 1..4");
+  if (d.n_planes < 1 || d.n_planes > kMaxPlanes) return fail(CHRF_EINVAL, "plan: n_planes must be in 1..64");
+  if (d.max_gaussians < 0 || (int64_t)d.max_gaussians * d.n_views >= ((int64_t)1 << 31))
+    return fail(CHRF_EINVAL, "plan: n_views * max_gaussians must be below 2^31");
+  if (d.pad_factor != 1 && d.pad_factor != 2) return fail(CHRF_EINVAL, "plan: pad_factor must be 1 or 2");
+  if (d.band_limit != 1 && d.band_limit != 2) return fail(CHRF_EINVAL, "plan: band_limit must be 1 or 2");
+  if (!(d.pitch > 0)) return fail(CHRF_EINVAL, "plan: pitch must be positive");
+  for (int l = 0; l < d.n_lambda; ++l)
+    if (!(d.wavelengths[l] > 0)) return fail(CHRF_EINVAL, "plan: wavelengths must be positive");
+  for (int k = 0; k < d.n_planes; ++k)
+    if (!std::isfinite(d.distances[k])) return fail(CHRF_EINVAL, "plan: distances must be finite");
+  if (!(d.k_sigma > 0) || !(d.alpha_max > 0 && d.alpha_max <= 1) || !(d.alpha_min >= 0) || !(d.t_min >= 0))
+    return fail(CHRF_EINVAL, "plan: thresholds out of range");
+  int tw = d.tile_w, th = d.tile_h;
+  if (tw == 0 && th == 0) tw = th = 16;
+  if (tw <= 0 || th <= 0 || tw % 8 || th % 8 || tw * th > kRasterThreads)
+    return fail(CHRF_EINVAL, "plan: tile_w, tile_h must be multiples of 8 with tile_w * tile_h <= 256");
+
+  chrf_plan* p = new (std::nothrow) chrf_plan();
+  if (!p) return fail(CHRF_ENOMEM, "plan: out of host memory");
+  p->ctx = ctx;
+  p->d = d;
+  p->d.tile_w = tw;
+  p->d.tile_h = th;
+  p->B = d.n_views;
+  p->H = d.height;
+  p->W = d.width;
+  p->L = d.n_lambda;
+  p->K = d.n_planes;
+  p->N = d.max_gaussians;
+  p->pH = d.pad_factor * d.height;
+  p->pW = d.pad_factor * d.width;
+  p->tiles_x = (d.width + tw - 1) / tw;
+  p->tiles_y = (d.height + th - 1) / th;
+  p->n_tiles = p->tiles_x * p->tiles_y;
+  p->g2 = 6 + 2 * p->L;
+  int64_t cap = d.max_pairs;
+  if (cap <= 0) {
+    cap = (int64_t)128 * p->B * (int64_t)(p->N > 0 ? p->N : 1);
+    if (cap > ((int64_t)1 << 28)) cap = (int64_t)1 << 28;
+  }
+  if (cap >= ((int64_t)1 << 32) - 1) {
+    delete p;
+    return fail(CHRF_EINVAL, "plan: max_pairs must be below 2^32");
+  }
+  p->cap = cap;
+  auto bad = [&](chrf_status st) {
+    delete p;
+    return st;
+  };
+  if (p->pW > 8192 || p->pH > 8192) return bad(fail(CHRF_EUNSUPPORTED, "plan: padded size above 8192"));
+  chrf_status st = make_fft(ctx, p->pW, &p->frow);
+  if (st != CHRF_OK) return bad(st);
+  st = make_fft(ctx, p->pH, &p->fcol);
+  if (st != CHRF_OK) return bad(st);
+  // columns per workgroup in the column passes (two LDS buffers of pH * C)
+  if ((int64_t)2 * 8 * p->pW > ctx->lds_per_block)
+    return bad(fail(CHRF_EUNSUPPORTED, "plan: a padded row does not fit the LDS"));
+  int C = d.cols_per_block;
+  if (C == 0) {
+    const int lds_cap = ctx->lds_per_block < 81920 ? ctx->lds_per_block : 81920;
+    C = 16;
+    while (C > 1 && ((int64_t)col_lds_bytes(p->pH, C) > lds_cap || p->pH * C > fft_max_elems() || p->pW % C)) C >>= 1;
+  }
+  if (C < 1 || (C & (C - 1)) || p->pW % C || (int64_t)col_lds_bytes(p->pH, C) > ctx->lds_per_block ||
+      p->pH * C > fft_max_elems())
+    return bad(fail(CHRF_EUNSUPPORTED, "plan: cols_per_block does not fit the LDS or the padded width"));
+  p->cols_per_block = C;
+  // transfer-function parameters
+  std::vector<HParam> hp(p->L * p->K);
+  const double dfx = 1.0 / (p->pW * d.pitch), dfy = 1.0 / (p->pH * d.pitch);
+  for (int l = 0; l < p->L; ++l)
+    for (int k = 0; k < p->K; ++k) {
+      const double lam = d.wavelengths[l], z = d.distances[k];
+      HParam& h = hp[l * p->K + k];
+      const double zl = z / lam;
+      h.frac_rev = (float)(zl - std::floor(zl));
+      h.z = (float)z;
+      h.inv_lam = (float)(1.0 / lam);
+      h.inv_lam2 = (float)(1.0 / (lam * lam));
+      if (d.band_limit >= 2) {
+        const double fxl = 1.0 / (lam * std::sqrt((2.0 * dfx * z) * (2.0 * dfx * z) + 1.0));
+        const double fyl = 1.0 / (lam * std::sqrt((2.0 * dfy * z) * (2.0 * dfy * z) + 1.0));
+        h.kx_max = (int)std::min(std::floor(fxl / dfx), 1e9);
+        h.ky_max = (int)std::min(std::floor(fyl / dfy), 1e9);
+      } else {
+        h.kx_max = h.ky_max = 1 << 30;
+      }
+      const double e = (double)p->pW * p->pH * d.pitch / lam;
+      const double bound = std::floor(e * e);
+      h.evan_bound = bound > 9e18 ? (long long)9e18 : (long long)bound;
+    }
+  {
+    hipError_t e = hipMalloc(&p->hp_dev, sizeof(HParam) * hp.size());
+    if (e == hipSuccess) e = hipMemcpy(p->hp_dev, hp.data(), sizeof(HParam) * hp.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bad(fail(CHRF_EHIP, std::string("plan: ") + hipGetErrorString(e)));
+  }
+  // sort geometry
+  p->gsort_bits = 32 + bits_for(p->B - 1);
+  p->psort_bits = bits_for((int64_t)p->B * p->n_tiles - 1);
+  p->gsort_alt = ((p->gsort_bits + 7) / 8) % 2 == 1;
+  p->psort_alt = ((p->psort_bits + 7) / 8) % 2 == 1;
+  // workspace layout
+  const int64_t BN = (int64_t)p->B * (p->N > 0 ? p->N : 1);
+  const int64_t hist = radix_hist_elems(std::max<int64_t>(cap, BN));
+  const int64_t scan_tmp = scan_tmp_elems(std::max<int64_t>(hist, BN)) + 16;
+  const int64_t pix = (int64_t)p->B * p->H * p->W;
+  size_t sz[R_NUM];
+  sz[R_V] = sizeof(float2) * (size_t)std::max(p->N, 1) * p->L;
+  sz[R_G0] = sizeof(float4) * BN;
+  sz[R_G1] = sizeof(float4) * BN;
+  sz[R_RECT] = sizeof(int4) * BN;
+  sz[R_GKEY] = sz[R_GKEY_ALT] = sizeof(uint64_t) * BN;
+  sz[R_GVAL] = sz[R_GVAL_ALT] = sizeof(uint32_t) * BN;
+  sz[R_GCOUNT] = sz[R_CNT_SORTED] = sizeof(uint32_t) * BN;
+  sz[R_OFFSETS] = sizeof(uint64_t) * BN;
+  sz[R_SCAN_TMP] = sizeof(uint64_t) * scan_tmp;
+  sz[R_HIST] = sizeof(uint32_t) * hist;
+  sz[R_PKEY] = sz[R_PKEY_ALT] = sz[R_PVAL] = sz[R_PVAL_ALT] = sizeof(uint32_t) * cap;
+  sz[R_RANGES] = sizeof(uint2) * (size_t)p->B * p->n_tiles;
+  sz[R_STATUS] = 256;
+  sz[R_TFINAL] = sizeof(float) * pix;
+  sz[R_LAST] = sizeof(uint32_t) * pix;
+  sz[R_FIELD] = sizeof(float2) * pix * p->L;
+  sz[R_X1] = sizeof(float2) * (size_t)p->B * p->L * p->H * p->pW;
+  sz[R_Y] = sizeof(float2) * (size_t)p->B * p->L * p->K * p->H * p->pW;
+  sz[R_GRAD_FIELD] = sizeof(float2) * pix * p->L;
+  sz[R_GRAD2D] = sizeof(float) * BN * p->g2;
+  sz[R_LOSS_PARTIAL] = sizeof(float) * (size_t)p->B * p->L * p->K * p->H;
+  size_t o = 0;
+  for (int r = 0; r < R_NUM; ++r) {
+    p->off[r] = o;
+    p->bytes[r] = sz[r];
+    o += align256(sz[r]);
+  }
+  p->ws_bytes = o;
+  *out = p;
+  return CHRF_OK;
+}
+
+void chrf_plan_destroy(chrf_plan* p) {
+  if (!p) return;
+  if (p->hp_dev) hipFree(p->hp_dev);
+  for (auto& r : p->trec) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  for (auto e : p->ev_pool) hipEventDestroy(e);
+  delete p;
+}
+
+size_t chrf_plan_workspace_bytes(const chrf_plan* p) { return p ? p->ws_bytes : 0; }
+
+chrf_status chrf_plan_region(const chrf_plan* p, int region, size_t* offset, size_t* bytes) {
+  if (!p || !offset || !bytes) return fail(CHRF_EINVAL, "chrf_plan_region: NULL argument");
+  int r;
+  switch (region) {
+    case CHRF_REGION_PAIR_KEYS: r = p->psort_alt ? R_PKEY_ALT : R_PKEY; break;
+    case CHRF_REGION_PAIR_VALUES: r = p->psort_alt ? R_PVAL_ALT : R_PVAL; break;
+    case CHRF_REGION_TILE_RANGES: r = R_RANGES; break;
+    case CHRF_REGION_STATUS: r = R_STATUS; break;
+    case CHRF_REGION_T_FINAL: r = R_TFINAL; break;
+    case CHRF_REGION_LAST: r = R_LAST; break;
+    case CHRF_REGION_FIELD: r = R_FIELD; break;
+    case CHRF_REGION_GRAD_FIELD: r = R_GRAD_FIELD; break;
+    default: return fail(CHRF_EINVAL, "chrf_plan_region: unknown region");
+  }
+  *offset = p->off[r];
+  *bytes = p->bytes[r];
+  return CHRF_OK;
+}
+
+static chrf_status check_gaussians(const chrf_plan* p, const chrf_gaussians* g) {
+  if (!g) return fail(CHRF_EINVAL, "gaussians is NULL");
+  if (g->n < 0 || g->n > p->N) return fail(CHRF_EINVAL, "gaussians: n exceeds the plan's max_gaussians");
+  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity || !g->amp || !g->phase))
+    return fail(CHRF_EINVAL, "gaussians: NULL array");
+  return CHRF_OK;
+}
+
+static chrf_status asm_forward(chrf_plan* plan, const float2* field, void* ws, float* prop_out, float* intensity_out,
+                               const float* target, hipStream_t s) {
+  const AsmGeom g = geom(plan);
+  float2* x1 = at<float2>(plan, ws, R_X1);
+  float2* y = at<float2>(plan, ws, R_Y);
+  RUN("rows_forward", launch_rows_forward(field, x1, g, plan->frow, s));
+  RUN("cols_forward", launch_cols_forward(x1, y, g, plan->fcol, plan->cols_per_block, s));
+  const double numel = (double)plan->B * plan->L * plan->K * plan->H * plan->W;
+  RUN("rows_inverse", launch_rows_inverse(y, g, plan->frow, reinterpret_cast<float2*>(prop_out), intensity_out,
+                                          target, at<float>(plan, ws, R_LOSS_PARTIAL), (float)(2.0 / numel),
+                                          target != nullptr, s));
+  return CHRF_OK;
+}
+
+chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_camera* cams, void* ws,
+                         float* field_out, float* prop_out, float* intensity_out, const float* target,
+                         float* loss_out, void* hip_stream) {
+  if (!plan || !cams || !ws) return fail(CHRF_EINVAL, "chrf_forward: NULL plan, cameras or workspace");
+  chrf_status st = check_gaussians(plan, g);
+  if (st != CHRF_OK) return st;
+  if (target && !loss_out) return fail(CHRF_EINVAL, "chrf_forward: target needs loss_out");
+  hipStream_t s = (hipStream_t)hip_stream;
+  plan->fused_ready = false;
+  const int Nst = std::max(plan->N, 1);
+  const int64_t BN = (int64_t)plan->B * Nst;
+  float2* field = field_out ? reinterpret_cast<float2*>(field_out) : at<float2>(plan, ws, R_FIELD);
+  uint32_t* status = at<uint32_t>(plan, ws, R_STATUS);
+  uint64_t* total = reinterpret_cast<uint64_t*>(status);
+
+  RUN("status_clear", launch_fill_u32(status, 0u, 8, s));
+  RUN("precompute_v", launch_precompute_v(g->amp, g->phase, g->n, plan->L, at<float2>(plan, ws, R_V), s));
+  ProjArgs pa{};
+  pa.means = g->means;
+  pa.log_scales = g->log_scales;
+  pa.quats = g->quats;
+  pa.opacity = g->opacity;
+  pa.cams = reinterpret_cast<const Cam*>(cams);
+  pa.n = g->n;
+  pa.n_stride = Nst;
+  pa.n_views = plan->B;
+  pa.width = plan->W;
+  pa.height = plan->H;
+  pa.tile_w = plan->d.tile_w;
+  pa.tile_h = plan->d.tile_h;
+  pa.tiles_x = plan->tiles_x;
+  pa.tiles_y = plan->tiles_y;
+  pa.k_sigma = plan->d.k_sigma;
+  pa.rec_g0 = at<float4>(plan, ws, R_G0);
+  pa.rec_g1 = at<float4>(plan, ws, R_G1);
+  pa.rec_rect = at<int4>(plan, ws, R_RECT);
+  pa.sort_key = at<uint64_t>(plan, ws, R_GKEY);
+  pa.sort_val = at<uint32_t>(plan, ws, R_GVAL);
+  pa.count = at<uint32_t>(plan, ws, R_GCOUNT);
+  pa.grad2d = nullptr;
+  RUN("project", launch_project(pa, s));
+
+  bool galt = false;
+  RUN("sort_gaussians", radix_sort_u64(at<uint64_t>(plan, ws, R_GKEY), at<uint64_t>(plan, ws, R_GKEY_ALT),
+                                       at<uint32_t>(plan, ws, R_GVAL), at<uint32_t>(plan, ws, R_GVAL_ALT), BN,
+                                       nullptr, 0, plan->gsort_bits, at<uint32_t>(plan, ws, R_HIST),
+                                       at<uint32_t>(plan, ws, R_SCAN_TMP), &galt, s));
+  const uint32_t* gval = at<uint32_t>(plan, ws, galt ? R_GVAL_ALT : R_GVAL);
+  RUN("gather_counts", launch_gather_counts(gval, at<uint32_t>(plan, ws, R_GCOUNT), at<uint32_t>(plan, ws, R_CNT_SORTED), BN, s));
+  RUN("scan_counts", launch_scan_u64_from_u32(at<uint32_t>(plan, ws, R_CNT_SORTED), at<uint64_t>(plan, ws, R_OFFSETS),
+                                              BN, at<uint64_t>(plan, ws, R_SCAN_TMP), total, s));
+  uint2* ranges = at<uint2>(plan, ws, R_RANGES);
+  RUN("ranges_clear", launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (int64_t)2 * plan->B * plan->n_tiles, s));
+  RUN("emit_pairs", launch_emit_pairs(gval, at<uint64_t>(plan, ws, R_OFFSETS), at<uint32_t>(plan, ws, R_GCOUNT),
+                                      at<int4>(plan, ws, R_RECT), BN, Nst, plan->d.tile_w, plan->d.tile_h,
+                                      plan->tiles_x, plan->n_tiles, at<uint32_t>(plan, ws, R_PKEY),
+                                      at<uint32_t>(plan, ws, R_PVAL), plan->cap, total, status + 2, s));
+  bool palt = false;
+  RUN("sort_pairs", radix_sort_u32(at<uint32_t>(plan, ws, R_PKEY), at<uint32_t>(plan, ws, R_PKEY_ALT),
+                                   at<uint32_t>(plan, ws, R_PVAL), at<uint32_t>(plan, ws, R_PVAL_ALT), plan->cap,
+                                   total, 0, plan->psort_bits, at<uint32_t>(plan, ws, R_HIST),
+                                   at<uint32_t>(plan, ws, R_SCAN_TMP), &palt, s));
+  const uint32_t* pkey = at<uint32_t>(plan, ws, palt ? R_PKEY_ALT : R_PKEY);
+  const uint32_t* pval = at<uint32_t>(plan, ws, palt ? R_PVAL_ALT : R_PVAL);
+  RUN("tile_ranges", launch_tile_ranges(pkey, total, plan->cap, ranges, s));
+
+  RasterArgs ra{};
+  ra.rec_g0 = at<float4>(plan, ws, R_G0);
+  ra.rec_g1 = at<float4>(plan, ws, R_G1);
+  ra.rec_rect = at<int4>(plan, ws, R_RECT);
+  ra.v = at<float2>(plan, ws, R_V);
+  ra.pair_val = pval;
+  ra.ranges = ranges;
+  ra.n_stride = Nst;
+  ra.n_lambda = plan->L;
+  ra.width = plan->W;
+  ra.height = plan->H;
+  ra.tile_w = plan->d.tile_w;
+  ra.tile_h = plan->d.tile_h;
+  ra.tiles_x = plan->tiles_x;
+  ra.tiles_y = plan->tiles_y;
+  ra.n_views = plan->B;
+  ra.k_sigma = plan->d.k_sigma;
+  ra.alpha_min = plan->d.alpha_min;
+  ra.alpha_max = plan->d.alpha_max;
+  ra.t_min = plan->d.t_min;
+  ra.field = field;
+  ra.t_final = at<float>(plan, ws, R_TFINAL);
+  ra.last = at<uint32_t>(plan, ws, R_LAST);
+  RUN("raster_forward", launch_raster_forward(ra, s));
+
+  st = asm_forward(plan, field, ws, prop_out, intensity_out, target, s);
+  if (st != CHRF_OK) return st;
+  if (target) {
+    const double numel = (double)plan->B * plan->L * plan->K * plan->H * plan->W;
+    RUN("reduce_loss", launch_reduce_loss(at<float>(plan, ws, R_LOSS_PARTIAL), (int64_t)plan->B * plan->L * plan->K * plan->H,
+                                          (float)(1.0 / numel), loss_out, s));
+    plan->fused_ready = true;
+  }
+  return CHRF_OK;
+}
+
+chrf_status chrf_backward(chrf_plan* plan, const chrf_gaussians* g, const chrf_camera* cams, void* ws,
+                          const float* dL_dI, const float* prop, const float* dL_dprop, const float* dL_dfield,
+                          const float* grad_scale, const chrf_grads* out, void* hip_stream) {
+  if (!plan || !cams || !ws || !out) return fail(CHRF_EINVAL, "chrf_backward: NULL plan, cameras, workspace or grads");
+  chrf_status st = check_gaussians(plan, g);
+  if (st != CHRF_OK) return st;
+  if (g->n > 0 && (!out->means || !out->log_scales || !out->quats || !out->opacity || !out->amp || !out->phase))
+    return fail(CHRF_EINVAL, "chrf_backward: NULL gradient array");
+  if (dL_dI && !prop) return fail(CHRF_EINVAL, "chrf_backward: dL_dI needs the saved prop");
+  const bool have_prop_grad = dL_dI || dL_dprop;
+  if (!have_prop_grad && !plan->fused_ready && !dL_dfield)
+    return fail(CHRF_EINVAL, "chrf_backward: no incoming gradient (no dL_dI/dL_dprop/dL_dfield and no fused loss)");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int Nst = std::max(plan->N, 1);
+  const AsmGeom geo = geom(plan);
+  float2* y = at<float2>(plan, ws, R_Y);
+  float2* x1 = at<float2>(plan, ws, R_X1);
+  const float2* grad_field = reinterpret_cast<const float2*>(dL_dfield);
+  if (have_prop_grad || plan->fused_ready) {
+    if (have_prop_grad)
+      RUN("rows_adjoint_in", launch_rows_adjoint_in(reinterpret_cast<const float2*>(prop), dL_dI,
+                                                    reinterpret_cast<const float2*>(dL_dprop), y, geo, plan->frow, s));
+    RUN("cols_adjoint", launch_cols_adjoint(y, x1, geo, plan->fcol, plan->cols_per_block, s));
+    float2* gf = at<float2>(plan, ws, R_GRAD_FIELD);
+    RUN("rows_adjoint_out", launch_rows_adjoint_out(x1, reinterpret_cast<const float2*>(dL_dfield), gf, geo,
+                                                    plan->frow, s));
+    grad_field = gf;
+  }
+  float* grad2d = at<float>(plan, ws, R_GRAD2D);
+  RUN("grad2d_clear", launch_fill_f32(grad2d, 0.f, (int64_t)plan->B * Nst * plan->g2, s));
+  size_t o, b;
+  chrf_plan_region(plan, CHRF_REGION_PAIR_VALUES, &o, &b);
+  RasterArgs ra{};
+  ra.rec_g0 = at<float4>(plan, ws, R_G0);
+  ra.rec_g1 = at<float4>(plan, ws, R_G1);
+  ra.rec_rect = at<int4>(plan, ws, R_RECT);
+  ra.v = at<float2>(plan, ws, R_V);
+  ra.pair_val = reinterpret_cast<const uint32_t*>(static_cast<char*>(ws) + o);
+  ra.ranges = at<uint2>(plan, ws, R_RANGES);
+  ra.n_stride = Nst;
+  ra.n_lambda = plan->L;
+  ra.width = plan->W;
+  ra.height = plan->H;
+  ra.tile_w = plan->d.tile_w;
+  ra.tile_h = plan->d.tile_h;
+  ra.tiles_x = plan->tiles_x;
+  ra.tiles_y = plan->tiles_y;
+  ra.n_views = plan->B;
+  ra.k_sigma = plan->d.k_sigma;
+  ra.alpha_min = plan->d.alpha_min;
+  ra.alpha_max = plan->d.alpha_max;
+  ra.t_min = plan->d.t_min;
+  ra.t_final = at<float>(plan, ws, R_TFINAL);
+  ra.last = at<uint32_t>(plan, ws, R_LAST);
+  ra.grad_field = grad_field;
+  ra.grad_scale = grad_scale;
+  ra.grad2d = grad2d;
+  ra.g2stride = plan->g2;
+  RUN("raster_backward", launch_raster_backward(ra, s));
+  RUN("project_backward",
+      launch_project_backward(g->means, g->log_scales, g->quats, g->amp, g->phase, reinterpret_cast<const Cam*>(cams),
+                              g->n, Nst, plan->B, plan->L, at<uint32_t>(plan, ws, R_GCOUNT), grad2d, plan->g2,
+                              out->means, out->log_scales, out->quats, out->opacity, out->amp, out->phase, s));
+  return CHRF_OK;
+}
+
+chrf_status chrf_propagate(chrf_plan* plan, const float* field, void* ws, float* prop_out, float* intensity_out,
+                           void* hip_stream) {
+  if (!plan || !field || !ws) return fail(CHRF_EINVAL, "chrf_propagate: NULL argument");
+  plan->fused_ready = false;
+  return asm_forward(plan, reinterpret_cast<const float2*>(field), ws, prop_out, intensity_out, nullptr,
+                     (hipStream_t)hip_stream);
+}
+
+chrf_status chrf_propagate_adjoint(chrf_plan* plan, const float* grad_prop, void* ws, float* grad_field,
+                                   void* hip_stream) {
+  if (!plan || !grad_prop || !ws || !grad_field) return fail(CHRF_EINVAL, "chrf_propagate_adjoint: NULL argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const AsmGeom geo = geom(plan);
+  float2* y = at<float2>(plan, ws, R_Y);
+  float2* x1 = at<float2>(plan, ws, R_X1);
+  RUN("rows_adjoint_in", launch_rows_adjoint_in(nullptr, nullptr, reinterpret_cast<const float2*>(grad_prop), y, geo,
+                                                plan->frow, s));
+  RUN("cols_adjoint", launch_cols_adjoint(y, x1, geo, plan->fcol, plan->cols_per_block, s));
+  RUN("rows_adjoint_out", launch_rows_adjoint_out(x1, nullptr, reinterpret_cast<float2*>(grad_field), geo,
+                                                  plan->frow, s));
+  return CHRF_OK;
+}
+
+chrf_status chrf_read_status(chrf_plan* plan, void* ws, int64_t* pairs_needed, void* hip_stream) {
+  if (!plan || !ws) return fail(CHRF_EINVAL, "chrf_read_status: NULL argument");
+  uint32_t h[4] = {0, 0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(h, at<uint32_t>(plan, ws, R_STATUS), sizeof(h), hipMemcpyDeviceToHost,
+                         (hipStream_t)hip_stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
+  const uint64_t total = (uint64_t)h[0] | ((uint64_t)h[1] << 32);
+  if (pairs_needed) *pairs_needed = (int64_t)total;
+  if (h[2] != 0 || total > (uint64_t)plan->cap)
+    return fail(CHRF_ECAPACITY, "pair list needs " + std::to_string(total) + " entries, capacity " +
+                                    std::to_string(plan->cap));
+  return CHRF_OK;
+}
+
+chrf_status chrf_timing_enable(chrf_plan* plan, int enable) {
+  if (!plan) return fail(CHRF_EINVAL, "chrf_timing_enable: NULL plan");
+  plan->timing = enable != 0;
+  return CHRF_OK;
+}
+
+chrf_status chrf_timing_report(chrf_plan* plan, char* buf, size_t size) {
+  if (!plan || !buf || size == 0) return fail(CHRF_EINVAL, "chrf_timing_report: bad argument");
+  std::map<std::string, std::pair<int, double>> acc;
+  std::vector<std::string> order;
+  for (auto& r : plan->trec) {
+    HIP_TRY(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    if (!acc.count(r.name)) order.push_back(r.name);
+    acc[r.name].first += 1;
+    acc[r.name].second += ms;
+    plan->ev_pool.push_back(r.a);
+    plan->ev_pool.push_back(r.b);
+  }
+  plan->trec.clear();
+  std::string outs;
+  for (auto& n : order) {
+    char line[256];
+    snprintf(line, sizeof(line), "%s %d %.6f\n", n.c_str(), acc[n].first, acc[n].second);
+    outs += line;
+  }
+  strncpy(buf, outs.c_str(), size - 1);
+  buf[size - 1] = 0;
+  return CHRF_OK;
+}
+
+}  // extern "C"

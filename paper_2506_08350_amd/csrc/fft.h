@@ -1,0 +1,264 @@
+// Mixed-radix Stockham FFT building blocks for LDS-resident sequences.
+//
+// The propagation of Eqs. 14 and 16 is two passes of 1-D transforms over a
+// zero-padded grid.  Each pass keeps one or a few sequences of length N in
+// LDS and runs log_R(N) Stockham stages on them; every stage reads R elements
+// per butterfly into registers, applies the inter-stage twiddles and a small
+// radix-R DFT, and writes the outputs back in autosorted order, so that the
+// result is in natural order with no bit-reversal pass.
+//
+// Small DFTs are written out for radix 2, 3, 4, 5, 8; radices 6, 9, 10, 12,
+// 15, 16 are composed from them with compile-time twiddles.  Forward
+// transforms use exp(-2 pi i k n / N), inverse ones exp(+2 pi i k n / N);
+// neither is normalised here.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace chrf {
+
+struct cpx {
+  float x, y;
+};
+
+__host__ __device__ inline cpx mk(float x, float y) { return cpx{x, y}; }
+__host__ __device__ inline cpx operator+(cpx a, cpx b) { return cpx{a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline cpx operator-(cpx a, cpx b) { return cpx{a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline cpx operator*(cpx a, float s) { return cpx{a.x * s, a.y * s}; }
+__host__ __device__ inline cpx cmul(cpx a, cpx b) { return cpx{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__host__ __device__ inline cpx cmulc(cpx a, cpx b) { return cpx{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }  // a * conj(b)
+__host__ __device__ inline cpx cconj(cpx a) { return cpx{a.x, -a.y}; }
+// multiply by -i for the forward sign, +i for the inverse sign
+template <bool INV> __host__ __device__ inline cpx rot(cpx a) {
+  return INV ? cpx{-a.y, a.x} : cpx{a.y, -a.x};
+}
+
+// ---- compile-time twiddles: exp(-2 pi i m / R) as double, folded to float ----
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double ct_sin(double x) {   // |x| <= pi after reduction
+  double term = x, sum = x;
+  for (int n = 1; n < 30; ++n) {
+    term *= -x * x / double((2 * n) * (2 * n + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double ct_reduce(double x) {
+  while (x > kPi) x -= 2 * kPi;
+  while (x < -kPi) x += 2 * kPi;
+  return x;
+}
+constexpr double ct_sin_r(double x) { return ct_sin(ct_reduce(x)); }
+constexpr double ct_cos_r(double x) { return ct_sin(ct_reduce(x + kPi / 2)); }
+
+template <int N>
+struct TwidN {   // exp(-2 pi i m / N), m < N
+  float c[N], s[N];
+  constexpr TwidN() : c(), s() {
+    for (int m = 0; m < N; ++m) {
+      c[m] = float(ct_cos_r(2.0 * kPi * double(m) / double(N)));
+      s[m] = float(ct_sin_r(2.0 * kPi * double(m) / double(N)));
+    }
+  }
+};
+
+template <int N, bool INV>
+__host__ __device__ inline cpx ct_tw(int m) {   // m is a compile-time constant after unrolling
+  constexpr TwidN<N> t{};
+  return INV ? cpx{t.c[m % N], t.s[m % N]} : cpx{t.c[m % N], -t.s[m % N]};
+}
+
+// ---- small DFTs in registers ----
+template <int R, bool INV> struct Dft;
+
+template <bool INV> struct Dft<2, INV> {
+  __host__ __device__ static inline void run(cpx* x) {
+    cpx a = x[0], b = x[1];
+    x[0] = a + b;
+    x[1] = a - b;
+  }
+};
+
+template <bool INV> struct Dft<3, INV> {
+  __host__ __device__ static inline void run(cpx* x) {
+    const float s3 = 0.86602540378443864676f;
+    cpx t = x[1] + x[2];
+    cpx m = x[0] - t * 0.5f;
+    cpx d = rot<INV>(x[1] - x[2]) * s3;
+    x[0] = x[0] + t;
+    x[1] = m + d;
+    x[2] = m - d;
+  }
+};
+
+template <bool INV> struct Dft<4, INV> {
+  __host__ __device__ static inline void run(cpx* x) {
+    cpx a = x[0] + x[2], b = x[0] - x[2];
+    cpx c = x[1] + x[3], d = rot<INV>(x[1] - x[3]);
+    x[0] = a + c;
+    x[2] = a - c;
+    x[1] = b + d;
+    x[3] = b - d;
+  }
+};
+
+template <bool INV> struct Dft<5, INV> {
+  __host__ __device__ static inline void run(cpx* x) {
+    const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
+    const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
+    cpx t1 = x[1] + x[4], t2 = x[2] + x[3];
+    cpx d1 = x[1] - x[4], d2 = x[2] - x[3];
+    cpx a1 = x[0] + t1 * c1 + t2 * c2;
+    cpx a2 = x[0] + t1 * c2 + t2 * c1;
+    cpx b1 = rot<INV>(d1 * s1 + d2 * s2);
+    cpx b2 = rot<INV>(d1 * s2 - d2 * s1);
+    x[0] = x[0] + t1 + t2;
+    x[1] = a1 + b1;
+    x[4] = a1 - b1;
+    x[2] = a2 + b2;
+    x[3] = a2 - b2;
+  }
+};
+
+template <bool INV> struct Dft<8, INV> {
+  __host__ __device__ static inline void run(cpx* x) {
+    const float h = 0.70710678118654752440f;
+    cpx e[4] = {x[0], x[2], x[4], x[6]};
+    cpx o[4] = {x[1], x[3], x[5], x[7]};
+    Dft<4, INV>::run(e);
+    Dft<4, INV>::run(o);
+    // o[q] *= W8^q (forward W8 = (1 - i)/sqrt2)
+    cpx o1 = (rot<INV>(o[1]) + o[1]) * h;          // (1 -+ i)/sqrt2 * o1
+    cpx o2 = rot<INV>(o[2]);
+    cpx o3 = (rot<INV>(o[3]) - o[3]) * h;          // (-1 -+ i)/sqrt2 * o3
+    x[0] = e[0] + o[0];
+    x[4] = e[0] - o[0];
+    x[1] = e[1] + o1;
+    x[5] = e[1] - o1;
+    x[2] = e[2] + o2;
+    x[6] = e[2] - o2;
+    x[3] = e[3] + o3;
+    x[7] = e[3] - o3;
+  }
+};
+
+// R = R1 * R2:  n = n1 + R1 n2,  k = k2 + R2 k1
+template <int R1, int R2, bool INV>
+struct DftComp {
+  __host__ __device__ static inline void run(cpx* x) {
+    constexpr int R = R1 * R2;
+    cpx y[R1][R2];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) {
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) y[n1][n2] = x[n1 + R1 * n2];
+      Dft<R2, INV>::run(y[n1]);
+#pragma unroll
+      for (int k2 = 1; k2 < R2; ++k2)
+        if (n1 > 0) y[n1][k2] = cmul(y[n1][k2], ct_tw<R, INV>(n1 * k2));
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+      cpx z[R1];
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) z[n1] = y[n1][k2];
+      Dft<R1, INV>::run(z);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) x[k2 + R2 * k1] = z[k1];
+    }
+  }
+};
+
+template <bool INV> struct Dft<6, INV> : DftComp<2, 3, INV> {};
+template <bool INV> struct Dft<9, INV> : DftComp<3, 3, INV> {};
+template <bool INV> struct Dft<10, INV> : DftComp<2, 5, INV> {};
+template <bool INV> struct Dft<12, INV> : DftComp<4, 3, INV> {};
+template <bool INV> struct Dft<15, INV> : DftComp<3, 5, INV> {};
+template <bool INV> struct Dft<16, INV> : DftComp<4, 4, INV> {};
+
+// Radices the planner may use, largest first.
+constexpr int kRadices[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
+constexpr int kMaxStages = 12;
+
+// Factor n into supported radices (largest first).  Returns the stage count,
+// or 0 if n has a prime factor other than 2, 3, 5.
+__host__ inline int fft_plan_radices(int n, int* radices) {
+  int count = 0;
+  while (n > 1) {
+    bool found = false;
+    for (int r : kRadices) {
+      if (n % r == 0) {
+        if (count >= kMaxStages) return 0;
+        radices[count++] = r;
+        n /= r;
+        found = true;
+        break;
+      }
+    }
+    if (!found) return 0;
+  }
+  return count;
+}
+
+// One Stockham stage on C interleaved sequences of length N, element (s, n)
+// at src[n * C + s].  Butterfly b covers sequence s = b % C and index
+// j = b / C; it reads src[(j + r N/R) C + s], r < R, applies w^{r k},
+// k = j mod Ns, with w = exp(-+2 pi i / (Ns R)), and writes output q to
+// dst[((j / Ns) Ns R + k + q Ns) C + s].  Ns is the product of the radices of
+// the earlier stages; tw[m] = exp(-2 pi i m / N) for m < N.  Stages are out of
+// place (src and dst alternate), so a thread only holds one butterfly.
+template <int R, int NT, bool INV>
+__device__ inline void stockham_stage(const cpx* __restrict__ src, cpx* __restrict__ dst, int N, int C, int logC,
+                                      int Ns, const cpx* __restrict__ tw) {
+  const int nb = N / R;
+  const int total = nb * C;
+  const int twstep = N / (Ns * R);
+  for (int b = threadIdx.x; b < total; b += NT) {
+    const int s = b & (C - 1);
+    const int j = b >> logC;
+    const int k = j % Ns;
+    cpx v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[(j + r * nb) * C + s];
+    if (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const cpx w = tw[r * k * twstep];
+        v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
+      }
+    }
+    Dft<R, INV>::run(v);
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int q = 0; q < R; ++q) dst[(base + q * Ns) * C + s] = v[q];
+  }
+  __syncthreads();
+}
+
+// All stages of one transform on data in buf0; returns the buffer (buf0 or
+// buf1) that holds the result.  radices/nstages come from fft_plan_radices.
+// The caller must have synchronised after writing buf0.
+template <int NT, bool INV>
+__device__ inline cpx* fft_lds(cpx* buf0, cpx* buf1, int N, int C, int logC, const int* radices, int nstages,
+                               const cpx* __restrict__ tw) {
+  int Ns = 1;
+  cpx* src = buf0;
+  cpx* dst = buf1;
+  for (int st = 0; st < nstages; ++st) {
+    const int R = radices[st];
+    switch (R) {
+#define CHRF_STAGE(RR) \
+  case RR: stockham_stage<RR, NT, INV>(src, dst, N, C, logC, Ns, tw); break;
+      CHRF_STAGE(16) CHRF_STAGE(15) CHRF_STAGE(12) CHRF_STAGE(10) CHRF_STAGE(9) CHRF_STAGE(8)
+      CHRF_STAGE(6) CHRF_STAGE(5) CHRF_STAGE(4) CHRF_STAGE(3) CHRF_STAGE(2)
+#undef CHRF_STAGE
+      default: break;
+    }
+    Ns *= R;
+    cpx* t = src;
+    src = dst;
+    dst = t;
+  }
+  return src;
+}
+
+}  // namespace chrf

@@ -1,0 +1,156 @@
+// Internal declarations shared by the kernel translation units and the C-ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft.h"
+
+namespace chrf {
+
+constexpr int kMaxLambda = 4;     // wavelengths handled by the raster kernels
+constexpr int kMaxPlanes = 64;
+constexpr int kRasterThreads = 256;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;   // keys per sort block
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Device copy of a camera: x_cam = R x + t; fx, fy, cx, cy in pixels.
+struct Cam {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy, z_near;
+  float pad_[3];
+};
+
+// Per-(view, Gaussian) raster record.
+//   g0 = (mu_x, mu_y, A, B), g1 = (C, opacity, -, -) with conic [[A, B], [B, C]]
+//   rect = (c0, c1 - c0, r0, r1 - r0): inclusive pixel rectangle of the support
+struct ProjArgs {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity;
+  const Cam* cams;
+  int n;          // Gaussians in this call
+  int n_stride;   // record stride per view (plan's maximum)
+  int n_views;
+  int width, height;
+  int tile_w, tile_h, tiles_x, tiles_y;
+  float k_sigma;
+  float4* rec_g0;
+  float4* rec_g1;
+  int4* rec_rect;
+  uint64_t* sort_key;   // (view << 32) | depth bits; invisible -> depth bits 0xffffffff
+  uint32_t* sort_val;   // view * n_stride + g
+  uint32_t* count;      // tiles covered (0 if culled)
+  float* grad2d;        // zeroed when not null
+  int grad2d_stride;
+};
+
+struct FftDesc {
+  int n;
+  int nstages;
+  int radix[kMaxStages];
+  const cpx* tw;  // exp(-2 pi i m / n), m < n
+};
+
+// Transfer-function parameters of one (wavelength, distance) pair.
+struct HParam {
+  float frac_rev;    // fractional part of z / lambda (carrier phase in revolutions)
+  float z;           // metres
+  float inv_lam;     // 1 / lambda
+  float inv_lam2;    // 1 / lambda^2
+  int kx_max, ky_max;          // sampling band limit in bins (mode 2), else large
+  long long evan_bound;        // kx^2 pH^2 + ky^2 pW^2 <= bound  <=> f^2 <= 1/lambda^2
+};
+
+struct AsmGeom {
+  int H, W, pH, pW;
+  int n_bl;         // views * wavelengths
+  int n_lambda, K;
+  int band_mode;
+  float ax, ay;     // 1 / (pW pitch), 1 / (pH pitch)
+  float norm;       // 1 / (pH pW)
+  const HParam* hp; // [n_lambda][K]
+};
+
+// ---- launchers (each returns hipGetLastError after the launch) ----
+hipError_t launch_precompute_v(const float* amp, const float* phase, int n, int n_lambda, float2* v, hipStream_t s);
+hipError_t launch_project(const ProjArgs& a, hipStream_t s);
+hipError_t launch_project_backward(const float* means, const float* log_scales, const float* quats,
+                                   const float* amp, const float* phase, const Cam* cams, int n, int n_stride,
+                                   int n_views, int n_lambda, const uint32_t* count, const float* grad2d,
+                                   int g2stride, float* d_means, float* d_log_scales, float* d_quats,
+                                   float* d_opacity, float* d_amp, float* d_phase, hipStream_t s);
+
+// exclusive scans; total (if not null) receives the sum
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* block_tmp, hipStream_t s);
+hipError_t launch_scan_u64_from_u32(const uint32_t* in, uint64_t* out, int64_t n, uint64_t* block_tmp,
+                                    uint64_t* total, hipStream_t s);
+int64_t scan_tmp_elems(int64_t n);
+
+// Stable LSD radix sort.  n_dev (device, may be null) caps the count at run time.
+hipError_t radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t n_max,
+                          const uint64_t* n_dev, int begin_bit, int end_bit, uint32_t* hist, uint32_t* scan_tmp,
+                          bool* result_in_alt, hipStream_t s);
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t n_max,
+                          const uint64_t* n_dev, int begin_bit, int end_bit, uint32_t* hist, uint32_t* scan_tmp,
+                          bool* result_in_alt, hipStream_t s);
+int64_t radix_hist_elems(int64_t n_max);
+
+hipError_t launch_gather_counts(const uint32_t* sorted_val, const uint32_t* count, uint32_t* out, int64_t n,
+                                hipStream_t s);
+hipError_t launch_emit_pairs(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* count,
+                             const int4* rect, int64_t n, int n_stride, int tile_w, int tile_h, int tiles_x,
+                             int n_tiles, uint32_t* pair_key, uint32_t* pair_val, int64_t capacity,
+                             const uint64_t* total, uint32_t* status, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
+hipError_t launch_tile_ranges(const uint32_t* pair_key, const uint64_t* total, int64_t capacity, uint2* ranges,
+                              hipStream_t s);
+
+struct RasterArgs {
+  const float4* rec_g0;
+  const float4* rec_g1;
+  const int4* rec_rect;
+  const float2* v;          // [N][n_lambda]
+  const uint32_t* pair_val;
+  const uint2* ranges;
+  int n_stride, n_lambda;
+  int width, height, tile_w, tile_h, tiles_x, tiles_y, n_views;
+  float k_sigma, alpha_min, alpha_max, t_min;
+  float2* field;            // [B][L][H][W]
+  float* t_final;           // [B][H][W]
+  uint32_t* last;           // [B][H][W]: index of the last included pair + 1 (0 = none)
+  // backward only
+  const float2* grad_field; // [B][L][H][W]
+  const float* grad_scale;  // device scalar or null
+  float* grad2d;            // [B * n_stride][g2stride]
+  int g2stride;
+};
+hipError_t launch_raster_forward(const RasterArgs& a, hipStream_t s);
+hipError_t launch_raster_backward(const RasterArgs& a, hipStream_t s);
+
+// Angular-spectrum passes (layout: rows of [bl][r] are contiguous complex64)
+hipError_t launch_rows_forward(const float2* in, float2* out, const AsmGeom& g, const FftDesc& fr, hipStream_t s);
+hipError_t launch_cols_forward(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, int cols_per_block,
+                               hipStream_t s);
+// inverse row pass with epilogue: u (optional), I, loss partials and the fused adjoint row FFT (when target != null)
+hipError_t launch_rows_inverse(float2* y, const AsmGeom& g, const FftDesc& fr, float2* prop_out, float* intensity,
+                               const float* target, float* loss_partial, float grad_coef, bool fuse_adjoint,
+                               hipStream_t s);
+hipError_t launch_rows_adjoint_in(const float2* prop, const float* dL_dI, const float2* dL_dprop, float2* z,
+                                  const AsmGeom& g, const FftDesc& fr, hipStream_t s);
+hipError_t launch_cols_adjoint(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, int cols_per_block,
+                               hipStream_t s);
+hipError_t launch_rows_adjoint_out(const float2* w1, const float2* dL_dfield, float2* grad_field, const AsmGeom& g,
+                                   const FftDesc& fr, hipStream_t s);
+hipError_t launch_reduce_loss(const float* partial, int64_t n, float scale, float* out, hipStream_t s);
+hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s);
+hipError_t asm_allow_lds(int bytes);
+size_t col_lds_bytes(int pH, int C);
+int fft_max_elems();
+
+}  // namespace chrf

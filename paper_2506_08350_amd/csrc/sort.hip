@@ -1,0 +1,343 @@
+// Tile binning: device-wide scans, a stable LSD radix sort, pair emission and
+// tile ranges (Algorithm 2: DuplicateWithDepthKeys, SortByKeys,
+// IdentifyTileRanges).
+//
+// Ordering.  Visible Gaussians of every view are first sorted by the key
+// (view, depth bits); the pairs (view * tiles + tile, Gaussian) are then
+// emitted in that order and stably sorted by their 32-bit tile key.  The
+// result equals a sort by (view, tile, depth, Gaussian index): the index
+// tie-break comes from the stability of both sorts, since the first sort
+// starts from index order.  Depths are positive floats, whose bit patterns
+// order like their values.
+//
+// The radix sort is the classic three-kernel LSD pass (digit histogram per
+// block, exclusive scan over (digit, block), stable scatter).  Ranks inside a
+// block come from wave ballots: a lane's rank among equal digits is the
+// popcount of the lower lanes whose 8 digit bits all match, plus the counts of
+// earlier waves and earlier rounds held in LDS.  Counts that are only known on
+// the device (the number of pairs) are read by every block, so the launch
+// grid can be sized by capacity and the sequence needs no host round trip.
+#include "internal.h"
+
+namespace chrf {
+
+// ----------------------------------------------------------------- scans ---
+template <typename T>
+__device__ inline T block_exclusive_scan(T v, T* lds_warp, T* total) {
+  // lds_warp holds kScanThreads / 64 entries
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    T y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) lds_warp[wave] = x;
+  __syncthreads();
+  T wbase = 0, tot = 0;
+  const int nw = blockDim.x >> 6;
+  for (int w = 0; w < nw; ++w) {
+    T c = lds_warp[w];
+    if (w < wave) wbase += c;
+    tot += c;
+  }
+  __syncthreads();
+  *total = tot;
+  return wbase + x - v;
+}
+
+template <typename TIn, typename TOut>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const TIn* __restrict__ in, int64_t n,
+                                                              TOut* __restrict__ block_sums) {
+  __shared__ TOut lw[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  TOut s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) s += (TOut)in[base + i];
+  TOut tot;
+  block_exclusive_scan<TOut>(s, lw, &tot);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of the block sums in place; sums[nb] = total
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scan_top(T* sums, int64_t nb, T* total) {
+  __shared__ T lw[1024 / 64];
+  T carry = 0;
+  for (int64_t base = 0; base < nb; base += blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    T v = i < nb ? sums[i] : 0;
+    T tot;
+    T ex = block_exclusive_scan<T>(v, lw, &tot);
+    if (i < nb) sums[i] = carry + ex;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <typename TIn, typename TOut>
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const TIn* __restrict__ in, TOut* __restrict__ out,
+                                                            int64_t n, const TOut* __restrict__ block_off) {
+  __shared__ TOut lw[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  TIn v[kScanItems];
+  TOut s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = base + i < n ? in[base + i] : 0;
+    s += (TOut)v[i];
+  }
+  TOut tot;
+  TOut run = block_exclusive_scan<TOut>(s, lw, &tot) + block_off[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += (TOut)v[i];
+  }
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+template <typename TIn, typename TOut>
+static hipError_t scan_impl(const TIn* in, TOut* out, int64_t n, TOut* tmp, TOut* total, hipStream_t s) {
+  if (n <= 0) {
+    if (total) return hipMemsetAsync(total, 0, sizeof(TOut), s);
+    return hipSuccess;
+  }
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  k_scan_reduce<TIn, TOut><<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, tmp);
+  k_scan_top<TOut><<<1, 1024, 0, s>>>(tmp, nb, total);
+  k_scan_down<TIn, TOut><<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t s) {
+  return scan_impl<uint32_t, uint32_t>(in, out, n, tmp, (uint32_t*)nullptr, s);
+}
+hipError_t launch_scan_u64_from_u32(const uint32_t* in, uint64_t* out, int64_t n, uint64_t* tmp, uint64_t* total,
+                                    hipStream_t s) {
+  return scan_impl<uint32_t, uint64_t>(in, out, n, tmp, total, s);
+}
+
+// ----------------------------------------------------------- radix sort ---
+__device__ inline int64_t live_count(int64_t n_max, const uint64_t* n_dev) {
+  if (!n_dev) return n_max;
+  const uint64_t v = *n_dev;
+  return v < (uint64_t)n_max ? (int64_t)v : n_max;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* __restrict__ keys, int64_t n_max,
+                                                             const uint64_t* n_dev, int shift,
+                                                             uint32_t* __restrict__ hist, int nblocks) {
+  __shared__ uint32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t n = live_count(n_max, n_dev);
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  if (base < n) {
+#pragma unroll 4
+    for (int i = 0; i < kSortItems; ++i) {
+      const int64_t idx = base + i * kSortThreads + threadIdx.x;
+      if (idx < n) atomicAdd(&cnt[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+    }
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restrict__ keys_in,
+                                                                const uint32_t* __restrict__ vals_in,
+                                                                K* __restrict__ keys_out,
+                                                                uint32_t* __restrict__ vals_out, int64_t n_max,
+                                                                const uint64_t* n_dev, int shift,
+                                                                const uint32_t* __restrict__ offsets, int nblocks) {
+  constexpr int NW = kSortThreads / 64;
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[NW][256];
+  __shared__ uint32_t goff[256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t n = live_count(n_max, n_dev);
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  if (base >= n) return;   // uniform per block
+  run[tid] = 0;
+  for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
+  goff[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+  __syncthreads();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t idx = base + (int64_t)r * kSortThreads + tid;
+    const bool valid = idx < n;
+    K key = 0;
+    uint32_t val = 0;
+    uint32_t d = 0;
+    if (valid) {
+      key = keys_in[idx];
+      val = vals_in[idx];
+      d = (uint32_t)(key >> shift) & 255u;
+    }
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const uint64_t m = __ballot(on);
+      peers &= on ? m : ~m;
+    }
+    const uint32_t lower = __popcll(peers & lt_mask);
+    if (valid && lower == 0) wcnt[wave][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t before = 0;
+      for (int w = 0; w < wave; ++w) before += wcnt[w][d];
+      const uint32_t pos = goff[d] + run[d] + before + lower;
+      keys_out[pos] = key;
+      vals_out[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < NW; ++w) {
+      add += wcnt[w][tid];
+      wcnt[w][tid] = 0;
+    }
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
+int64_t radix_hist_elems(int64_t n_max) {
+  const int64_t nb = (n_max + kSortTile - 1) / kSortTile;
+  return 256 * (nb > 0 ? nb : 1);
+}
+
+template <typename K>
+static hipError_t radix_sort_impl(K* keys, K* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t n_max,
+                                  const uint64_t* n_dev, int begin_bit, int end_bit, uint32_t* hist,
+                                  uint32_t* scan_tmp, bool* result_in_alt, hipStream_t s) {
+  *result_in_alt = false;
+  if (n_max <= 0) return hipSuccess;
+  const int nblocks = (int)((n_max + kSortTile - 1) / kSortTile);
+  K* kin = keys;
+  K* kout = keys_alt;
+  uint32_t* vin = vals;
+  uint32_t* vout = vals_alt;
+  bool alt = false;
+  for (int shift = begin_bit; shift < end_bit; shift += 8) {
+    k_radix_hist<K><<<nblocks, kSortThreads, 0, s>>>(kin, n_max, n_dev, shift, hist, nblocks);
+    hipError_t e = launch_scan_u32(hist, hist, (int64_t)256 * nblocks, scan_tmp, s);
+    if (e != hipSuccess) return e;
+    k_radix_scatter<K><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n_max, n_dev, shift, hist, nblocks);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    K* tk = kin; kin = kout; kout = tk;
+    uint32_t* tv = vin; vin = vout; vout = tv;
+    alt = !alt;
+  }
+  *result_in_alt = alt;
+  return hipGetLastError();
+}
+
+hipError_t radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t n_max,
+                          const uint64_t* n_dev, int begin_bit, int end_bit, uint32_t* hist, uint32_t* scan_tmp,
+                          bool* result_in_alt, hipStream_t s) {
+  return radix_sort_impl<uint64_t>(keys, keys_alt, vals, vals_alt, n_max, n_dev, begin_bit, end_bit, hist,
+                                   scan_tmp, result_in_alt, s);
+}
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t n_max,
+                          const uint64_t* n_dev, int begin_bit, int end_bit, uint32_t* hist, uint32_t* scan_tmp,
+                          bool* result_in_alt, hipStream_t s) {
+  return radix_sort_impl<uint32_t>(keys, keys_alt, vals, vals_alt, n_max, n_dev, begin_bit, end_bit, hist,
+                                   scan_tmp, result_in_alt, s);
+}
+
+// -------------------------------------------------------- pair emission ---
+__global__ void k_gather_counts(const uint32_t* __restrict__ sorted_val, const uint32_t* __restrict__ count,
+                                uint32_t* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = count[sorted_val[i]];
+}
+
+hipError_t launch_gather_counts(const uint32_t* sorted_val, const uint32_t* count, uint32_t* out, int64_t n,
+                                hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_gather_counts<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(sorted_val, count, out, n);
+  return hipGetLastError();
+}
+
+// One thread per sorted (view, Gaussian); pairs of one Gaussian are emitted in
+// row-major tile order.  Pairs past the capacity are dropped and flagged.
+__global__ void k_emit_pairs(const uint32_t* __restrict__ sorted_val, const uint64_t* __restrict__ offsets,
+                             const uint32_t* __restrict__ count, const int4* __restrict__ rect, int64_t n,
+                             int n_stride, int tile_w, int tile_h, int tiles_x, int n_tiles,
+                             uint32_t* __restrict__ pair_key, uint32_t* __restrict__ pair_val, int64_t capacity,
+                             const uint64_t* total, uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && *total > (uint64_t)capacity) status[0] = 1u;
+  if (i >= n) return;
+  const uint32_t rid = sorted_val[i];
+  const uint32_t cnt = count[rid];
+  if (cnt == 0) return;
+  const int4 rc = rect[rid];
+  const int tx0 = rc.x / tile_w, tx1 = (rc.x + rc.y) / tile_w;
+  const int ty0 = rc.z / tile_h, ty1 = (rc.z + rc.w) / tile_h;
+  const uint32_t view = rid / (uint32_t)n_stride;
+  uint64_t pos = offsets[i];
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx, ++pos) {
+      if (pos >= (uint64_t)capacity) return;
+      pair_key[pos] = view * (uint32_t)n_tiles + (uint32_t)(ty * tiles_x + tx);
+      pair_val[pos] = rid;
+    }
+}
+
+hipError_t launch_emit_pairs(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* count,
+                             const int4* rect, int64_t n, int n_stride, int tile_w, int tile_h, int tiles_x,
+                             int n_tiles, uint32_t* pair_key, uint32_t* pair_val, int64_t capacity,
+                             const uint64_t* total, uint32_t* status, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_emit_pairs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(sorted_val, offsets, count, rect, n, n_stride, tile_w,
+                                                           tile_h, tiles_x, n_tiles, pair_key, pair_val, capacity,
+                                                           total, status);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_f32(float* p, float v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_fill_u32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, value, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_fill_f32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, value, n);
+  return hipGetLastError();
+}
+
+__global__ void k_tile_ranges(const uint32_t* __restrict__ key, const uint64_t* total, int64_t capacity,
+                              uint2* __restrict__ ranges) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t t = *total;
+  const int64_t n = t < (uint64_t)capacity ? (int64_t)t : capacity;
+  if (i >= n) return;
+  const uint32_t k = key[i];
+  if (i == 0 || key[i - 1] != k) ranges[k].x = (uint32_t)i;
+  if (i == n - 1 || key[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
+}
+
+hipError_t launch_tile_ranges(const uint32_t* pair_key, const uint64_t* total, int64_t capacity, uint2* ranges,
+                              hipStream_t s) {
+  if (capacity <= 0) return hipSuccess;
+  k_tile_ranges<<<(unsigned)((capacity + 255) / 256), 256, 0, s>>>(pair_key, total, capacity, ranges);
+  return hipGetLastError();
+}
+
+}  // namespace chrf
