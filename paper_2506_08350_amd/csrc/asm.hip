@@ -285,6 +285,7 @@ static int ept_for(int elems) {
 static size_t row_lds(const AsmGeom& g) { return 2 * sizeof(cpx) * g.pW; }
 
 hipError_t launch_rows_forward(const float2* in, float2* out, const AsmGeom& g, const FftDesc& fr, hipStream_t s) {
+  if (tuned_rows(g)) return launch_rows_forward_t(in, out, g, fr, s);
   const unsigned rows = (unsigned)(g.n_bl * g.H);
   k_rows_forward<<<rows, kFftThreads, row_lds(g), s>>>(in, out, g, fr);
   return hipGetLastError();
@@ -293,6 +294,8 @@ hipError_t launch_rows_forward(const float2* in, float2* out, const AsmGeom& g, 
 hipError_t launch_rows_inverse(float2* y, const AsmGeom& g, const FftDesc& fr, float2* prop_out, float* intensity,
                                const float* target, float* loss_partial, float grad_coef, bool fuse_adjoint,
                                hipStream_t s) {
+  if (tuned_rows(g))
+    return launch_rows_inverse_t(y, g, fr, prop_out, intensity, target, loss_partial, grad_coef, fuse_adjoint, s);
   const unsigned rows = (unsigned)(g.n_bl * g.K * g.H);
   k_rows_inverse<<<rows, kFftThreads, row_lds(g), s>>>(y, g, fr, prop_out, intensity, target, loss_partial,
                                                        grad_coef, fuse_adjoint ? 1 : 0);
@@ -301,6 +304,7 @@ hipError_t launch_rows_inverse(float2* y, const AsmGeom& g, const FftDesc& fr, f
 
 hipError_t launch_rows_adjoint_in(const float2* prop, const float* dL_dI, const float2* dL_dprop, float2* z,
                                   const AsmGeom& g, const FftDesc& fr, hipStream_t s) {
+  if (tuned_rows(g)) return launch_rows_adjoint_in_t(prop, dL_dI, dL_dprop, z, g, fr, s);
   const unsigned rows = (unsigned)(g.n_bl * g.K * g.H);
   k_rows_adjoint_in<<<rows, kFftThreads, row_lds(g), s>>>(prop, dL_dI, dL_dprop, z, g, fr);
   return hipGetLastError();
@@ -308,6 +312,7 @@ hipError_t launch_rows_adjoint_in(const float2* prop, const float* dL_dI, const 
 
 hipError_t launch_rows_adjoint_out(const float2* w1, const float2* dL_dfield, float2* grad_field, const AsmGeom& g,
                                    const FftDesc& fr, hipStream_t s) {
+  if (tuned_rows(g)) return launch_rows_adjoint_out_t(w1, dL_dfield, grad_field, g, fr, s);
   const unsigned rows = (unsigned)(g.n_bl * g.H);
   k_rows_adjoint_out<<<rows, kFftThreads, row_lds(g), s>>>(w1, dL_dfield, grad_field, g, fr);
   return hipGetLastError();
@@ -323,6 +328,7 @@ size_t col_lds_bytes(int pH, int C) { return 2 * sizeof(cpx) * (size_t)pH * C; }
 
 hipError_t launch_cols_forward(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, int C,
                                hipStream_t s) {
+  if (tuned_cols(g)) return launch_cols_forward_t(x1, y, g, fc, s);
   const int ngroups = g.pW / C;
   const unsigned blocks = (unsigned)(g.n_bl * ngroups);
   const int span = C * 8 >= 128 ? 1 : 128 / (C * 8);
@@ -334,6 +340,7 @@ hipError_t launch_cols_forward(const float2* x1, float2* y, const AsmGeom& g, co
 
 hipError_t launch_cols_adjoint(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, int C,
                                hipStream_t s) {
+  if (tuned_cols(g)) return launch_cols_adjoint_t(z, w1, g, fc, s);
   const int ngroups = g.pW / C;
   const unsigned blocks = (unsigned)(g.n_bl * ngroups);
   const int span = C * 8 >= 128 ? 1 : 128 / (C * 8);

@@ -1,0 +1,344 @@
+// Tuned propagation passes for the padded grid of the 1080 x 1920 workloads
+// (rows of 3840 = 16 * 16 * 15, columns of 2160 = 16 * 15 * 9), built on the
+// compile-time three-stage transform of fft.h.  Same data flow and layouts as
+// the generic passes in asm.hip; the differences are that
+//   * every butterfly of every stage fits one thread (no stage loops), so
+//     a single in-place LDS buffer suffices and occupancy is higher;
+//   * the first stage reads HBM directly into registers and the last stage
+//     writes HBM directly, skipping two LDS round trips per transform;
+//   * fused transforms hand their registers to the next one without LDS:
+//     an inverse row FFT (16,16,15) followed by the adjoint's forward row FFT
+//     (15,16,16), and in the column pass the forward spectrum (16,15,9) stays
+//     in registers, is multiplied by H_k and fed to the inverse (9,15,16);
+//   * a column workgroup covers 4 adjacent columns with 1024 threads.
+#include "internal.h"
+
+namespace chrf {
+
+__device__ inline cpx ldc(const float2* p) {
+  const float2 v = *p;
+  return cpx{v.x, v.y};
+}
+__device__ inline void stc(float2* p, cpx v) { *p = make_float2(v.x, v.y); }
+
+__device__ inline int sbin(int k, int n) { return 2 * k < n ? k : k - n; }
+
+// Values that do not change across the plane loop would otherwise be hoisted
+// out of it (twiddles of every stage, per-element frequency terms) and kept
+// live in registers for the whole loop; passing them through an empty asm
+// statement makes each iteration recompute them instead.
+template <typename T>
+__device__ inline T opaque_s(T v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+__device__ inline int opaque_v(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// H_k / (pH pW) at bins (kx, ky), hardware sine/cosine of the residual phase in
+// revolutions (reduced to [-0.5, 0.5] first).
+__device__ inline cpx transfer_fast(const HParam& hp, int kx, int ky, const AsmGeom& g) {
+  const int sx = sbin(kx, g.pW), sy = sbin(ky, g.pH);
+  if (g.band_mode >= 2 && (abs(sx) > hp.kx_max || abs(sy) > hp.ky_max)) return cpx{0.f, 0.f};
+  const long long lhs = (long long)sx * sx * g.pH * g.pH + (long long)sy * sy * g.pW * g.pW;
+  if (lhs > hp.evan_bound) return cpx{0.f, 0.f};
+  const float fx = (float)sx * g.ax, fy = (float)sy * g.ay;
+  const float f2 = fx * fx + fy * fy;
+  const float root = __builtin_sqrtf(fmaxf(hp.inv_lam2 - f2, 0.0f));
+  float rev = hp.frac_rev - hp.z * f2 / (hp.inv_lam + root);
+  rev -= rintf(rev);
+  float s, c;
+  sincospif(2.0f * rev, &s, &c);
+  return cpx{c * g.norm, s * g.norm};
+}
+
+template <int N_, int NT, int R1_, int R2, int R3_>
+struct RowT {
+  static constexpr int N = N_, R1 = R1_, R3 = R3_;
+  using Fwd = Fft3<N, 1, NT, R1, R2, R3, false>;
+  using Inv = Fft3<N, 1, NT, R1, R2, R3, true>;
+  using FwdRev = Fft3<N, 1, NT, R3, R2, R1, false>;   // takes Inv's outputs as inputs
+  static_assert(Fwd::M1 == 1 && Fwd::M3 == 1 && FwdRev::M1 == 1 && FwdRev::M3 == 1, "one butterfly per thread");
+  static constexpr int S1 = N / R1, S3 = N / R3;
+};
+
+template <class RT>
+__global__ __launch_bounds__(256) void k_rows_forward_t(const float2* __restrict__ in, float2* __restrict__ out,
+                                                        AsmGeom g, FftDesc fr) {
+  __shared__ cpx lds[RT::N];
+  const size_t row = blockIdx.x;
+  const float2* src = in + row * g.W;
+  const int j = threadIdx.x;
+  cpx v1[1][RT::R1], v3[1][RT::R3];
+  if (j < RT::S1) {
+#pragma unroll
+    for (int r = 0; r < RT::R1; ++r) {
+      const int e = j + r * RT::S1;
+      v1[0][r] = e < g.W ? ldc(src + e) : cpx{0.f, 0.f};
+    }
+  }
+  RT::Fwd::run(v1, v3, lds, fr.tw);
+  float2* dst = out + row * (size_t)g.pW;
+  if (j < RT::S3) {
+#pragma unroll
+    for (int q = 0; q < RT::R3; ++q) stc(dst + j + q * RT::S3, v3[0][q]);
+  }
+}
+
+template <class RT>
+__global__ __launch_bounds__(256) void k_rows_inverse_t(float2* __restrict__ y, AsmGeom g, FftDesc fr,
+                                                        float2* __restrict__ prop_out, float* __restrict__ intensity,
+                                                        const float* __restrict__ target,
+                                                        float* __restrict__ loss_partial, float grad_coef, int fuse) {
+  __shared__ cpx lds[RT::N];
+  __shared__ float red[4];
+  const size_t row = blockIdx.x;
+  float2* yrow = y + row * (size_t)g.pW;
+  const int j = threadIdx.x;
+  cpx v1[1][RT::R1], v3[1][RT::R3];
+  if (j < RT::S1) {
+#pragma unroll
+    for (int r = 0; r < RT::R1; ++r) v1[0][r] = ldc(yrow + j + r * RT::S1);
+  }
+  RT::Inv::run(v1, v3, lds, fr.tw);
+  // v3[0][q] = u at column j + q * 256
+  const size_t ob = row * (size_t)g.W;
+  float lsum = 0.f;
+#pragma unroll
+  for (int q = 0; q < RT::R3; ++q) {
+    const int e = j + q * RT::S3;
+    if (e < g.W) {
+      const cpx u = v3[0][q];
+      if (prop_out) stc(prop_out + ob + e, u);
+      const float I = u.x * u.x + u.y * u.y;
+      if (intensity) intensity[ob + e] = I;
+      if (target) {
+        const float d = I - target[ob + e];
+        lsum += d * d;
+        v3[0][q] = u * (2.0f * grad_coef * d);
+      }
+    } else {
+      v3[0][q] = cpx{0.f, 0.f};
+    }
+  }
+  if (target) {
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0) loss_partial[row] = red[0] + red[1] + red[2] + red[3];
+  }
+  if (fuse) {
+    cpx w3[1][RT::R1];
+    RT::FwdRev::run(v3, w3, lds, fr.tw);
+    if (j < RT::S1) {
+#pragma unroll
+      for (int q = 0; q < RT::R1; ++q) stc(yrow + j + q * RT::S1, w3[0][q]);
+    }
+  }
+}
+
+template <class RT>
+__global__ __launch_bounds__(256) void k_rows_adjoint_in_t(const float2* __restrict__ prop,
+                                                           const float* __restrict__ dL_dI,
+                                                           const float2* __restrict__ dL_dprop,
+                                                           float2* __restrict__ z, AsmGeom g, FftDesc fr) {
+  __shared__ cpx lds[RT::N];
+  const size_t row = blockIdx.x;
+  const size_t ob = row * (size_t)g.W;
+  const int j = threadIdx.x;
+  cpx v1[1][RT::R1], v3[1][RT::R3];
+  if (j < RT::S1) {
+#pragma unroll
+    for (int r = 0; r < RT::R1; ++r) {
+      const int e = j + r * RT::S1;
+      cpx G{0.f, 0.f};
+      if (e < g.W) {
+        if (dL_dI) G = ldc(prop + ob + e) * (2.0f * dL_dI[ob + e]);
+        if (dL_dprop) G = G + ldc(dL_dprop + ob + e);
+      }
+      v1[0][r] = G;
+    }
+  }
+  RT::Fwd::run(v1, v3, lds, fr.tw);
+  float2* zrow = z + row * (size_t)g.pW;
+  if (j < RT::S3) {
+#pragma unroll
+    for (int q = 0; q < RT::R3; ++q) stc(zrow + j + q * RT::S3, v3[0][q]);
+  }
+}
+
+template <class RT>
+__global__ __launch_bounds__(256) void k_rows_adjoint_out_t(const float2* __restrict__ w1,
+                                                            const float2* __restrict__ dL_dfield,
+                                                            float2* __restrict__ grad_field, AsmGeom g, FftDesc fr) {
+  __shared__ cpx lds[RT::N];
+  const size_t row = blockIdx.x;
+  const float2* src = w1 + row * (size_t)g.pW;
+  const int j = threadIdx.x;
+  cpx v1[1][RT::R1], v3[1][RT::R3];
+  if (j < RT::S1) {
+#pragma unroll
+    for (int r = 0; r < RT::R1; ++r) v1[0][r] = ldc(src + j + r * RT::S1);
+  }
+  RT::Inv::run(v1, v3, lds, fr.tw);
+  const size_t ob = row * (size_t)g.W;
+#pragma unroll
+  for (int q = 0; q < RT::R3; ++q) {
+    const int e = j + q * RT::S3;
+    if (e < g.W) {
+      cpx v = v3[0][q];
+      if (dL_dfield) v = v + ldc(dL_dfield + ob + e);
+      stc(grad_field + ob + e, v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- columns ---
+// 4 adjacent columns per workgroup, one butterfly per thread (1024 threads).
+// LDS holds the work buffer of the transforms and, in the forward pass, the
+// spectrum that is reused for every plane (2 x 4 x 2160 complex = 135 KiB).
+constexpr int kColN = 2160, kColC = 4, kColNT = 1024;
+using ColFwd = Fft3<kColN, kColC, kColNT, 16, 15, 9, false>;
+using ColInv = Fft3<kColN, kColC, kColNT, 9, 15, 16, true>;
+static_assert(ColFwd::M1 == 1 && ColFwd::M3 == 1 && ColInv::M1 == 1 && ColInv::M3 == 1, "one butterfly per thread");
+static_assert(ColFwd::B3 == ColInv::B1, "forward outputs feed the inverse inputs");
+
+__device__ inline int col_remap(int id, int nblocks) {
+  // 4 column groups of 4 columns share one 128-byte line; give them to
+  // consecutive workgroups of the same XCD (dispatch is round-robin over 8)
+  const int span = 4, per = 8 * span;
+  const int full = (nblocks / per) * per;
+  if (id >= full) return id;
+  const int xcd = id & 7, slot = id >> 3;
+  return ((slot / span) * 8 + xcd) * span + slot % span;
+}
+
+__global__ __launch_bounds__(kColNT) void k_cols_forward_t(const float2* __restrict__ x1, float2* __restrict__ y,
+                                                           AsmGeom g, FftDesc fc) {
+  __shared__ cpx lds[kColN * kColC];
+  __shared__ cpx spec[kColN * kColC];
+  const int ngroups = g.pW / kColC;
+  const int gid = col_remap(blockIdx.x, gridDim.x);
+  const int bl = gid / ngroups;
+  const int c0 = (gid % ngroups) * kColC;
+  const int lam = bl % g.n_lambda;
+  const int b = threadIdx.x;
+  const int s = b % kColC, j = b / kColC;
+  {
+    cpx v1[1][16], v3[1][9];
+    if (b < ColFwd::B1) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = j + r * (kColN / 16);
+        v1[0][r] = n < g.H ? ldc(x1 + ((size_t)bl * g.H + n) * g.pW + c0 + s) : cpx{0.f, 0.f};
+      }
+    }
+    ColFwd::run(v1, v3, lds, fc.tw);
+    if (b < ColFwd::B3) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) spec[b + q * ColFwd::B3] = v3[0][q];
+    }
+  }
+  for (int k = 0; k < g.K; ++k) {
+    const HParam hp = g.hp[lam * g.K + k];
+    const cpx* tw = opaque_s(fc.tw);
+    const int jj = opaque_v(j), kx = opaque_v(c0 + s);
+    cpx w1[1][9], w3[1][16];
+    if (b < ColInv::B1) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) w1[0][q] = cmul(spec[b + q * ColInv::B1], transfer_fast(hp, kx, jj + q * (kColN / 9), g));
+    }
+    ColInv::run(w1, w3, lds, tw, opaque_v(b));
+    if (b < ColInv::B3) {
+      float2* yk = y + ((size_t)bl * g.K + k) * g.H * g.pW + kx;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int n = jj + q * (kColN / 16);
+        if (n < g.H) stc(yk + (size_t)n * g.pW, w3[0][q]);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kColNT) void k_cols_adjoint_t(const float2* __restrict__ z, float2* __restrict__ w1out,
+                                                           AsmGeom g, FftDesc fc) {
+  __shared__ cpx lds[kColN * kColC];
+  const int ngroups = g.pW / kColC;
+  const int gid = col_remap(blockIdx.x, gridDim.x);
+  const int bl = gid / ngroups;
+  const int c0 = (gid % ngroups) * kColC;
+  const int lam = bl % g.n_lambda;
+  const int b = threadIdx.x;
+  const int s = b % kColC, j = b / kColC;
+  cpx acc[1][9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[0][q] = cpx{0.f, 0.f};
+  for (int k = 0; k < g.K; ++k) {
+    const float2* zk = z + ((size_t)bl * g.K + k) * g.H * g.pW + c0 + s;
+    const cpx* tw = opaque_s(fc.tw);
+    const int jj = opaque_v(j), kx = opaque_v(c0 + s);
+    cpx v1[1][16], v3[1][9];
+    if (b < ColFwd::B1) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = jj + r * (kColN / 16);
+        v1[0][r] = n < g.H ? ldc(zk + (size_t)n * g.pW) : cpx{0.f, 0.f};
+      }
+    }
+    ColFwd::run(v1, v3, lds, tw, opaque_v(b));
+    const HParam hp = g.hp[lam * g.K + k];
+    if (b < ColFwd::B3) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+        acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_fast(hp, kx, jj + q * (kColN / 9), g));
+    }
+  }
+  cpx w3[1][16];
+  ColInv::run(acc, w3, lds, fc.tw);
+  if (b < ColInv::B3) {
+    float2* dst = w1out + (size_t)bl * g.H * g.pW + c0 + s;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int n = j + q * (kColN / 16);
+      if (n < g.H) stc(dst + (size_t)n * g.pW, w3[0][q]);
+    }
+  }
+}
+
+using Row3840 = RowT<3840, 256, 16, 16, 15>;
+
+bool tuned_rows(const AsmGeom& g) { return g.pW == 3840; }
+bool tuned_cols(const AsmGeom& g) { return g.pH == kColN && g.pW % (kColC * 32) == 0; }
+
+hipError_t launch_rows_forward_t(const float2* in, float2* out, const AsmGeom& g, const FftDesc& fr, hipStream_t s) {
+  k_rows_forward_t<Row3840><<<(unsigned)(g.n_bl * g.H), 256, 0, s>>>(in, out, g, fr);
+  return hipGetLastError();
+}
+hipError_t launch_rows_inverse_t(float2* y, const AsmGeom& g, const FftDesc& fr, float2* prop_out, float* intensity,
+                                 const float* target, float* loss_partial, float grad_coef, bool fuse, hipStream_t s) {
+  k_rows_inverse_t<Row3840><<<(unsigned)(g.n_bl * g.K * g.H), 256, 0, s>>>(y, g, fr, prop_out, intensity, target,
+                                                                            loss_partial, grad_coef, fuse ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t launch_rows_adjoint_in_t(const float2* prop, const float* dL_dI, const float2* dL_dprop, float2* z,
+                                    const AsmGeom& g, const FftDesc& fr, hipStream_t s) {
+  k_rows_adjoint_in_t<Row3840><<<(unsigned)(g.n_bl * g.K * g.H), 256, 0, s>>>(prop, dL_dI, dL_dprop, z, g, fr);
+  return hipGetLastError();
+}
+hipError_t launch_rows_adjoint_out_t(const float2* w1, const float2* dL_dfield, float2* grad_field, const AsmGeom& g,
+                                     const FftDesc& fr, hipStream_t s) {
+  k_rows_adjoint_out_t<Row3840><<<(unsigned)(g.n_bl * g.H), 256, 0, s>>>(w1, dL_dfield, grad_field, g, fr);
+  return hipGetLastError();
+}
+hipError_t launch_cols_forward_t(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, hipStream_t s) {
+  k_cols_forward_t<<<(unsigned)(g.n_bl * (g.pW / kColC)), kColNT, 0, s>>>(x1, y, g, fc);
+  return hipGetLastError();
+}
+hipError_t launch_cols_adjoint_t(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, hipStream_t s) {
+  k_cols_adjoint_t<<<(unsigned)(g.n_bl * (g.pW / kColC)), kColNT, 0, s>>>(z, w1, g, fc);
+  return hipGetLastError();
+}
+
+}  // namespace chrf

@@ -189,9 +189,11 @@ chrf_status chrf_create(int device, chrf_ctx** out) {
   if (c->lds_per_block > 65536) {
     // Opt in to the full LDS for the FFT passes; if the runtime refuses,
     // clear its sticky error and stay within 64 KiB.
-    if (asm_allow_lds(c->lds_per_block) != hipSuccess) {
+    if (asm_allow_lds(c->lds_per_block - 1024) != hipSuccess) {
       (void)hipGetLastError();
       c->lds_per_block = 65536;
+    } else {
+      c->lds_per_block -= 1024;
     }
   }
   *out = c;

@@ -174,6 +174,9 @@ template <bool INV> struct Dft<10, INV> : DftComp<2, 5, INV> {};
 template <bool INV> struct Dft<12, INV> : DftComp<4, 3, INV> {};
 template <bool INV> struct Dft<15, INV> : DftComp<3, 5, INV> {};
 template <bool INV> struct Dft<16, INV> : DftComp<4, 4, INV> {};
+template <bool INV> struct Dft<18, INV> : DftComp<2, 9, INV> {};
+template <bool INV> struct Dft<20, INV> : DftComp<4, 5, INV> {};
+template <bool INV> struct Dft<24, INV> : DftComp<8, 3, INV> {};
 
 // Radices the planner may use, largest first.
 constexpr int kRadices[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
@@ -260,5 +263,88 @@ __device__ inline cpx* fft_lds(cpx* buf0, cpx* buf1, int N, int C, int logC, con
   }
   return src;
 }
+
+// ---------------------------------------------------------------------------
+// Compile-time three-stage transform for the tuned sizes.  C sequences of
+// length N = R1 R2 R3 are interleaved as element (s, n) -> n * C + s.  A
+// butterfly b = tid + i * NT of a stage with radix R covers sequence
+// s = b % C and index j = b / C.
+//   in : v1[i][r] = element (s, j + r N/R1) of the stage-1 butterfly b
+//   out: v3[i][q] = element (s, j + q N/R3) of the stage-3 butterfly b
+// Stage 1 reads its inputs from registers and stage 3 leaves its outputs in
+// registers, so the caller loads from and stores to HBM directly; only the
+// two inner exchanges go through LDS (C * N values, in place).  A transform
+// whose R1 equals the R3 of the previous one consumes that one's v3 as is.
+// tw[m] = exp(-2 pi i m / N).
+// ---------------------------------------------------------------------------
+template <int N, int C, int NT, int R1, int R2, int R3, bool INV>
+struct Fft3 {
+  static_assert(R1 * R2 * R3 == N, "radices must multiply to N");
+  static constexpr int B1 = C * N / R1, B2 = C * N / R2, B3 = C * N / R3;
+  static constexpr int M1 = (B1 + NT - 1) / NT, M2 = (B2 + NT - 1) / NT, M3 = (B3 + NT - 1) / NT;
+
+  __device__ static inline cpx twid(const cpx* __restrict__ tw, int m) {
+    const cpx w = tw[m];
+    return INV ? cpx{w.x, -w.y} : w;
+  }
+
+  // tid is the thread index; callers inside loops may pass an opaque copy so
+  // that the per-stage LDS addresses are not hoisted and kept live.
+  __device__ static inline void run(cpx (&v1)[M1][R1], cpx (&v3)[M3][R3], cpx* lds, const cpx* __restrict__ tw,
+                                    int tid = threadIdx.x) {
+    // stage 1 (Ns = 1): no twiddles; output q of butterfly j goes to j R1 + q
+#pragma unroll
+    for (int i = 0; i < M1; ++i) {
+      const int b = tid + i * NT;
+      if (B1 % NT == 0 || b < B1) {
+        const int s = b % C, j = b / C;
+        Dft<R1, INV>::run(v1[i]);
+#pragma unroll
+        for (int q = 0; q < R1; ++q) lds[(j * R1 + q) * C + s] = v1[i][q];
+      }
+    }
+    __syncthreads();
+    // stage 2 (Ns = R1)
+    cpx v2[M2][R2];
+#pragma unroll
+    for (int i = 0; i < M2; ++i) {
+      const int b = tid + i * NT;
+      if (B2 % NT == 0 || b < B2) {
+        const int s = b % C, j = b / C, k = j % R1;
+#pragma unroll
+        for (int r = 0; r < R2; ++r) v2[i][r] = lds[(j + r * (N / R2)) * C + s];
+#pragma unroll
+        for (int r = 1; r < R2; ++r) v2[i][r] = cmul(v2[i][r], twid(tw, r * k * (N / (R1 * R2))));
+        Dft<R2, INV>::run(v2[i]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < M2; ++i) {
+      const int b = tid + i * NT;
+      if (B2 % NT == 0 || b < B2) {
+        const int s = b % C, j = b / C, k = j % R1;
+        const int base = (j - k) * R2 + k;
+#pragma unroll
+        for (int q = 0; q < R2; ++q) lds[(base + q * R1) * C + s] = v2[i][q];
+      }
+    }
+    __syncthreads();
+    // stage 3 (Ns = R1 R2 = N / R3): j < Ns, so k = j and outputs land at j + q N/R3
+#pragma unroll
+    for (int i = 0; i < M3; ++i) {
+      const int b = tid + i * NT;
+      if (B3 % NT == 0 || b < B3) {
+        const int s = b % C, j = b / C;
+#pragma unroll
+        for (int r = 0; r < R3; ++r) v3[i][r] = lds[(j + r * (N / R3)) * C + s];
+#pragma unroll
+        for (int r = 1; r < R3; ++r) v3[i][r] = cmul(v3[i][r], twid(tw, r * j));
+        Dft<R3, INV>::run(v3[i]);
+      }
+    }
+    __syncthreads();   // LDS is free again for the caller
+  }
+};
 
 }  // namespace chrf

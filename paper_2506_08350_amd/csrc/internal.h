@@ -150,6 +150,18 @@ hipError_t launch_rows_adjoint_out(const float2* w1, const float2* dL_dfield, fl
 hipError_t launch_reduce_loss(const float* partial, int64_t n, float scale, float* out, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s);
 hipError_t asm_allow_lds(int bytes);
+// tuned passes for padded rows of 3840 and columns of 2160 (asm_tuned.hip)
+bool tuned_rows(const AsmGeom& g);
+bool tuned_cols(const AsmGeom& g);
+hipError_t launch_rows_forward_t(const float2* in, float2* out, const AsmGeom& g, const FftDesc& fr, hipStream_t s);
+hipError_t launch_rows_inverse_t(float2* y, const AsmGeom& g, const FftDesc& fr, float2* prop_out, float* intensity,
+                                 const float* target, float* loss_partial, float grad_coef, bool fuse, hipStream_t s);
+hipError_t launch_rows_adjoint_in_t(const float2* prop, const float* dL_dI, const float2* dL_dprop, float2* z,
+                                    const AsmGeom& g, const FftDesc& fr, hipStream_t s);
+hipError_t launch_rows_adjoint_out_t(const float2* w1, const float2* dL_dfield, float2* grad_field, const AsmGeom& g,
+                                     const FftDesc& fr, hipStream_t s);
+hipError_t launch_cols_forward_t(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, hipStream_t s);
+hipError_t launch_cols_adjoint_t(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, hipStream_t s);
 size_t col_lds_bytes(int pH, int C);
 int fft_max_elems();
 
