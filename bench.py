@@ -39,6 +39,42 @@ def kernel_bytes(name, B, L, K, H, W, pH, pW, train):
     return table.get(name)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_step_c3_1080p_100k.md")
+
+
+def kernel_sources_sha256():
+    """Hash of every HIP source of the library (any change invalidates counters)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2506_08350_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or
+    None when that summary is missing or the sources changed since it was taken."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    sha = None
+    table = {}
+    for line in text.splitlines():
+        if line.startswith("sources-sha256:"):
+            sha = line.split(":", 1)[1].strip()
+        cells = [c.strip(" `") for c in line.strip().strip("|").split("|")]
+        if len(cells) == 5 and cells[0] and cells[4].isdigit():
+            table[cells[0]] = int(cells[4])
+    if sha != kernel_sources_sha256():
+        return None
+    return table.get(kernel)
+
+
 def cpu_baseline(w, seed=0):
     """Time the CPU oracle on a bounded sample of the workload.
 
@@ -82,14 +118,76 @@ def cpu_baseline(w, seed=0):
     }
 
 
+def bench_batched(args):
+    """16 views of the 500,000-Gaussian ring scene in one batched step, against
+    the same work done one view at a time with a single-view plan."""
+    import torch
+
+    import scenegen
+    from paper_2506_08350_amd import api
+
+    w = scenegen.make_workload("c4")
+    sc, cams, opt = w.scene, w.cameras, w.optics
+    B, H, W = len(cams), cams[0].height, cams[0].width
+    o = api.Optics(opt.wavelengths, opt.distances, opt.pitch, opt.pad, opt.band_limit)
+    params = {k: torch.from_numpy(a).cuda() for k, a in zip(api.PARAM_NAMES, sc.arrays())}
+    cam_t = api.pack_cameras(cams)
+    target = torch.from_numpy(w.targets).cuda()
+    probe = api.Renderer(H, W, o, n_views=B, max_gaussians=sc.n, max_pairs=1 << 28)
+    probe.forward(params, cam_t, want_field=False, want_intensity=False)
+    st, need = probe.read_status()
+    del probe
+    rb = api.Renderer(H, W, o, n_views=B, max_gaussians=sc.n, max_pairs=int(need * 1.1) + 4096)
+    r1 = api.Renderer(H, W, o, n_views=1, max_gaussians=sc.n, max_pairs=int(need * 1.1) + 4096)
+    tv = [target[v:v + 1].contiguous() for v in range(B)]
+
+    def batched():
+        return rb.train_step(params, cam_t, target)
+
+    def sequential():
+        for v in range(B):
+            r1.train_step(params, cam_t[v:v + 1], tv[v])
+
+    res = {}
+    for name, fn in (("batched", batched), ("sequential", sequential)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) * 1000.0 / args.steps
+    line = {
+        "metric": "hologram frames/s (splat+ASM, fwd+bwd) 1080p x 3 wavelengths x 8 planes, 16-view batch",
+        "value": round(B * 1000.0 / res["batched"], 3), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(res["batched"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c4_batched_16view_ring_500k", "gaussians": sc.n, "views_per_step": B,
+                   "height": H, "width": W, "wavelengths": sc.n_lambda, "planes": len(opt.distances),
+                   "pairs": int(need), "parallelism": "single-gpu"},
+        "sequential_ms_per_step": round(res["sequential"], 4),
+        "sequential_frames_per_s": round(B * 1000.0 / res["sequential"], 3),
+        "speedup_vs_sequential": round(res["sequential"] / res["batched"], 3),
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3"])
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4"],
+                    help="c3: 1080p fwd+bwd (default); c2: same, forward only; c4: 16-view batch vs sequential")
+    ap.add_argument("--graph", action="store_true", help="time replays of the step captured in a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-table", action="store_true", help="also print the per-kernel table to stderr")
+    ap.add_argument("--cols-per-block", type=int, default=0, help="column FFT pass: 2 or 4 columns per workgroup")
+    ap.add_argument("--tile", default="16x16", help="raster tile, e.g. 16x16, 16x8, 8x8")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one GPU "
@@ -103,6 +201,16 @@ def main(argv=None):
     from paper_2506_08350_amd import _lib, api
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"calibration copy: {n} bytes read, {n} bytes written", file=sys.stderr)
+        del src, dst
+    if args.workload == "c4":
+        return bench_batched(args)
     w = scenegen.make_workload("c3")          # c2 is the same scene and optics without the loss
     sc, cams, opt = w.scene, w.cameras, w.optics
     B, L, K = len(cams), sc.n_lambda, len(opt.distances)
@@ -115,12 +223,15 @@ def main(argv=None):
     target = torch.from_numpy(w.targets).cuda()
 
     # size the pair list from one eager forward
-    r = api.Renderer(H, W, o, n_views=B, max_gaussians=sc.n, max_pairs=1 << 26)
+    r = api.Renderer(H, W, o, n_views=B, max_gaussians=sc.n, max_pairs=1 << 27,
+                     tile=tuple(int(v) for v in args.tile.split("x")))
     r.forward(params, cam_t, want_field=False, want_intensity=False)
     st, need = r.read_status()
     cap = int(need * 1.25) + 4096
     del r
-    r = api.Renderer(H, W, o, n_views=B, max_gaussians=sc.n, max_pairs=cap)
+    tile = tuple(int(v) for v in args.tile.split("x"))
+    r = api.Renderer(H, W, o, n_views=B, max_gaussians=sc.n, max_pairs=cap, tile=tile,
+                     cols_per_block=args.cols_per_block)
 
     def step():
         if train:
@@ -134,13 +245,25 @@ def main(argv=None):
     if st != 0:
         raise RuntimeError(f"pair list overflow: {need} > {cap}")
     torch.cuda.synchronize()
-    r.timing(True)
+    if args.graph and train:
+        captured = api.CapturedTrainStep(r, params, cam_t, target)
+        step = captured.replay
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+    r.timing(not args.graph)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     r.timing(False)
+    if args.graph:       # per-kernel events cannot live inside a graph: time them eagerly
+        r.timing(True)
+        for _ in range(args.steps):
+            r.train_step(params, cam_t, target) if train else r.forward(params, cam_t, want_field=False)
+        torch.cuda.synchronize()
+        r.timing(False)
     kt = r.timing_report()
     ms = (t1 - t0) * 1000.0 / args.steps
     value = B * 1000.0 / ms
@@ -165,7 +288,7 @@ def main(argv=None):
     dom_bytes = kernel_bytes(dom, B, L, K, H, W, pH, pW, train)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
                 "avg_ms": round(dom_ms, 4), "algorithmic_bytes": dom_bytes}
     if args.kernel_table:
         tot = sum(c * m for c, m in per_launch.values())
@@ -184,6 +307,7 @@ def main(argv=None):
                    "views_per_step": B, "pad": opt.pad, "pairs": int(need), "parallelism": "single-gpu"},
         "fwd_frames_per_s": round(1000.0 / fwd_ms * B, 3) if fwd_ms else None,
         "fwd_ms": round(fwd_ms, 4) if fwd_ms else None,
+        "graph": bool(args.graph),
         "roofline": roofline,
         "kernels_ms_per_step": {n: round(c * m / args.steps, 4) for n, (c, m) in per_launch.items()},
     }

@@ -111,7 +111,7 @@ typedef struct chrf_grads {
  *   alpha_min, alpha_max, t_min   compositing thresholds (1/255, 0.99, 1e-4):
  *                      a Gaussian contributes where a >= alpha_min; a is
  *                      clamped at alpha_max; a pixel stops after T < t_min
- *   tile_w, tile_h     raster tile, multiples of 8 with tile_w*tile_h <= 256
+ *   tile_w, tile_h     raster tile, multiples of 8 with tile_w*tile_h in {64,128,256}
  *                      (0, 0 selects 16 x 16, the tile of Sec. 4.2)
  *   cols_per_block     columns per workgroup in the column FFT passes
  *                      (0 = choose from the LDS size)

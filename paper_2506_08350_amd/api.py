@@ -193,6 +193,35 @@ class Renderer:
         return out
 
 
+class CapturedTrainStep:
+    """The fused training step (forward with the MSE, then the backward)
+    captured once in a HIP graph and replayed.
+
+    The graph holds the pointers of ``params``, ``cams`` and ``target``: update
+    those tensors in place (``copy_``) between replays.  ``loss`` and ``grads``
+    are overwritten by every replay.  The library's forward and backward
+    enqueue no synchronisation, allocation or memset, so the whole sequence
+    (projection, sorts, raster, propagation, backward) is capturable.
+    """
+
+    def __init__(self, renderer: Renderer, params: dict, cams: torch.Tensor, target: torch.Tensor, warmup: int = 2):
+        self.renderer = renderer
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                renderer.train_step(params, cams, target)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.loss, self.grads, _ = renderer.train_step(params, cams, target)
+
+    def replay(self):
+        self.graph.replay()
+        return self.loss, self.grads
+
+
 class HologramFunction(torch.autograd.Function):
     """Intensities [B, L, K, H, W] of the propagated complex field, differentiable
     w.r.t. all six Gaussian parameter tensors through the library's backward."""

@@ -328,7 +328,7 @@ size_t col_lds_bytes(int pH, int C) { return 2 * sizeof(cpx) * (size_t)pH * C; }
 
 hipError_t launch_cols_forward(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, int C,
                                hipStream_t s) {
-  if (tuned_cols(g)) return launch_cols_forward_t(x1, y, g, fc, s);
+  if (tuned_cols(g)) return launch_cols_forward_t(x1, y, g, fc, C == 2 ? 2 : 4, s);
   const int ngroups = g.pW / C;
   const unsigned blocks = (unsigned)(g.n_bl * ngroups);
   const int span = C * 8 >= 128 ? 1 : 128 / (C * 8);
@@ -340,7 +340,7 @@ hipError_t launch_cols_forward(const float2* x1, float2* y, const AsmGeom& g, co
 
 hipError_t launch_cols_adjoint(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, int C,
                                hipStream_t s) {
-  if (tuned_cols(g)) return launch_cols_adjoint_t(z, w1, g, fc, s);
+  if (tuned_cols(g)) return launch_cols_adjoint_t(z, w1, g, fc, C == 2 ? 2 : 4, s);
   const int ngroups = g.pW / C;
   const unsigned blocks = (unsigned)(g.n_bl * ngroups);
   const int span = C * 8 >= 128 ? 1 : 128 / (C * 8);

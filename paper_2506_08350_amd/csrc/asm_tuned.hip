@@ -67,7 +67,7 @@ struct RowT {
 template <class RT>
 __global__ __launch_bounds__(256) void k_rows_forward_t(const float2* __restrict__ in, float2* __restrict__ out,
                                                         AsmGeom g, FftDesc fr) {
-  __shared__ cpx lds[RT::N];
+  __shared__ cpx lds[lds_padded_size(RT::N)];
   const size_t row = blockIdx.x;
   const float2* src = in + row * g.W;
   const int j = threadIdx.x;
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_rows_inverse_t(float2* __restrict__ y, 
                                                         float2* __restrict__ prop_out, float* __restrict__ intensity,
                                                         const float* __restrict__ target,
                                                         float* __restrict__ loss_partial, float grad_coef, int fuse) {
-  __shared__ cpx lds[RT::N];
+  __shared__ cpx lds[lds_padded_size(RT::N)];
   __shared__ float red[4];
   const size_t row = blockIdx.x;
   float2* yrow = y + row * (size_t)g.pW;
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256) void k_rows_adjoint_in_t(const float2* __restr
                                                            const float* __restrict__ dL_dI,
                                                            const float2* __restrict__ dL_dprop,
                                                            float2* __restrict__ z, AsmGeom g, FftDesc fr) {
-  __shared__ cpx lds[RT::N];
+  __shared__ cpx lds[lds_padded_size(RT::N)];
   const size_t row = blockIdx.x;
   const size_t ob = row * (size_t)g.W;
   const int j = threadIdx.x;
@@ -173,7 +173,7 @@ template <class RT>
 __global__ __launch_bounds__(256) void k_rows_adjoint_out_t(const float2* __restrict__ w1,
                                                             const float2* __restrict__ dL_dfield,
                                                             float2* __restrict__ grad_field, AsmGeom g, FftDesc fr) {
-  __shared__ cpx lds[RT::N];
+  __shared__ cpx lds[lds_padded_size(RT::N)];
   const size_t row = blockIdx.x;
   const float2* src = w1 + row * (size_t)g.pW;
   const int j = threadIdx.x;
@@ -196,62 +196,82 @@ __global__ __launch_bounds__(256) void k_rows_adjoint_out_t(const float2* __rest
 }
 
 // ---------------------------------------------------------------- columns ---
-// 4 adjacent columns per workgroup, one butterfly per thread (1024 threads).
-// LDS holds the work buffer of the transforms and, in the forward pass, the
-// spectrum that is reused for every plane (2 x 4 x 2160 complex = 135 KiB).
-constexpr int kColN = 2160, kColC = 4, kColNT = 1024;
-using ColFwd = Fft3<kColN, kColC, kColNT, 16, 15, 9, false>;
-using ColInv = Fft3<kColN, kColC, kColNT, 9, 15, 16, true>;
-static_assert(ColFwd::M1 == 1 && ColFwd::M3 == 1 && ColInv::M1 == 1 && ColInv::M3 == 1, "one butterfly per thread");
-static_assert(ColFwd::B3 == ColInv::B1, "forward outputs feed the inverse inputs");
+// C adjacent columns per workgroup (C = 4: 1024 threads, one workgroup per CU;
+// C = 2: 512 threads, two per CU), one butterfly per thread.  LDS holds the
+// work buffer of the transforms, the twiddles and, in the forward pass, the
+// spectrum reused for every plane.
+constexpr int kColN = 2160;
 
-__device__ inline int col_remap(int id, int nblocks) {
-  // 4 column groups of 4 columns share one 128-byte line; give them to
-  // consecutive workgroups of the same XCD (dispatch is round-robin over 8)
-  const int span = 4, per = 8 * span;
+template <int C>
+struct ColT {
+  static constexpr int NT = 256 * C;
+  using Fwd = Fft3<kColN, C, NT, 16, 15, 9, false>;
+  using Inv = Fft3<kColN, C, NT, 9, 15, 16, true>;
+  static_assert(Fwd::M1 == 1 && Fwd::M3 == 1 && Inv::M1 == 1 && Inv::M3 == 1, "one butterfly per thread");
+  static_assert(Fwd::B3 == Inv::B1, "forward outputs feed the inverse inputs");
+  static constexpr int SPAN = 128 / (8 * C);   // column groups per 128-byte line
+};
+
+__device__ inline int col_remap(int id, int nblocks, int span) {
+  // column groups that share a 128-byte line go to consecutive workgroups of
+  // the same XCD (dispatch is round-robin over the 8 XCDs)
+  const int per = 8 * span;
   const int full = (nblocks / per) * per;
   if (id >= full) return id;
   const int xcd = id & 7, slot = id >> 3;
   return ((slot / span) * 8 + xcd) * span + slot % span;
 }
 
-__global__ __launch_bounds__(kColNT) void k_cols_forward_t(const float2* __restrict__ x1, float2* __restrict__ y,
-                                                           AsmGeom g, FftDesc fc) {
-  __shared__ cpx lds[kColN * kColC];
-  __shared__ cpx spec[kColN * kColC];
-  const int ngroups = g.pW / kColC;
-  const int gid = col_remap(blockIdx.x, gridDim.x);
+// The N twiddles are copied to LDS once per workgroup: the stages of every
+// plane read them there instead of through the vector caches.
+template <int NT>
+__device__ inline const cpx* stage_twiddles(cpx* s_tw, const cpx* __restrict__ tw) {
+  for (int i = threadIdx.x; i < kColN; i += NT) s_tw[i] = tw[i];
+  __syncthreads();
+  return s_tw;
+}
+
+template <int C>
+__global__ __launch_bounds__(ColT<C>::NT) void k_cols_forward_t(const float2* __restrict__ x1,
+                                                                float2* __restrict__ y, AsmGeom g, FftDesc fc) {
+  using CT = ColT<C>;
+  __shared__ cpx lds[lds_padded_size(kColN * C)];
+  __shared__ cpx spec[kColN * C];
+  __shared__ cpx s_tw[kColN];
+  const cpx* twl = stage_twiddles<CT::NT>(s_tw, fc.tw);
+  const int ngroups = g.pW / C;
+  const int gid = col_remap(blockIdx.x, gridDim.x, CT::SPAN);
   const int bl = gid / ngroups;
-  const int c0 = (gid % ngroups) * kColC;
+  const int c0 = (gid % ngroups) * C;
   const int lam = bl % g.n_lambda;
   const int b = threadIdx.x;
-  const int s = b % kColC, j = b / kColC;
+  const int s = b % C, j = b / C;
   {
     cpx v1[1][16], v3[1][9];
-    if (b < ColFwd::B1) {
+    if (b < CT::Fwd::B1) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int n = j + r * (kColN / 16);
         v1[0][r] = n < g.H ? ldc(x1 + ((size_t)bl * g.H + n) * g.pW + c0 + s) : cpx{0.f, 0.f};
       }
     }
-    ColFwd::run(v1, v3, lds, fc.tw);
-    if (b < ColFwd::B3) {
+    CT::Fwd::run(v1, v3, lds, twl);
+    if (b < CT::Fwd::B3) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) spec[b + q * ColFwd::B3] = v3[0][q];
+      for (int q = 0; q < 9; ++q) spec[b + q * CT::Fwd::B3] = v3[0][q];
     }
   }
   for (int k = 0; k < g.K; ++k) {
     const HParam hp = g.hp[lam * g.K + k];
-    const cpx* tw = opaque_s(fc.tw);
     const int jj = opaque_v(j), kx = opaque_v(c0 + s);
     cpx w1[1][9], w3[1][16];
-    if (b < ColInv::B1) {
+    if (b < CT::Inv::B1) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) w1[0][q] = cmul(spec[b + q * ColInv::B1], transfer_fast(hp, kx, jj + q * (kColN / 9), g));
+      for (int q = 0; q < 9; ++q)
+        w1[0][q] = cmul(spec[b + q * CT::Inv::B1], transfer_fast(hp, kx, jj + q * (kColN / 9), g));
     }
-    ColInv::run(w1, w3, lds, tw, opaque_v(b));
-    if (b < ColInv::B3) {
+    CT::Inv::run(w1, w3, lds, twl, opaque_v(b));
+    if (b < CT::Inv::B3) {
       float2* yk = y + ((size_t)bl * g.K + k) * g.H * g.pW + kx;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
@@ -262,42 +282,46 @@ __global__ __launch_bounds__(kColNT) void k_cols_forward_t(const float2* __restr
   }
 }
 
-__global__ __launch_bounds__(kColNT) void k_cols_adjoint_t(const float2* __restrict__ z, float2* __restrict__ w1out,
-                                                           AsmGeom g, FftDesc fc) {
-  __shared__ cpx lds[kColN * kColC];
-  const int ngroups = g.pW / kColC;
-  const int gid = col_remap(blockIdx.x, gridDim.x);
+template <int C>
+__global__ __launch_bounds__(ColT<C>::NT) void k_cols_adjoint_t(const float2* __restrict__ z,
+                                                                float2* __restrict__ w1out, AsmGeom g,
+                                                                FftDesc fc) {
+  using CT = ColT<C>;
+  __shared__ cpx lds[lds_padded_size(kColN * C)];
+  __shared__ cpx s_tw[kColN];
+  const cpx* twl = stage_twiddles<CT::NT>(s_tw, fc.tw);
+  const int ngroups = g.pW / C;
+  const int gid = col_remap(blockIdx.x, gridDim.x, CT::SPAN);
   const int bl = gid / ngroups;
-  const int c0 = (gid % ngroups) * kColC;
+  const int c0 = (gid % ngroups) * C;
   const int lam = bl % g.n_lambda;
   const int b = threadIdx.x;
-  const int s = b % kColC, j = b / kColC;
+  const int s = b % C, j = b / C;
   cpx acc[1][9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) acc[0][q] = cpx{0.f, 0.f};
   for (int k = 0; k < g.K; ++k) {
     const float2* zk = z + ((size_t)bl * g.K + k) * g.H * g.pW + c0 + s;
-    const cpx* tw = opaque_s(fc.tw);
     const int jj = opaque_v(j), kx = opaque_v(c0 + s);
     cpx v1[1][16], v3[1][9];
-    if (b < ColFwd::B1) {
+    if (b < CT::Fwd::B1) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int n = jj + r * (kColN / 16);
         v1[0][r] = n < g.H ? ldc(zk + (size_t)n * g.pW) : cpx{0.f, 0.f};
       }
     }
-    ColFwd::run(v1, v3, lds, tw, opaque_v(b));
+    CT::Fwd::run(v1, v3, lds, twl, opaque_v(b));
     const HParam hp = g.hp[lam * g.K + k];
-    if (b < ColFwd::B3) {
+    if (b < CT::Fwd::B3) {
 #pragma unroll
       for (int q = 0; q < 9; ++q)
         acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_fast(hp, kx, jj + q * (kColN / 9), g));
     }
   }
   cpx w3[1][16];
-  ColInv::run(acc, w3, lds, fc.tw);
-  if (b < ColInv::B3) {
+  CT::Inv::run(acc, w3, lds, twl);
+  if (b < CT::Inv::B3) {
     float2* dst = w1out + (size_t)bl * g.H * g.pW + c0 + s;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -310,7 +334,7 @@ __global__ __launch_bounds__(kColNT) void k_cols_adjoint_t(const float2* __restr
 using Row3840 = RowT<3840, 256, 16, 16, 15>;
 
 bool tuned_rows(const AsmGeom& g) { return g.pW == 3840; }
-bool tuned_cols(const AsmGeom& g) { return g.pH == kColN && g.pW % (kColC * 32) == 0; }
+bool tuned_cols(const AsmGeom& g) { return g.pH == kColN && g.pW % 128 == 0; }
 
 hipError_t launch_rows_forward_t(const float2* in, float2* out, const AsmGeom& g, const FftDesc& fr, hipStream_t s) {
   k_rows_forward_t<Row3840><<<(unsigned)(g.n_bl * g.H), 256, 0, s>>>(in, out, g, fr);
@@ -332,12 +356,20 @@ hipError_t launch_rows_adjoint_out_t(const float2* w1, const float2* dL_dfield, 
   k_rows_adjoint_out_t<Row3840><<<(unsigned)(g.n_bl * g.H), 256, 0, s>>>(w1, dL_dfield, grad_field, g, fr);
   return hipGetLastError();
 }
-hipError_t launch_cols_forward_t(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, hipStream_t s) {
-  k_cols_forward_t<<<(unsigned)(g.n_bl * (g.pW / kColC)), kColNT, 0, s>>>(x1, y, g, fc);
+hipError_t launch_cols_forward_t(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, int C,
+                                 hipStream_t s) {
+  if (C == 2)
+    k_cols_forward_t<2><<<(unsigned)(g.n_bl * (g.pW / 2)), ColT<2>::NT, 0, s>>>(x1, y, g, fc);
+  else
+    k_cols_forward_t<4><<<(unsigned)(g.n_bl * (g.pW / 4)), ColT<4>::NT, 0, s>>>(x1, y, g, fc);
   return hipGetLastError();
 }
-hipError_t launch_cols_adjoint_t(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, hipStream_t s) {
-  k_cols_adjoint_t<<<(unsigned)(g.n_bl * (g.pW / kColC)), kColNT, 0, s>>>(z, w1, g, fc);
+hipError_t launch_cols_adjoint_t(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, int C,
+                                 hipStream_t s) {
+  if (C == 2)
+    k_cols_adjoint_t<2><<<(unsigned)(g.n_bl * (g.pW / 2)), ColT<2>::NT, 0, s>>>(z, w1, g, fc);
+  else
+    k_cols_adjoint_t<4><<<(unsigned)(g.n_bl * (g.pW / 4)), ColT<4>::NT, 0, s>>>(z, w1, g, fc);
   return hipGetLastError();
 }
 

@@ -228,8 +228,8 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
     return fail(CHRF_EINVAL, "plan: thresholds out of range");
   int tw = d.tile_w, th = d.tile_h;
   if (tw == 0 && th == 0) tw = th = 16;
-  if (tw <= 0 || th <= 0 || tw % 8 || th % 8 || tw * th > kRasterThreads)
-    return fail(CHRF_EINVAL, "plan: tile_w, tile_h must be multiples of 8 with tile_w * tile_h <= 256");
+  if (tw <= 0 || th <= 0 || tw % 8 || th % 8 || (tw * th != 64 && tw * th != 128 && tw * th != 256))
+    return fail(CHRF_EINVAL, "plan: tile_w, tile_h must be multiples of 8 with tile_w * tile_h in {64, 128, 256}");
 
   chrf_plan* p = new (std::nothrow) chrf_plan();
   if (!p) return fail(CHRF_ENOMEM, "plan: out of host memory");
@@ -248,7 +248,7 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   p->tiles_x = (d.width + tw - 1) / tw;
   p->tiles_y = (d.height + th - 1) / th;
   p->n_tiles = p->tiles_x * p->tiles_y;
-  p->g2 = 6 + 2 * p->L;
+  p->g2 = 16;   // 6 + 2 * n_lambda values, padded to one 64-byte row per (view, Gaussian)
   int64_t cap = d.max_pairs;
   if (cap <= 0) {
     cap = (int64_t)128 * p->B * (int64_t)(p->N > 0 ? p->N : 1);
@@ -272,14 +272,22 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   if ((int64_t)2 * 8 * p->pW > ctx->lds_per_block)
     return bad(fail(CHRF_EUNSUPPORTED, "plan: a padded row does not fit the LDS"));
   int C = d.cols_per_block;
-  if (C == 0) {
-    const int lds_cap = ctx->lds_per_block < 81920 ? ctx->lds_per_block : 81920;
-    C = 16;
-    while (C > 1 && ((int64_t)col_lds_bytes(p->pH, C) > lds_cap || p->pH * C > fft_max_elems() || p->pW % C)) C >>= 1;
+  if (tuned_cols(geom(p))) {
+    // tuned column pass: 4 columns x 1024 threads (default) or 2 x 512
+    if (C != 0 && C != 2 && C != 4)
+      return bad(fail(CHRF_EUNSUPPORTED, "plan: cols_per_block must be 2 or 4 for this padded height"));
+    if (C == 0) C = 4;
+  } else {
+    if (C == 0) {
+      const int lds_cap = ctx->lds_per_block < 81920 ? ctx->lds_per_block : 81920;
+      C = 16;
+      while (C > 1 && ((int64_t)col_lds_bytes(p->pH, C) > lds_cap || p->pH * C > fft_max_elems() || p->pW % C))
+        C >>= 1;
+    }
+    if (C < 1 || (C & (C - 1)) || p->pW % C || (int64_t)col_lds_bytes(p->pH, C) > ctx->lds_per_block ||
+        p->pH * C > fft_max_elems())
+      return bad(fail(CHRF_EUNSUPPORTED, "plan: cols_per_block does not fit the LDS or the padded width"));
   }
-  if (C < 1 || (C & (C - 1)) || p->pW % C || (int64_t)col_lds_bytes(p->pH, C) > ctx->lds_per_block ||
-      p->pH * C > fft_max_elems())
-    return bad(fail(CHRF_EUNSUPPORTED, "plan: cols_per_block does not fit the LDS or the padded width"));
   p->cols_per_block = C;
   // transfer-function parameters
   std::vector<HParam> hp(p->L * p->K);
@@ -314,6 +322,10 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   p->gsort_bits = 32 + bits_for(p->B - 1);
   p->psort_bits = bits_for((int64_t)p->B * p->n_tiles - 1);
   p->gsort_alt = ((p->gsort_bits + 7) / 8) % 2 == 1;
+  // one scan covers the histograms of every pass, so passes * count must fit 32 bits
+  if ((int64_t)((p->psort_bits + 7) / 8) * cap >= ((int64_t)1 << 32) ||
+      (int64_t)((p->gsort_bits + 7) / 8) * p->B * std::max(p->N, 1) >= ((int64_t)1 << 32))
+    return bad(fail(CHRF_EUNSUPPORTED, "plan: pair capacity too large for the 32-bit sort offsets"));
   p->psort_alt = ((p->psort_bits + 7) / 8) % 2 == 1;
   // workspace layout
   const int64_t BN = (int64_t)p->B * (p->N > 0 ? p->N : 1);

@@ -273,10 +273,16 @@ __device__ inline cpx* fft_lds(cpx* buf0, cpx* buf1, int N, int C, int logC, con
 //   out: v3[i][q] = element (s, j + q N/R3) of the stage-3 butterfly b
 // Stage 1 reads its inputs from registers and stage 3 leaves its outputs in
 // registers, so the caller loads from and stores to HBM directly; only the
-// two inner exchanges go through LDS (C * N values, in place).  A transform
+// two inner exchanges go through LDS (lds_padded_size(C * N) values, in place).  A transform
 // whose R1 equals the R3 of the previous one consumes that one's v3 as is.
 // tw[m] = exp(-2 pi i m / N).
 // ---------------------------------------------------------------------------
+// LDS index with one padding slot per 32 complex values: the Stockham stages
+// write with strides of R or R * C elements, which without padding would send
+// every lane of a wave to the same few banks.
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 5); }
+__host__ __device__ constexpr int lds_padded_size(int n) { return n + (n >> 5) + 1; }
+
 template <int N, int C, int NT, int R1, int R2, int R3, bool INV>
 struct Fft3 {
   static_assert(R1 * R2 * R3 == N, "radices must multiply to N");
@@ -300,7 +306,7 @@ struct Fft3 {
         const int s = b % C, j = b / C;
         Dft<R1, INV>::run(v1[i]);
 #pragma unroll
-        for (int q = 0; q < R1; ++q) lds[(j * R1 + q) * C + s] = v1[i][q];
+        for (int q = 0; q < R1; ++q) lds[lds_pad((j * R1 + q) * C + s)] = v1[i][q];
       }
     }
     __syncthreads();
@@ -312,9 +318,16 @@ struct Fft3 {
       if (B2 % NT == 0 || b < B2) {
         const int s = b % C, j = b / C, k = j % R1;
 #pragma unroll
-        for (int r = 0; r < R2; ++r) v2[i][r] = lds[(j + r * (N / R2)) * C + s];
+        for (int r = 0; r < R2; ++r) v2[i][r] = lds[lds_pad((j + r * (N / R2)) * C + s)];
+        // w^r for r >= 1 from one table entry by repeated multiplication
+        // (error grows by about one rounding per power: < 1e-6 for R <= 16)
+        const cpx w = twid(tw, k * (N / (R1 * R2)));
+        cpx wr = w;
 #pragma unroll
-        for (int r = 1; r < R2; ++r) v2[i][r] = cmul(v2[i][r], twid(tw, r * k * (N / (R1 * R2))));
+        for (int r = 1; r < R2; ++r) {
+          v2[i][r] = cmul(v2[i][r], wr);
+          wr = cmul(wr, w);
+        }
         Dft<R2, INV>::run(v2[i]);
       }
     }
@@ -326,7 +339,7 @@ struct Fft3 {
         const int s = b % C, j = b / C, k = j % R1;
         const int base = (j - k) * R2 + k;
 #pragma unroll
-        for (int q = 0; q < R2; ++q) lds[(base + q * R1) * C + s] = v2[i][q];
+        for (int q = 0; q < R2; ++q) lds[lds_pad((base + q * R1) * C + s)] = v2[i][q];
       }
     }
     __syncthreads();
@@ -337,9 +350,14 @@ struct Fft3 {
       if (B3 % NT == 0 || b < B3) {
         const int s = b % C, j = b / C;
 #pragma unroll
-        for (int r = 0; r < R3; ++r) v3[i][r] = lds[(j + r * (N / R3)) * C + s];
+        for (int r = 0; r < R3; ++r) v3[i][r] = lds[lds_pad((j + r * (N / R3)) * C + s)];
+        const cpx w = twid(tw, j);
+        cpx wr = w;
 #pragma unroll
-        for (int r = 1; r < R3; ++r) v3[i][r] = cmul(v3[i][r], twid(tw, r * j));
+        for (int r = 1; r < R3; ++r) {
+          v3[i][r] = cmul(v3[i][r], wr);
+          wr = cmul(wr, w);
+        }
         Dft<R3, INV>::run(v3[i]);
       }
     }

@@ -13,6 +13,7 @@ constexpr int kRasterThreads = 256;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // keys per sort block
+constexpr int kMaxSortPasses = 5;                       // 8-bit digits of up to 40-bit keys
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
@@ -160,8 +161,11 @@ hipError_t launch_rows_adjoint_in_t(const float2* prop, const float* dL_dI, cons
                                     const AsmGeom& g, const FftDesc& fr, hipStream_t s);
 hipError_t launch_rows_adjoint_out_t(const float2* w1, const float2* dL_dfield, float2* grad_field, const AsmGeom& g,
                                      const FftDesc& fr, hipStream_t s);
-hipError_t launch_cols_forward_t(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, hipStream_t s);
-hipError_t launch_cols_adjoint_t(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, hipStream_t s);
+// C = 2 or 4 columns per workgroup
+hipError_t launch_cols_forward_t(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, int C,
+                                 hipStream_t s);
+hipError_t launch_cols_adjoint_t(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, int C,
+                                 hipStream_t s);
 size_t col_lds_bytes(int pH, int C);
 int fft_max_elems();
 

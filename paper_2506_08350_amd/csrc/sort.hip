@@ -10,8 +10,9 @@
 // starts from index order.  Depths are positive floats, whose bit patterns
 // order like their values.
 //
-// The radix sort is the classic three-kernel LSD pass (digit histogram per
-// block, exclusive scan over (digit, block), stable scatter).  Ranks inside a
+// The radix sort is LSD with 8-bit digits: one kernel counts the digit
+// histograms of every pass per block, one exclusive scan covers all of them
+// (pass, digit, block), and each pass is a stable scatter.  Ranks inside a
 // block come from wave ballots: a lane's rank among equal digits is the
 // popcount of the lower lanes whose 8 digit bits all match, plus the counts of
 // earlier waves and earlier rounds held in LDS.  Counts that are only known on
@@ -100,11 +101,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const TIn* __restric
 
 int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
+template <typename T>
+__global__ void k_zero_one(T* p) {
+  *p = 0;
+}
+
 template <typename TIn, typename TOut>
 static hipError_t scan_impl(const TIn* in, TOut* out, int64_t n, TOut* tmp, TOut* total, hipStream_t s) {
-  if (n <= 0) {
-    if (total) return hipMemsetAsync(total, 0, sizeof(TOut), s);
-    return hipSuccess;
+  if (n <= 0) {   // a kernel, not a memset, so that the sequence stays capturable
+    if (total) k_zero_one<TOut><<<1, 1, 0, s>>>(total);
+    return hipGetLastError();
   }
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   k_scan_reduce<TIn, TOut><<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, tmp);
@@ -128,12 +134,14 @@ __device__ inline int64_t live_count(int64_t n_max, const uint64_t* n_dev) {
   return v < (uint64_t)n_max ? (int64_t)v : n_max;
 }
 
+// Digit histograms of every pass in one read of the keys:
+// hist[(pass * 256 + digit) * nblocks + block].
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* __restrict__ keys, int64_t n_max,
-                                                             const uint64_t* n_dev, int shift,
+                                                             const uint64_t* n_dev, int begin_bit, int npasses,
                                                              uint32_t* __restrict__ hist, int nblocks) {
-  __shared__ uint32_t cnt[256];
-  cnt[threadIdx.x] = 0;
+  __shared__ uint32_t cnt[kMaxSortPasses][256];
+  for (int p = 0; p < npasses; ++p) cnt[p][threadIdx.x] = 0;
   __syncthreads();
   const int64_t n = live_count(n_max, n_dev);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
@@ -141,11 +149,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* __restrict
 #pragma unroll 4
     for (int i = 0; i < kSortItems; ++i) {
       const int64_t idx = base + i * kSortThreads + threadIdx.x;
-      if (idx < n) atomicAdd(&cnt[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+      if (idx < n) {
+        const K key = keys[idx];
+        for (int p = 0; p < npasses; ++p) atomicAdd(&cnt[p][(uint32_t)(key >> (begin_bit + 8 * p)) & 255u], 1u);
+      }
     }
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+  for (int p = 0; p < npasses; ++p)
+    hist[((int64_t)p * 256 + threadIdx.x) * nblocks + blockIdx.x] = cnt[p][threadIdx.x];
 }
 
 template <typename K>
@@ -153,8 +165,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
                                                                 const uint32_t* __restrict__ vals_in,
                                                                 K* __restrict__ keys_out,
                                                                 uint32_t* __restrict__ vals_out, int64_t n_max,
-                                                                const uint64_t* n_dev, int shift,
+                                                                const uint64_t* n_dev, int shift, int pass,
                                                                 const uint32_t* __restrict__ offsets, int nblocks) {
+  // offsets is the exclusive scan of every pass's histogram laid end to end;
+  // each pass counts n keys, so this pass's offsets start at pass * n
   constexpr int NW = kSortThreads / 64;
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[NW][256];
@@ -165,7 +179,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
   if (base >= n) return;   // uniform per block
   run[tid] = 0;
   for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
-  goff[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+  goff[tid] = offsets[((int64_t)pass * 256 + tid) * nblocks + blockIdx.x] - (uint32_t)(pass * n);
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int r = 0; r < kSortItems; ++r) {
@@ -209,7 +223,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
 
 int64_t radix_hist_elems(int64_t n_max) {
   const int64_t nb = (n_max + kSortTile - 1) / kSortTile;
-  return 256 * (nb > 0 ? nb : 1);
+  return (int64_t)kMaxSortPasses * 256 * (nb > 0 ? nb : 1);
 }
 
 template <typename K>
@@ -219,16 +233,21 @@ static hipError_t radix_sort_impl(K* keys, K* keys_alt, uint32_t* vals, uint32_t
   *result_in_alt = false;
   if (n_max <= 0) return hipSuccess;
   const int nblocks = (int)((n_max + kSortTile - 1) / kSortTile);
+  const int npasses = (end_bit - begin_bit + 7) / 8;
+  if (npasses <= 0) return hipSuccess;
+  if (npasses > kMaxSortPasses) return hipErrorInvalidValue;
   K* kin = keys;
   K* kout = keys_alt;
   uint32_t* vin = vals;
   uint32_t* vout = vals_alt;
   bool alt = false;
-  for (int shift = begin_bit; shift < end_bit; shift += 8) {
-    k_radix_hist<K><<<nblocks, kSortThreads, 0, s>>>(kin, n_max, n_dev, shift, hist, nblocks);
-    hipError_t e = launch_scan_u32(hist, hist, (int64_t)256 * nblocks, scan_tmp, s);
-    if (e != hipSuccess) return e;
-    k_radix_scatter<K><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n_max, n_dev, shift, hist, nblocks);
+  k_radix_hist<K><<<nblocks, kSortThreads, 0, s>>>(keys, n_max, n_dev, begin_bit, npasses, hist, nblocks);
+  hipError_t e = launch_scan_u32(hist, hist, (int64_t)npasses * 256 * nblocks, scan_tmp, s);
+  if (e != hipSuccess) return e;
+  for (int pass = 0; pass < npasses; ++pass) {
+    const int shift = begin_bit + 8 * pass;
+    k_radix_scatter<K><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n_max, n_dev, shift, pass, hist,
+                                                        nblocks);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     K* tk = kin; kin = kout; kout = tk;
@@ -266,40 +285,47 @@ hipError_t launch_gather_counts(const uint32_t* sorted_val, const uint32_t* coun
   return hipGetLastError();
 }
 
-// One thread per sorted (view, Gaussian); pairs of one Gaussian are emitted in
-// row-major tile order.  Pairs past the capacity are dropped and flagged.
+// One thread per pair.  Pair p belongs to the sorted (view, Gaussian) entry i
+// with offsets[i] <= p < offsets[i] + count (found by binary search over the
+// exclusive scan of the counts); its tiles are enumerated in row-major order
+// over the Gaussian's tile rectangle.  Pairs past the capacity are dropped and
+// flagged, so every write stays in bounds.
 __global__ void k_emit_pairs(const uint32_t* __restrict__ sorted_val, const uint64_t* __restrict__ offsets,
                              const uint32_t* __restrict__ count, const int4* __restrict__ rect, int64_t n,
                              int n_stride, int tile_w, int tile_h, int tiles_x, int n_tiles,
                              uint32_t* __restrict__ pair_key, uint32_t* __restrict__ pair_val, int64_t capacity,
                              const uint64_t* total, uint32_t* status) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0 && *total > (uint64_t)capacity) status[0] = 1u;
-  if (i >= n) return;
-  const uint32_t rid = sorted_val[i];
-  const uint32_t cnt = count[rid];
-  if (cnt == 0) return;
+  const uint64_t tot = *total;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0 && tot > (uint64_t)capacity) status[0] = 1u;
+  const int64_t live = tot < (uint64_t)capacity ? (int64_t)tot : capacity;
+  if (p >= live) return;
+  // largest i with offsets[i] <= p; entries with zero count share the offset of
+  // the next one, so take the last of a run of equal offsets
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (offsets[mid] <= (uint64_t)p) lo = mid; else hi = mid - 1;
+  }
+  const uint32_t rid = sorted_val[lo];
   const int4 rc = rect[rid];
   const int tx0 = rc.x / tile_w, tx1 = (rc.x + rc.y) / tile_w;
-  const int ty0 = rc.z / tile_h, ty1 = (rc.z + rc.w) / tile_h;
+  const int ty0 = rc.z / tile_h;
+  const int wt = tx1 - tx0 + 1;
+  const int local = (int)(p - (int64_t)offsets[lo]);
   const uint32_t view = rid / (uint32_t)n_stride;
-  uint64_t pos = offsets[i];
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx, ++pos) {
-      if (pos >= (uint64_t)capacity) return;
-      pair_key[pos] = view * (uint32_t)n_tiles + (uint32_t)(ty * tiles_x + tx);
-      pair_val[pos] = rid;
-    }
+  pair_key[p] = view * (uint32_t)n_tiles + (uint32_t)((ty0 + local / wt) * tiles_x + tx0 + local % wt);
+  pair_val[p] = rid;
 }
 
 hipError_t launch_emit_pairs(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* count,
                              const int4* rect, int64_t n, int n_stride, int tile_w, int tile_h, int tiles_x,
                              int n_tiles, uint32_t* pair_key, uint32_t* pair_val, int64_t capacity,
                              const uint64_t* total, uint32_t* status, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  k_emit_pairs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(sorted_val, offsets, count, rect, n, n_stride, tile_w,
-                                                           tile_h, tiles_x, n_tiles, pair_key, pair_val, capacity,
-                                                           total, status);
+  if (n <= 0 || capacity <= 0) return hipSuccess;
+  k_emit_pairs<<<(unsigned)((capacity + 255) / 256), 256, 0, s>>>(sorted_val, offsets, count, rect, n, n_stride,
+                                                                  tile_w, tile_h, tiles_x, n_tiles, pair_key,
+                                                                  pair_val, capacity, total, status);
   return hipGetLastError();
 }
 

@@ -1,0 +1,149 @@
+"""Full-size workloads in the launch configuration the benchmark times.
+
+At these sizes the oracle cannot render whole frames in test time, so the
+checks are
+* the rendered field on sampled windows of every view against the FP64 oracle
+  restricted to those windows (relative L2 <= 1e-4);
+* the tile lists of sampled tiles against the oracle's single-precision
+  binning (bit-exact);
+* the fused loss against the intensities the same call returned;
+* the gradient against a central difference of the loss along the gradient
+  direction with the means held fixed (a property that holds at any size).
+The propagation at the full padded size is checked in test_gpu_asm.py.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import binning, projection, raster
+from paper_2506_08350_amd import _lib, api
+from scenegen import make_workload
+from tests.gpu_helpers import announce, cplx, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+WINDOWS = ((0.25, 0.3), (0.5, 0.5), (0.7, 0.8))   # fractional (row, column) of sampled windows
+WIN = (40, 64)
+
+
+def _renderer(w, cap_factor=1.25, want_cap=None):
+    cams = w.cameras
+    o = api.Optics(w.optics.wavelengths, w.optics.distances, w.optics.pitch, w.optics.pad, w.optics.band_limit)
+    H, W = cams[0].height, cams[0].width
+    params = {k: torch.from_numpy(a).cuda() for k, a in zip(api.PARAM_NAMES, w.scene.arrays())}
+    cam_t = api.pack_cameras(cams)
+    r = api.Renderer(H, W, o, n_views=len(cams), max_gaussians=w.scene.n, max_pairs=want_cap or (1 << 26))
+    r.forward(params, cam_t, want_field=False, want_intensity=False)
+    st, need = r.read_status()
+    if st != 0 or want_cap is None:
+        del r
+        r = api.Renderer(H, W, o, n_views=len(cams), max_gaussians=w.scene.n, max_pairs=int(need * cap_factor) + 4096)
+    return r, params, cam_t
+
+
+def _window_checks(w, field, r):
+    sc = w.scene
+    H, W = w.cameras[0].height, w.cameras[0].width
+    U = field
+    for b, cam in enumerate(w.cameras):
+        p = projection.project(sc.means, sc.log_scales, sc.quats, sc.amp, sc.phase, cam)
+        fp = binning.fp32_footprint(sc.means, sc.log_scales, sc.quats, cam)
+        for fr, fc in WINDOWS[: (3 if len(w.cameras) <= 4 else 1)]:
+            r0, c0 = int(fr * H), int(fc * W)
+            win = (r0, r0 + WIN[0], c0, c0 + WIN[1])
+            res = raster.render_field(p, sc.opacity, fp, W, H, oracle.DEFAULT, window=win)
+            got = cplx(U[b, :, win[0]:win[1], win[2]:win[3]])
+            ref = res.U[:, win[0]:win[1], win[2]:win[3]]
+            assert rel_l2(got, ref) < 1e-4, (b, win)
+
+
+def _tile_checks(w, r):
+    """Sampled tiles: the sorted Gaussian list of the tile equals the oracle's."""
+    sc = w.scene
+    H, W = w.cameras[0].height, w.cameras[0].width
+    tx, ty = (W + 15) // 16, (H + 15) // 16
+    n_tiles = tx * ty
+    ranges = r.region(_lib.REGION_TILE_RANGES, torch.int32).cpu().numpy().view(np.uint32).reshape(-1, 2)
+    vals = r.region(_lib.REGION_PAIR_VALUES, torch.int32)
+    for b, cam in enumerate(w.cameras[:4]):
+        fp = binning.fp32_footprint(sc.means, sc.log_scales, sc.quats, cam)
+        vis = np.nonzero(fp["visible"])[0]
+        tiles = fp["tiles"][vis]
+        for (fr, fc) in WINDOWS:
+            t_r, t_c = int(fr * ty), int(fc * tx)
+            t = b * n_tiles + t_r * tx + t_c
+            inside = (tiles[:, 0] <= t_c) & (t_c <= tiles[:, 1]) & (tiles[:, 2] <= t_r) & (t_r <= tiles[:, 3])
+            g = vis[inside]
+            ref = g[np.lexsort((g, fp["key"][g].astype(np.int64)))]
+            s, e = ranges[t]
+            got = vals[int(s):int(e)].cpu().numpy().view(np.uint32).astype(np.int64) - b * sc.n
+            assert np.array_equal(got, ref), (b, t)
+
+
+def _directional_check(r, params, cam_t, target, loss0, grads):
+    gnorm2 = sum(float((grads[k].double() ** 2).sum()) for k in api.PARAM_NAMES)
+    d = {k: grads[k] / np.sqrt(gnorm2) for k in api.PARAM_NAMES}
+    h = 2e-3
+    losses = []
+    for sgn in (1.0, -1.0):
+        pp = {k: (params[k] + sgn * h * d[k]).contiguous() for k in api.PARAM_NAMES}
+        out = r.forward(pp, cam_t, want_field=False, want_intensity=False, target=target)
+        losses.append(float(out["loss"]))
+    fd = (losses[0] - losses[1]) / (2 * h)
+    an = np.sqrt(gnorm2)
+    assert abs(fd - an) < 0.1 * an, (fd, an)
+
+
+def test_forward_backward_1080p_100k():
+    w = make_workload("c3")
+    announce("workload 1080p 100k fwd+bwd")
+    r, params, cam_t = _renderer(w)
+    target = torch.from_numpy(w.targets).cuda()
+    out = r.forward(params, cam_t, want_field=True, want_intensity=True, target=target)
+    grads = r.backward(params, cam_t)
+    torch.cuda.synchronize()
+    assert r.read_status()[0] == 0
+    I = out["intensity"].double()
+    ref_loss = float(((I - target.double()) ** 2).mean())
+    assert abs(float(out["loss"]) - ref_loss) < 1e-5 * ref_loss
+    _window_checks(w, out["field"], r)
+    _tile_checks(w, r)
+    for k in api.PARAM_NAMES:
+        assert torch.isfinite(grads[k]).all(), k
+
+
+def test_gradient_direction_1080p_100k():
+    """Directional derivative at full size along the gradient with the means
+    held fixed.  Moving means reorders depths, and at 100,000 Gaussians the
+    jumps from depth swaps outweigh the derivative; every other parameter
+    leaves the sort order alone, and the remaining support/termination jumps
+    are orders of magnitude smaller than the signal."""
+    w = make_workload("c3")
+    announce("workload 1080p 100k directional derivative")
+    r, params, cam_t = _renderer(w)
+    target = torch.from_numpy(w.targets).cuda()
+    out = r.forward(params, cam_t, want_field=False, want_intensity=False, target=target)
+    grads = r.backward(params, cam_t)
+    torch.cuda.synchronize()
+    grads["means"] = torch.zeros_like(grads["means"])
+    _directional_check(r, params, cam_t, target, float(out["loss"]), grads)
+
+
+def test_batched_16_views_ring_500k():
+    w = make_workload("c4")
+    announce("workload 16 views 500k")
+    r, params, cam_t = _renderer(w)
+    target = torch.from_numpy(w.targets).cuda()
+    out = r.forward(params, cam_t, want_field=True, want_intensity=False, target=target)
+    grads = r.backward(params, cam_t)
+    torch.cuda.synchronize()
+    st, need = r.read_status()
+    assert st == 0
+    counts = [int(np.count_nonzero(binning.fp32_footprint(w.scene.means, w.scene.log_scales, w.scene.quats,
+                                                          c)["visible"])) for c in w.cameras[:3]]
+    assert len(set(counts)) > 1      # uneven post-culling counts per view
+    _window_checks(w, out["field"], r)
+    _tile_checks(w, r)
+    for k in api.PARAM_NAMES:
+        assert torch.isfinite(grads[k]).all(), k
