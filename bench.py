@@ -179,13 +179,16 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4"],
-                    help="c3: 1080p fwd+bwd (default); c2: same, forward only; c4: 16-view batch vs sequential")
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c3_layers"],
+                    help="c3: 1080p fwd+bwd (default); c2: same, forward only; c4: 16-view batch vs sequential; "
+                         "c3_layers: the c3 scene as a four-layer hologram (record + inverse propagation)")
     ap.add_argument("--graph", action="store_true", help="time replays of the step captured in a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-table", action="store_true", help="also print the per-kernel table to stderr")
     ap.add_argument("--cols-per-block", type=int, default=0, help="column FFT pass: 2 or 4 columns per workgroup")
-    ap.add_argument("--tile", default="16x16", help="raster tile, e.g. 16x16, 16x8, 8x8")
+    ap.add_argument("--tile", default=None, help="raster tile, e.g. 16x16, 16x8, 8x8 (default 16x16; 8x8 layered)")
+    ap.add_argument("--no-fwd-rate", action="store_true",
+                    help="skip the separate forward-only timing (keeps every launch a training-step launch)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args(argv)
@@ -211,27 +214,29 @@ def main(argv=None):
         del src, dst
     if args.workload == "c4":
         return bench_batched(args)
-    w = scenegen.make_workload("c3")          # c2 is the same scene and optics without the loss
+    layered = args.workload == "c3_layers"
+    w = scenegen.make_workload("c3_layers" if layered else "c3")   # c2: the c3 scene and optics without the loss
     sc, cams, opt = w.scene, w.cameras, w.optics
     B, L, K = len(cams), sc.n_lambda, len(opt.distances)
     H, W = cams[0].height, cams[0].width
     pH, pW = opt.pad * H, opt.pad * W
-    train = args.workload == "c3"
+    train = args.workload in ("c3", "c3_layers")
     o = api.Optics(opt.wavelengths, opt.distances, opt.pitch, opt.pad, opt.band_limit)
     params = {k: torch.from_numpy(a).cuda() for k, a in zip(api.PARAM_NAMES, sc.arrays())}
+    if layered:
+        params[api.LAYER_LOGITS] = torch.from_numpy(w.notes["logits"]).cuda()
+    tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else ((8, 8) if layered else (16, 16))
     cam_t = api.pack_cameras(cams)
     target = torch.from_numpy(w.targets).cuda()
 
     # size the pair list from one eager forward
-    r = api.Renderer(H, W, o, n_views=B, max_gaussians=sc.n, max_pairs=1 << 27,
-                     tile=tuple(int(v) for v in args.tile.split("x")))
+    r = api.Renderer(H, W, o, n_views=B, max_gaussians=sc.n, max_pairs=1 << 27, tile=tile, layered=layered)
     r.forward(params, cam_t, want_field=False, want_intensity=False)
     st, need = r.read_status()
     cap = int(need * 1.25) + 4096
     del r
-    tile = tuple(int(v) for v in args.tile.split("x"))
     r = api.Renderer(H, W, o, n_views=B, max_gaussians=sc.n, max_pairs=cap, tile=tile,
-                     cols_per_block=args.cols_per_block)
+                     cols_per_block=args.cols_per_block, layered=layered)
 
     def step():
         if train:
@@ -270,7 +275,7 @@ def main(argv=None):
 
     # forward-only rate (intensities out), same scene and optics
     fwd_ms = None
-    if train:
+    if train and not args.no_fwd_rate:
         for _ in range(2):
             r.forward(params, cam_t, want_field=False, want_intensity=True)
         torch.cuda.synchronize()
@@ -297,12 +302,15 @@ def main(argv=None):
             bw = f"{b / (m * 1e-3) / 1e9:8.1f} GB/s" if b else ""
             print(f"{n:18s} {c:4d} x {m:8.4f} ms  {100 * c * m / tot:5.1f}%  {bw}", file=sys.stderr)
 
+    metric = ("hologram frames/s (splat+ASM, fwd+bwd) 1080p x 3 wavelengths x 4 planes" if not layered else
+              "hologram frames/s (4-layer splat + record + inverse ASM, fwd+bwd) 1080p x 3 wavelengths")
+    workload = ("c3_fwd_bwd_1080p_3l_4z_100k" if train else "c2_fwd_1080p_3l_4z_100k") if not layered else w.name
     line = {
-        "metric": "hologram frames/s (splat+ASM, fwd+bwd) 1080p x 3 wavelengths x 4 planes",
+        "metric": metric,
         "value": round(value, 3), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "c3_fwd_bwd_1080p_3l_4z_100k" if train else "c2_fwd_1080p_3l_4z_100k",
+        "config": {"workload": workload, "tile": f"{tile[0]}x{tile[1]}",
                    "gaussians": sc.n, "height": H, "width": W, "wavelengths": L, "planes": K,
                    "views_per_step": B, "pad": opt.pad, "pairs": int(need), "parallelism": "single-gpu"},
         "fwd_frames_per_s": round(1000.0 / fwd_ms * B, 3) if fwd_ms else None,
@@ -311,7 +319,7 @@ def main(argv=None):
         "roofline": roofline,
         "kernels_ms_per_step": {n: round(c * m / args.steps, 4) for n, (c, m) in per_launch.items()},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not layered:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)
     return 0

@@ -63,12 +63,13 @@ typedef struct chrf_camera {
 } chrf_camera;
 
 /*
- * Complex Gaussians (Eq. 9 without the plane logits: this build renders one
- * plane, rho = 1).  Device arrays:
+ * Complex Gaussians k = (c, x, R, S, alpha, phi, rho') of Eq. 9.  Device arrays:
  *   means [n,3]; log_scales [n,3] (S = diag(exp(s))); quats [n,4] as
  *   (w, x, y, z) of any nonzero norm (normalised inside); opacity [n] already
  *   activated, in (0,1); amp [n, n_lambda] (c, the wave amplitude); phase
- *   [n, n_lambda] in radians (phi).
+ *   [n, n_lambda] in radians (phi); logits [n, n_planes], the raw plane
+ *   assignment logits rho' of a layered plan (Eq. 12; NULL for a
+ *   single-plane plan, where rho = 1).
  */
 typedef struct chrf_gaussians {
   int32_t n;
@@ -78,9 +79,13 @@ typedef struct chrf_gaussians {
   const float* opacity;
   const float* amp;
   const float* phase;
+  const float* logits;
 } chrf_gaussians;
 
-/* Gradients, same shapes as chrf_gaussians; every array is overwritten. */
+/* Gradients, same shapes as chrf_gaussians; every non-NULL array is
+ * overwritten.  logits (layered plans only, may be NULL) receives the
+ * straight-through gradient dL/drho' = dL/drho * softmax(rho' / 0.001)
+ * (Eq. 12, backward). */
 typedef struct chrf_grads {
   float* means;
   float* log_scales;
@@ -88,6 +93,7 @@ typedef struct chrf_grads {
   float* opacity;
   float* amp;
   float* phase;
+  float* logits;
 } chrf_grads;
 
 /*
@@ -115,6 +121,17 @@ typedef struct chrf_grads {
  *                      (0, 0 selects 16 x 16, the tile of Sec. 4.2)
  *   cols_per_block     columns per workgroup in the column FFT passes
  *                      (0 = choose from the LDS size)
+ *   layered            0: single plane (rho = 1): the rendered field U is
+ *                      propagated to every distance z_k.
+ *                      1: multi-layer hologram (Sec. 4.1, Eqs. 12-16) with
+ *                      n_planes layers, 1..4, at distances Z_l (metres,
+ *                      layer to hologram plane): every Gaussian joins the
+ *                      layer of its largest logit and composites only with
+ *                      that layer (per-layer transmittance and early
+ *                      termination); the hologram is recorded as
+ *                      P = sum_l ASM(U_l; +Z_l) and propagated back to every
+ *                      layer, u_k = ASM(P; -Z_k), I_k = |u_k|^2.  Needs
+ *                      8 x 8 tiles (0, 0 selects them).
  */
 typedef struct chrf_plan_desc {
   int32_t height, width;
@@ -129,7 +146,8 @@ typedef struct chrf_plan_desc {
   float k_sigma, alpha_min, alpha_max, t_min;
   int32_t tile_w, tile_h;
   int32_t cols_per_block;
-  int32_t reserved[7];
+  int32_t layered;
+  int32_t reserved[6];
 } chrf_plan_desc;
 
 /* Named regions of the workspace, for inspection by tests and tools. */
@@ -142,6 +160,11 @@ typedef enum chrf_region {
   CHRF_REGION_LAST = 5,        /* uint32 [n_views][H][W] last included pair + 1 */
   CHRF_REGION_FIELD = 6,       /* complex [n_views][n_lambda][H][W] rendered field */
   CHRF_REGION_GRAD_FIELD = 7,  /* complex [n_views][n_lambda][H][W] dL/dU after backward */
+  /* layered plans only (zero bytes otherwise) */
+  CHRF_REGION_LAYER_FIELDS = 8,  /* complex [n_views][n_lambda][n_planes][H][W] layer fields U_l */
+  CHRF_REGION_LAYER_T_FINAL = 9, /* float [n_views][n_planes][H][W] transmittance of each layer */
+  CHRF_REGION_LAYER_STOP = 10,   /* uint32 [n_views][n_planes][H][W] pair + 1 that ended the layer, ~0 if none */
+  CHRF_REGION_LAYER_GRAD = 11,   /* complex [n_views][n_lambda][n_planes][H][W] dL/dU_l after backward */
   CHRF_REGION_COUNT
 } chrf_region;
 
@@ -167,10 +190,13 @@ chrf_status chrf_plan_region(const chrf_plan* plan, int region, size_t* offset, 
 /*
  * Forward pass: project and cull (Eqs. 2-4, 8), bin into tiles and sort by
  * depth (Algorithm 2), composite front to back (Eqs. 10, 13 with one plane),
- * propagate every wavelength to every distance (Eqs. 7, 14, 16).
+ * propagate every wavelength to every distance (Eqs. 7, 14, 16).  A layered
+ * plan composites every layer (Eq. 13), records the hologram P (Eqs. 14-15)
+ * and propagates it back to the layers (Eq. 16).
  *   cams            device [n_views] chrf_camera
  *   workspace       device, chrf_plan_workspace_bytes() bytes
- *   field_out       complex [n_views][n_lambda][H][W] or NULL
+ *   field_out       complex [n_views][n_lambda][H][W] or NULL: the rendered
+ *                   field U, or for a layered plan the hologram P
  *   prop_out        complex [n_views][n_lambda][n_planes][H][W] or NULL (u)
  *   intensity_out   float   [n_views][n_lambda][n_planes][H][W] or NULL (|u|^2)
  *   target          float   same shape as intensity, or NULL; when given,
@@ -193,7 +219,7 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
  *   prop       complex u saved from chrf_forward (prop_out); required when
  *              dL_dI is given
  *   dL_dprop   complex, same shape as prop, or NULL
- *   dL_dfield  complex [n_views][n_lambda][H][W] or NULL
+ *   dL_dfield  complex [n_views][n_lambda][H][W] or NULL (dL/dP for a layered plan)
  *   grad_scale device float scalar multiplying all of the above, or NULL (1)
  *   out        gradients (overwritten)
  */
@@ -204,6 +230,9 @@ chrf_status chrf_backward(chrf_plan* plan, const chrf_gaussians* g, const chrf_c
 /*
  * Propagation only (Eqs. 14/16 on a given field): field [n_views][n_lambda][H][W]
  * complex -> prop_out (complex, may be NULL) and intensity_out (may be NULL).
+ * For a layered plan this is the inverse propagation of a hologram P to the
+ * layers (distances -Z_k), and chrf_propagate_adjoint, its adjoint, is the
+ * forward recording of layer fields into P (Eqs. 14-15).
  */
 chrf_status chrf_propagate(chrf_plan* plan, const float* field, void* workspace, float* prop_out,
                            float* intensity_out, void* hip_stream);

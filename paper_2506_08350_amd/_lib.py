@@ -27,6 +27,10 @@ REGION_T_FINAL = 4
 REGION_LAST = 5
 REGION_FIELD = 6
 REGION_GRAD_FIELD = 7
+REGION_LAYER_FIELDS = 8
+REGION_LAYER_T_FINAL = 9
+REGION_LAYER_STOP = 10
+REGION_LAYER_GRAD = 11
 
 EXPORTED = [
     "chrf_create", "chrf_destroy", "chrf_last_error", "chrf_version", "chrf_plan_create",
@@ -43,12 +47,12 @@ class Camera(C.Structure):
 
 class Gaussians(C.Structure):
     _fields_ = [("n", C.c_int32), ("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
-                ("opacity", C.c_void_p), ("amp", C.c_void_p), ("phase", C.c_void_p)]
+                ("opacity", C.c_void_p), ("amp", C.c_void_p), ("phase", C.c_void_p), ("logits", C.c_void_p)]
 
 
 class Grads(C.Structure):
     _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
-                ("opacity", C.c_void_p), ("amp", C.c_void_p), ("phase", C.c_void_p)]
+                ("opacity", C.c_void_p), ("amp", C.c_void_p), ("phase", C.c_void_p), ("logits", C.c_void_p)]
 
 
 class PlanDesc(C.Structure):
@@ -58,7 +62,7 @@ class PlanDesc(C.Structure):
                 ("wavelengths", C.c_double * 4), ("distances", C.c_double * 64), ("k_sigma", C.c_float),
                 ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
                 ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("cols_per_block", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("layered", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class ChrfError(RuntimeError):

@@ -15,6 +15,7 @@ from . import _lib
 from ._lib import check
 
 PARAM_NAMES = ("means", "log_scales", "quats", "opacity", "amp", "phase")
+LAYER_LOGITS = "logits"   # [N, layers] plane-assignment logits of a layered renderer
 
 
 def _ptr(t):
@@ -75,7 +76,11 @@ class Renderer:
 
     def __init__(self, height, width, optics: Optics, n_views=1, max_gaussians=1, n_lambda=None,
                  max_pairs=0, k_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
-                 tile=(16, 16), cols_per_block=0, device=0):
+                 tile=None, cols_per_block=0, layered=False, device=0):
+        """layered=True: multi-layer hologram with one layer per entry of
+        optics.distances (the layer-to-hologram distances Z_l); the Gaussians
+        then carry "logits" [N, layers] and the forward's "field" is the
+        recorded hologram P."""
         self.ctx = context(device)
         self.lib = self.ctx.lib
         d = _lib.PlanDesc()
@@ -93,8 +98,12 @@ class Renderer:
         for i, z in enumerate(optics.distances):
             d.distances[i] = float(z)
         d.k_sigma, d.alpha_min, d.alpha_max, d.t_min = k_sigma, alpha_min, alpha_max, t_min
+        if tile is None:
+            tile = (8, 8) if layered else (16, 16)
         d.tile_w, d.tile_h = int(tile[0]), int(tile[1])
         d.cols_per_block = int(cols_per_block)
+        d.layered = 1 if layered else 0
+        self.layered = bool(layered)
         self.desc = d
         h = C.c_void_p()
         check(self.lib.chrf_plan_create(self.ctx.handle, C.byref(d), C.byref(h)))
@@ -144,7 +153,14 @@ class Renderer:
             t = p[k]
             assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous(), k
             setattr(g, k, t.data_ptr())
+        if self.layered:
+            t = p[LAYER_LOGITS]
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.shape == (g.n, self.K)
+            g.logits = t.data_ptr()
         return g
+
+    def param_names(self):
+        return PARAM_NAMES + ((LAYER_LOGITS,) if self.layered else ())
 
     def forward(self, params: dict, cams: torch.Tensor, want_field=True, want_prop=False, want_intensity=True,
                 target=None):
@@ -163,8 +179,10 @@ class Renderer:
 
     def backward(self, params: dict, cams: torch.Tensor, dL_dI=None, prop=None, dL_dprop=None, dL_dfield=None,
                  grad_scale=None):
-        grads = {k: torch.empty_like(params[k]) for k in PARAM_NAMES}
+        grads = {k: torch.empty_like(params[k]) for k in self.param_names()}
         gr = _lib.Grads(*[grads[k].data_ptr() for k in PARAM_NAMES])
+        if self.layered:
+            gr.logits = grads[LAYER_LOGITS].data_ptr()
         g = self._gauss(params)
         check(self.lib.chrf_backward(self.plan, C.byref(g), _ptr(cams), _ptr(self.workspace), _ptr(dL_dI),
                                      _ptr(prop), _ptr(dL_dprop), _ptr(dL_dfield), _ptr(grad_scale),
@@ -224,11 +242,15 @@ class CapturedTrainStep:
 
 class HologramFunction(torch.autograd.Function):
     """Intensities [B, L, K, H, W] of the propagated complex field, differentiable
-    w.r.t. all six Gaussian parameter tensors through the library's backward."""
+    w.r.t. all six Gaussian parameter tensors (and the layer logits of a
+    layered renderer, through the straight-through estimator) by the
+    library's backward."""
 
     @staticmethod
-    def forward(ctx, renderer: Renderer, cams, means, log_scales, quats, opacity, amp, phase):
+    def forward(ctx, renderer: Renderer, cams, means, log_scales, quats, opacity, amp, phase, logits=None):
         params = dict(zip(PARAM_NAMES, (means, log_scales, quats, opacity, amp, phase)))
+        if renderer.layered:
+            params[LAYER_LOGITS] = logits
         params = {k: v.detach().contiguous() for k, v in params.items()}
         out = renderer.forward(params, cams, want_field=False, want_prop=True, want_intensity=True)
         ctx.renderer = renderer
@@ -241,8 +263,9 @@ class HologramFunction(torch.autograd.Function):
     def backward(ctx, dI):
         (prop,) = ctx.saved_tensors
         grads = ctx.renderer.backward(ctx.params, ctx.cams, dL_dI=dI.contiguous(), prop=prop)
-        return (None, None) + tuple(grads[k] for k in PARAM_NAMES)
+        g_logits = grads.get(LAYER_LOGITS)
+        return (None, None) + tuple(grads[k] for k in PARAM_NAMES) + (g_logits,)
 
 
-def render_intensity(renderer: Renderer, cams, means, log_scales, quats, opacity, amp, phase):
-    return HologramFunction.apply(renderer, cams, means, log_scales, quats, opacity, amp, phase)
+def render_intensity(renderer: Renderer, cams, means, log_scales, quats, opacity, amp, phase, logits=None):
+    return HologramFunction.apply(renderer, cams, means, log_scales, quats, opacity, amp, phase, logits)

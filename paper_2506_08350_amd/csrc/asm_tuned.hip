@@ -37,21 +37,39 @@ __device__ inline int opaque_v(int v) {
   return v;
 }
 
-// H_k / (pH pW) at bins (kx, ky), hardware sine/cosine of the residual phase in
-// revolutions (reduced to [-0.5, 0.5] first).
-__device__ inline cpx transfer_fast(const HParam& hp, int kx, int ky, const AsmGeom& g) {
-  const int sx = sbin(kx, g.pW), sy = sbin(ky, g.pH);
-  if (g.band_mode >= 2 && (abs(sx) > hp.kx_max || abs(sy) > hp.ky_max)) return cpx{0.f, 0.f};
-  const long long lhs = (long long)sx * sx * g.pH * g.pH + (long long)sy * sy * g.pW * g.pW;
-  if (lhs > hp.evan_bound) return cpx{0.f, 0.f};
-  const float fx = (float)sx * g.ax, fy = (float)sy * g.ay;
-  const float f2 = fx * fx + fy * fy;
-  const float root = __builtin_sqrtf(fmaxf(hp.inv_lam2 - f2, 0.0f));
-  float rev = hp.frac_rev - hp.z * f2 / (hp.inv_lam + root);
-  rev -= rintf(rev);
-  float s, c;
-  sincospif(2.0f * rev, &s, &c);
-  return cpx{c * g.norm, s * g.norm};
+// Transfer function H_k at the bins of one column.  The column terms are
+// computed once per plane; per element the band tests are integer compares,
+// the residual phase is formed in revolutions with the hardware square root
+// and reciprocal, reduced to [-0.5, 0.5] (exact) and fed to the hardware
+// sine and cosine, which take their argument in revolutions.  The
+// 1 / (pH pW) normalisation is applied by the callers outside the plane loop.
+struct ColFreq {
+  long long cterm;   // sx^2 pH^2 of the evanescent bin test
+  float fx2;         // fx^2
+  bool pass;         // column inside the sampling band limit
+};
+
+__device__ inline ColFreq col_freq(const HParam& hp, int kx, const AsmGeom& g) {
+  const int sx = sbin(kx, g.pW);
+  ColFreq c;
+  c.cterm = (long long)(sx * sx) * (long long)(g.pH * g.pH);
+  const float fx = (float)sx * g.ax;
+  c.fx2 = fx * fx;
+  c.pass = g.band_mode < 2 || abs(sx) <= hp.kx_max;
+  return c;
+}
+
+__device__ inline cpx transfer_col(const HParam& hp, const ColFreq& c, int ky, const AsmGeom& g) {
+  const int sy = sbin(ky, g.pH);
+  const long long lhs = c.cterm + (long long)(sy * sy) * (long long)(g.pW * g.pW);
+  const bool pass = c.pass && (g.band_mode < 2 || abs(sy) <= hp.ky_max) && lhs <= hp.evan_bound;
+  const float fy = (float)sy * g.ay;
+  const float f2 = fy * fy + c.fx2;
+  const float root = __builtin_amdgcn_sqrtf(fmaxf(hp.inv_lam2 - f2, 0.0f));
+  float rev = hp.frac_rev - (hp.z * f2) * __builtin_amdgcn_rcpf(hp.inv_lam + root);
+  rev -= __builtin_rintf(rev);
+  const float cs = __builtin_amdgcn_cosf(rev), sn = __builtin_amdgcn_sinf(rev);
+  return pass ? cpx{cs, sn} : cpx{0.f, 0.f};
 }
 
 template <int N_, int NT, int R1_, int R2, int R3_>
@@ -64,7 +82,11 @@ struct RowT {
   static constexpr int S1 = N / R1, S3 = N / R3;
 };
 
-template <class RT>
+// HALF: the field is half the padded extent (W = pW / 2 for rows, H = pH / 2
+// for columns), so which inputs are zero padding and which outputs are
+// cropped is known at compile time and the corresponding butterfly
+// arithmetic folds away.
+template <class RT, bool HALF>
 __global__ __launch_bounds__(256) void k_rows_forward_t(const float2* __restrict__ in, float2* __restrict__ out,
                                                         AsmGeom g, FftDesc fr) {
   __shared__ cpx lds[lds_padded_size(RT::N)];
@@ -76,7 +98,8 @@ __global__ __launch_bounds__(256) void k_rows_forward_t(const float2* __restrict
 #pragma unroll
     for (int r = 0; r < RT::R1; ++r) {
       const int e = j + r * RT::S1;
-      v1[0][r] = e < g.W ? ldc(src + e) : cpx{0.f, 0.f};
+      const bool live = HALF ? r < RT::R1 / 2 : e < g.W;
+      v1[0][r] = live ? ldc(src + e) : cpx{0.f, 0.f};
     }
   }
   RT::Fwd::run(v1, v3, lds, fr.tw);
@@ -87,7 +110,7 @@ __global__ __launch_bounds__(256) void k_rows_forward_t(const float2* __restrict
   }
 }
 
-template <class RT>
+template <class RT, bool HALF>
 __global__ __launch_bounds__(256) void k_rows_inverse_t(float2* __restrict__ y, AsmGeom g, FftDesc fr,
                                                         float2* __restrict__ prop_out, float* __restrict__ intensity,
                                                         const float* __restrict__ target,
@@ -109,7 +132,7 @@ __global__ __launch_bounds__(256) void k_rows_inverse_t(float2* __restrict__ y, 
 #pragma unroll
   for (int q = 0; q < RT::R3; ++q) {
     const int e = j + q * RT::S3;
-    if (e < g.W) {
+    if (!(HALF && q * RT::S3 >= RT::N / 2) && e < g.W) {
       const cpx u = v3[0][q];
       if (prop_out) stc(prop_out + ob + e, u);
       const float I = u.x * u.x + u.y * u.y;
@@ -139,7 +162,7 @@ __global__ __launch_bounds__(256) void k_rows_inverse_t(float2* __restrict__ y, 
   }
 }
 
-template <class RT>
+template <class RT, bool HALF>
 __global__ __launch_bounds__(256) void k_rows_adjoint_in_t(const float2* __restrict__ prop,
                                                            const float* __restrict__ dL_dI,
                                                            const float2* __restrict__ dL_dprop,
@@ -154,7 +177,7 @@ __global__ __launch_bounds__(256) void k_rows_adjoint_in_t(const float2* __restr
     for (int r = 0; r < RT::R1; ++r) {
       const int e = j + r * RT::S1;
       cpx G{0.f, 0.f};
-      if (e < g.W) {
+      if (HALF ? r < RT::R1 / 2 : e < g.W) {
         if (dL_dI) G = ldc(prop + ob + e) * (2.0f * dL_dI[ob + e]);
         if (dL_dprop) G = G + ldc(dL_dprop + ob + e);
       }
@@ -169,7 +192,7 @@ __global__ __launch_bounds__(256) void k_rows_adjoint_in_t(const float2* __restr
   }
 }
 
-template <class RT>
+template <class RT, bool HALF>
 __global__ __launch_bounds__(256) void k_rows_adjoint_out_t(const float2* __restrict__ w1,
                                                             const float2* __restrict__ dL_dfield,
                                                             float2* __restrict__ grad_field, AsmGeom g, FftDesc fr) {
@@ -187,7 +210,7 @@ __global__ __launch_bounds__(256) void k_rows_adjoint_out_t(const float2* __rest
 #pragma unroll
   for (int q = 0; q < RT::R3; ++q) {
     const int e = j + q * RT::S3;
-    if (e < g.W) {
+    if (!(HALF && q * RT::S3 >= RT::N / 2) && e < g.W) {
       cpx v = v3[0][q];
       if (dL_dfield) v = v + ldc(dL_dfield + ob + e);
       stc(grad_field + ob + e, v);
@@ -231,7 +254,7 @@ __device__ inline const cpx* stage_twiddles(cpx* s_tw, const cpx* __restrict__ t
   return s_tw;
 }
 
-template <int C>
+template <int C, bool HALF>
 __global__ __launch_bounds__(ColT<C>::NT) void k_cols_forward_t(const float2* __restrict__ x1,
                                                                 float2* __restrict__ y, AsmGeom g, FftDesc fc) {
   using CT = ColT<C>;
@@ -252,13 +275,14 @@ __global__ __launch_bounds__(ColT<C>::NT) void k_cols_forward_t(const float2* __
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int n = j + r * (kColN / 16);
-        v1[0][r] = n < g.H ? ldc(x1 + ((size_t)bl * g.H + n) * g.pW + c0 + s) : cpx{0.f, 0.f};
+        const bool live = HALF ? r < 8 : n < g.H;
+        v1[0][r] = live ? ldc(x1 + ((size_t)bl * g.H + n) * g.pW + c0 + s) : cpx{0.f, 0.f};
       }
     }
     CT::Fwd::run(v1, v3, lds, twl);
     if (b < CT::Fwd::B3) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) spec[b + q * CT::Fwd::B3] = v3[0][q];
+      for (int q = 0; q < 9; ++q) spec[b + q * CT::Fwd::B3] = v3[0][q] * g.norm;
     }
   }
   for (int k = 0; k < g.K; ++k) {
@@ -266,9 +290,10 @@ __global__ __launch_bounds__(ColT<C>::NT) void k_cols_forward_t(const float2* __
     const int jj = opaque_v(j), kx = opaque_v(c0 + s);
     cpx w1[1][9], w3[1][16];
     if (b < CT::Inv::B1) {
+      const ColFreq cf = col_freq(hp, kx, g);
 #pragma unroll
       for (int q = 0; q < 9; ++q)
-        w1[0][q] = cmul(spec[b + q * CT::Inv::B1], transfer_fast(hp, kx, jj + q * (kColN / 9), g));
+        w1[0][q] = cmul(spec[b + q * CT::Inv::B1], transfer_col(hp, cf, jj + q * (kColN / 9), g));
     }
     CT::Inv::run(w1, w3, lds, twl, opaque_v(b));
     if (b < CT::Inv::B3) {
@@ -276,13 +301,13 @@ __global__ __launch_bounds__(ColT<C>::NT) void k_cols_forward_t(const float2* __
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int n = jj + q * (kColN / 16);
-        if (n < g.H) stc(yk + (size_t)n * g.pW, w3[0][q]);
+        if (HALF ? q < 8 : n < g.H) stc(yk + (size_t)n * g.pW, w3[0][q]);
       }
     }
   }
 }
 
-template <int C>
+template <int C, bool HALF>
 __global__ __launch_bounds__(ColT<C>::NT) void k_cols_adjoint_t(const float2* __restrict__ z,
                                                                 float2* __restrict__ w1out, AsmGeom g,
                                                                 FftDesc fc) {
@@ -308,17 +333,20 @@ __global__ __launch_bounds__(ColT<C>::NT) void k_cols_adjoint_t(const float2* __
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int n = jj + r * (kColN / 16);
-        v1[0][r] = n < g.H ? ldc(zk + (size_t)n * g.pW) : cpx{0.f, 0.f};
+        v1[0][r] = (HALF ? r < 8 : n < g.H) ? ldc(zk + (size_t)n * g.pW) : cpx{0.f, 0.f};
       }
     }
     CT::Fwd::run(v1, v3, lds, twl, opaque_v(b));
     const HParam hp = g.hp[lam * g.K + k];
     if (b < CT::Fwd::B3) {
+      const ColFreq cf = col_freq(hp, kx, g);
 #pragma unroll
       for (int q = 0; q < 9; ++q)
-        acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_fast(hp, kx, jj + q * (kColN / 9), g));
+        acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_col(hp, cf, jj + q * (kColN / 9), g));
     }
   }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[0][q] = acc[0][q] * g.norm;
   cpx w3[1][16];
   CT::Inv::run(acc, w3, lds, twl);
   if (b < CT::Inv::B3) {
@@ -326,7 +354,7 @@ __global__ __launch_bounds__(ColT<C>::NT) void k_cols_adjoint_t(const float2* __
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int n = j + q * (kColN / 16);
-      if (n < g.H) stc(dst + (size_t)n * g.pW, w3[0][q]);
+      if (HALF ? q < 8 : n < g.H) stc(dst + (size_t)n * g.pW, w3[0][q]);
     }
   }
 }
@@ -336,40 +364,78 @@ using Row3840 = RowT<3840, 256, 16, 16, 15>;
 bool tuned_rows(const AsmGeom& g) { return g.pW == 3840; }
 bool tuned_cols(const AsmGeom& g) { return g.pH == kColN && g.pW % 128 == 0; }
 
+static bool rows_half(const AsmGeom& g) { return 2 * g.W == g.pW; }
+static bool cols_half(const AsmGeom& g) { return 2 * g.H == g.pH; }
+
 hipError_t launch_rows_forward_t(const float2* in, float2* out, const AsmGeom& g, const FftDesc& fr, hipStream_t s) {
-  k_rows_forward_t<Row3840><<<(unsigned)(g.n_bl * g.H), 256, 0, s>>>(in, out, g, fr);
+  const unsigned grid = (unsigned)(g.n_bl * g.H);
+  if (rows_half(g))
+    k_rows_forward_t<Row3840, true><<<grid, 256, 0, s>>>(in, out, g, fr);
+  else
+    k_rows_forward_t<Row3840, false><<<grid, 256, 0, s>>>(in, out, g, fr);
   return hipGetLastError();
 }
 hipError_t launch_rows_inverse_t(float2* y, const AsmGeom& g, const FftDesc& fr, float2* prop_out, float* intensity,
                                  const float* target, float* loss_partial, float grad_coef, bool fuse, hipStream_t s) {
-  k_rows_inverse_t<Row3840><<<(unsigned)(g.n_bl * g.K * g.H), 256, 0, s>>>(y, g, fr, prop_out, intensity, target,
-                                                                            loss_partial, grad_coef, fuse ? 1 : 0);
+  const unsigned grid = (unsigned)(g.n_bl * g.K * g.H);
+  if (rows_half(g))
+    k_rows_inverse_t<Row3840, true><<<grid, 256, 0, s>>>(y, g, fr, prop_out, intensity, target, loss_partial,
+                                                         grad_coef, fuse ? 1 : 0);
+  else
+    k_rows_inverse_t<Row3840, false><<<grid, 256, 0, s>>>(y, g, fr, prop_out, intensity, target, loss_partial,
+                                                          grad_coef, fuse ? 1 : 0);
   return hipGetLastError();
 }
 hipError_t launch_rows_adjoint_in_t(const float2* prop, const float* dL_dI, const float2* dL_dprop, float2* z,
                                     const AsmGeom& g, const FftDesc& fr, hipStream_t s) {
-  k_rows_adjoint_in_t<Row3840><<<(unsigned)(g.n_bl * g.K * g.H), 256, 0, s>>>(prop, dL_dI, dL_dprop, z, g, fr);
+  const unsigned grid = (unsigned)(g.n_bl * g.K * g.H);
+  if (rows_half(g))
+    k_rows_adjoint_in_t<Row3840, true><<<grid, 256, 0, s>>>(prop, dL_dI, dL_dprop, z, g, fr);
+  else
+    k_rows_adjoint_in_t<Row3840, false><<<grid, 256, 0, s>>>(prop, dL_dI, dL_dprop, z, g, fr);
   return hipGetLastError();
 }
 hipError_t launch_rows_adjoint_out_t(const float2* w1, const float2* dL_dfield, float2* grad_field, const AsmGeom& g,
                                      const FftDesc& fr, hipStream_t s) {
-  k_rows_adjoint_out_t<Row3840><<<(unsigned)(g.n_bl * g.H), 256, 0, s>>>(w1, dL_dfield, grad_field, g, fr);
+  const unsigned grid = (unsigned)(g.n_bl * g.H);
+  if (rows_half(g))
+    k_rows_adjoint_out_t<Row3840, true><<<grid, 256, 0, s>>>(w1, dL_dfield, grad_field, g, fr);
+  else
+    k_rows_adjoint_out_t<Row3840, false><<<grid, 256, 0, s>>>(w1, dL_dfield, grad_field, g, fr);
   return hipGetLastError();
 }
+
+template <int C>
+static void cols_forward_c(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, hipStream_t s) {
+  const unsigned grid = (unsigned)(g.n_bl * (g.pW / C));
+  if (cols_half(g))
+    k_cols_forward_t<C, true><<<grid, ColT<C>::NT, 0, s>>>(x1, y, g, fc);
+  else
+    k_cols_forward_t<C, false><<<grid, ColT<C>::NT, 0, s>>>(x1, y, g, fc);
+}
+template <int C>
+static void cols_adjoint_c(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, hipStream_t s) {
+  const unsigned grid = (unsigned)(g.n_bl * (g.pW / C));
+  if (cols_half(g))
+    k_cols_adjoint_t<C, true><<<grid, ColT<C>::NT, 0, s>>>(z, w1, g, fc);
+  else
+    k_cols_adjoint_t<C, false><<<grid, ColT<C>::NT, 0, s>>>(z, w1, g, fc);
+}
+
 hipError_t launch_cols_forward_t(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, int C,
                                  hipStream_t s) {
   if (C == 2)
-    k_cols_forward_t<2><<<(unsigned)(g.n_bl * (g.pW / 2)), ColT<2>::NT, 0, s>>>(x1, y, g, fc);
+    cols_forward_c<2>(x1, y, g, fc, s);
   else
-    k_cols_forward_t<4><<<(unsigned)(g.n_bl * (g.pW / 4)), ColT<4>::NT, 0, s>>>(x1, y, g, fc);
+    cols_forward_c<4>(x1, y, g, fc, s);
   return hipGetLastError();
 }
 hipError_t launch_cols_adjoint_t(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, int C,
                                  hipStream_t s) {
   if (C == 2)
-    k_cols_adjoint_t<2><<<(unsigned)(g.n_bl * (g.pW / 2)), ColT<2>::NT, 0, s>>>(z, w1, g, fc);
+    cols_adjoint_c<2>(z, w1, g, fc, s);
   else
-    k_cols_adjoint_t<4><<<(unsigned)(g.n_bl * (g.pW / 4)), ColT<4>::NT, 0, s>>>(z, w1, g, fc);
+    cols_adjoint_c<4>(z, w1, g, fc, s);
   return hipGetLastError();
 }
 

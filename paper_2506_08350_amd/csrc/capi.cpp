@@ -36,7 +36,9 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 enum Reg {
   R_V, R_G0, R_G1, R_RECT, R_GKEY, R_GKEY_ALT, R_GVAL, R_GVAL_ALT, R_GCOUNT, R_CNT_SORTED, R_OFFSETS, R_SCAN_TMP,
   R_HIST, R_PKEY, R_PKEY_ALT, R_PVAL, R_PVAL_ALT, R_RANGES, R_STATUS, R_TFINAL, R_LAST, R_FIELD, R_X1, R_Y,
-  R_GRAD_FIELD, R_GRAD2D, R_LOSS_PARTIAL, R_NUM
+  R_GRAD_FIELD, R_GRAD2D, R_LOSS_PARTIAL,
+  R_LAYER_OF, R_LFIELD, R_LTFINAL, R_LSTOP, R_LGRAD,   // layered plans only
+  R_NUM
 };
 
 struct TimingRec {
@@ -62,6 +64,7 @@ struct chrf_plan {
   int64_t cap = 0;
   int cols_per_block = 0;
   int g2 = 0;
+  bool layered = false;
   int gsort_bits = 0, psort_bits = 0;
   bool gsort_alt = false, psort_alt = false;
   FftDesc frow{}, fcol{};
@@ -226,8 +229,11 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
     if (!std::isfinite(d.distances[k])) return fail(CHRF_EINVAL, "plan: distances must be finite");
   if (!(d.k_sigma > 0) || !(d.alpha_max > 0 && d.alpha_max <= 1) || !(d.alpha_min >= 0) || !(d.t_min >= 0))
     return fail(CHRF_EINVAL, "plan: thresholds out of range");
+  if (d.layered != 0 && d.layered != 1) return fail(CHRF_EINVAL, "plan: layered must be 0 or 1");
+  if (d.layered && d.n_planes > kMaxLayers) return fail(CHRF_EUNSUPPORTED, "plan: a layered plan takes 1..4 layers");
   int tw = d.tile_w, th = d.tile_h;
-  if (tw == 0 && th == 0) tw = th = 16;
+  if (tw == 0 && th == 0) tw = th = d.layered ? 8 : 16;
+  if (d.layered && (tw != 8 || th != 8)) return fail(CHRF_EUNSUPPORTED, "plan: a layered plan needs 8 x 8 tiles");
   if (tw <= 0 || th <= 0 || tw % 8 || th % 8 || (tw * th != 64 && tw * th != 128 && tw * th != 256))
     return fail(CHRF_EINVAL, "plan: tile_w, tile_h must be multiples of 8 with tile_w * tile_h in {64, 128, 256}");
 
@@ -248,7 +254,10 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   p->tiles_x = (d.width + tw - 1) / tw;
   p->tiles_y = (d.height + th - 1) / th;
   p->n_tiles = p->tiles_x * p->tiles_y;
-  p->g2 = 16;   // 6 + 2 * n_lambda values, padded to one 64-byte row per (view, Gaussian)
+  p->layered = d.layered != 0;
+  // per-(view, Gaussian) gradient row: 6 + 2 n_lambda values (+ n_layers), padded
+  // to 16 floats (one 64-byte row) or the next multiple of 4
+  p->g2 = std::max(16, (6 + 2 * p->L + (p->layered ? p->K : 0) + 3) & ~3);
   int64_t cap = d.max_pairs;
   if (cap <= 0) {
     cap = (int64_t)128 * p->B * (int64_t)(p->N > 0 ? p->N : 1);
@@ -294,7 +303,9 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   const double dfx = 1.0 / (p->pW * d.pitch), dfy = 1.0 / (p->pH * d.pitch);
   for (int l = 0; l < p->L; ++l)
     for (int k = 0; k < p->K; ++k) {
-      const double lam = d.wavelengths[l], z = d.distances[k];
+      // a layered plan propagates the hologram back to its layers (-Z_k);
+      // the recording (+Z_l) is the adjoint of that map
+      const double lam = d.wavelengths[l], z = p->layered ? -d.distances[k] : d.distances[k];
       HParam& h = hp[l * p->K + k];
       const double zl = z / lam;
       h.frac_rev = (float)(zl - std::floor(zl));
@@ -322,10 +333,6 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   p->gsort_bits = 32 + bits_for(p->B - 1);
   p->psort_bits = bits_for((int64_t)p->B * p->n_tiles - 1);
   p->gsort_alt = ((p->gsort_bits + 7) / 8) % 2 == 1;
-  // one scan covers the histograms of every pass, so passes * count must fit 32 bits
-  if ((int64_t)((p->psort_bits + 7) / 8) * cap >= ((int64_t)1 << 32) ||
-      (int64_t)((p->gsort_bits + 7) / 8) * p->B * std::max(p->N, 1) >= ((int64_t)1 << 32))
-    return bad(fail(CHRF_EUNSUPPORTED, "plan: pair capacity too large for the 32-bit sort offsets"));
   p->psort_alt = ((p->psort_bits + 7) / 8) % 2 == 1;
   // workspace layout
   const int64_t BN = (int64_t)p->B * (p->N > 0 ? p->N : 1);
@@ -354,6 +361,11 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   sz[R_GRAD_FIELD] = sizeof(float2) * pix * p->L;
   sz[R_GRAD2D] = sizeof(float) * BN * p->g2;
   sz[R_LOSS_PARTIAL] = sizeof(float) * (size_t)p->B * p->L * p->K * p->H;
+  const size_t lpix = p->layered ? (size_t)pix * p->K : 0;
+  sz[R_LAYER_OF] = p->layered ? (size_t)std::max(p->N, 1) : 0;
+  sz[R_LFIELD] = sz[R_LGRAD] = sizeof(float2) * lpix * p->L;
+  sz[R_LTFINAL] = sizeof(float) * lpix;
+  sz[R_LSTOP] = sizeof(uint32_t) * lpix;
   size_t o = 0;
   for (int r = 0; r < R_NUM; ++r) {
     p->off[r] = o;
@@ -390,6 +402,10 @@ chrf_status chrf_plan_region(const chrf_plan* p, int region, size_t* offset, siz
     case CHRF_REGION_LAST: r = R_LAST; break;
     case CHRF_REGION_FIELD: r = R_FIELD; break;
     case CHRF_REGION_GRAD_FIELD: r = R_GRAD_FIELD; break;
+    case CHRF_REGION_LAYER_FIELDS: r = R_LFIELD; break;
+    case CHRF_REGION_LAYER_T_FINAL: r = R_LTFINAL; break;
+    case CHRF_REGION_LAYER_STOP: r = R_LSTOP; break;
+    case CHRF_REGION_LAYER_GRAD: r = R_LGRAD; break;
     default: return fail(CHRF_EINVAL, "chrf_plan_region: unknown region");
   }
   *offset = p->off[r];
@@ -402,6 +418,7 @@ static chrf_status check_gaussians(const chrf_plan* p, const chrf_gaussians* g) 
   if (g->n < 0 || g->n > p->N) return fail(CHRF_EINVAL, "gaussians: n exceeds the plan's max_gaussians");
   if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity || !g->amp || !g->phase))
     return fail(CHRF_EINVAL, "gaussians: NULL array");
+  if (p->layered && g->n > 0 && !g->logits) return fail(CHRF_EINVAL, "gaussians: a layered plan needs logits");
   return CHRF_OK;
 }
 
@@ -505,10 +522,30 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
   ra.alpha_min = plan->d.alpha_min;
   ra.alpha_max = plan->d.alpha_max;
   ra.t_min = plan->d.t_min;
-  ra.field = field;
-  ra.t_final = at<float>(plan, ws, R_TFINAL);
   ra.last = at<uint32_t>(plan, ws, R_LAST);
-  RUN("raster_forward", launch_raster_forward(ra, s));
+  if (plan->layered) {
+    const AsmGeom geo = geom(plan);
+    uint8_t* layer_of = at<uint8_t>(plan, ws, R_LAYER_OF);
+    float2* lfield = at<float2>(plan, ws, R_LFIELD);
+    RUN("assign_layers", launch_assign_layers(g->logits, g->n, plan->K, layer_of, s));
+    ra.layer_of = layer_of;
+    ra.n_layers = plan->K;
+    ra.layer_stop = at<uint32_t>(plan, ws, R_LSTOP);
+    ra.field = lfield;
+    ra.t_final = at<float>(plan, ws, R_LTFINAL);
+    RUN("raster_layers_forward", launch_raster_layers_forward(ra, s));
+    // forward recording P = sum_l ASM(U_l; +Z_l): the adjoint of the inverse
+    // propagation the plan's transfer functions describe
+    float2* y = at<float2>(plan, ws, R_Y);
+    float2* x1 = at<float2>(plan, ws, R_X1);
+    RUN("record_rows_in", launch_rows_adjoint_in(nullptr, nullptr, lfield, y, geo, plan->frow, s));
+    RUN("record_cols", launch_cols_adjoint(y, x1, geo, plan->fcol, plan->cols_per_block, s));
+    RUN("record_rows_out", launch_rows_adjoint_out(x1, nullptr, field, geo, plan->frow, s));
+  } else {
+    ra.field = field;
+    ra.t_final = at<float>(plan, ws, R_TFINAL);
+    RUN("raster_forward", launch_raster_forward(ra, s));
+  }
 
   st = asm_forward(plan, field, ws, prop_out, intensity_out, target, s);
   if (st != CHRF_OK) return st;
@@ -549,6 +586,18 @@ chrf_status chrf_backward(chrf_plan* plan, const chrf_gaussians* g, const chrf_c
                                                     plan->frow, s));
     grad_field = gf;
   }
+  if (plan->layered) {
+    // dL/dU_l = ASM(dL/dP; -Z_l): the adjoint of the recording
+    const double numel = (double)plan->B * plan->L * plan->K * plan->H * plan->W;
+    float2* lgrad = at<float2>(plan, ws, R_LGRAD);
+    RUN("layer_grad_rows", launch_rows_forward(grad_field, x1, geo, plan->frow, s));
+    RUN("layer_grad_cols", launch_cols_forward(x1, y, geo, plan->fcol, plan->cols_per_block, s));
+    RUN("layer_grad_rows_inv", launch_rows_inverse(y, geo, plan->frow, lgrad, nullptr, nullptr,
+                                                   at<float>(plan, ws, R_LOSS_PARTIAL), (float)(2.0 / numel),
+                                                   false, s));
+    plan->fused_ready = false;   // Y now holds the layer gradients' spectra
+    grad_field = lgrad;
+  }
   float* grad2d = at<float>(plan, ws, R_GRAD2D);
   RUN("grad2d_clear", launch_fill_f32(grad2d, 0.f, (int64_t)plan->B * Nst * plan->g2, s));
   size_t o, b;
@@ -579,11 +628,23 @@ chrf_status chrf_backward(chrf_plan* plan, const chrf_gaussians* g, const chrf_c
   ra.grad_scale = grad_scale;
   ra.grad2d = grad2d;
   ra.g2stride = plan->g2;
-  RUN("raster_backward", launch_raster_backward(ra, s));
+  if (plan->layered) {
+    ra.layer_of = at<uint8_t>(plan, ws, R_LAYER_OF);
+    ra.n_layers = plan->K;
+    ra.layer_stop = at<uint32_t>(plan, ws, R_LSTOP);
+    ra.t_final = at<float>(plan, ws, R_LTFINAL);
+    RUN("raster_layers_backward", launch_raster_layers_backward(ra, s));
+  } else {
+    RUN("raster_backward", launch_raster_backward(ra, s));
+  }
   RUN("project_backward",
       launch_project_backward(g->means, g->log_scales, g->quats, g->amp, g->phase, reinterpret_cast<const Cam*>(cams),
                               g->n, Nst, plan->B, plan->L, at<uint32_t>(plan, ws, R_GCOUNT), grad2d, plan->g2,
                               out->means, out->log_scales, out->quats, out->opacity, out->amp, out->phase, s));
+  if (plan->layered && out->logits)
+    RUN("logits_backward", launch_logits_backward(g->logits, grad2d, plan->g2, 6 + 2 * plan->L,
+                                                  at<uint32_t>(plan, ws, R_GCOUNT), g->n, Nst, plan->B, plan->K,
+                                                  1e-3f, out->logits, s));
   return CHRF_OK;
 }
 

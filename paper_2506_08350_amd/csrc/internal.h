@@ -130,9 +130,22 @@ struct RasterArgs {
   const float* grad_scale;  // device scalar or null
   float* grad2d;            // [B * n_stride][g2stride]
   int g2stride;
+  // multi-layer mode: field, grad_field [B][L][n_layers][H][W], t_final [B][n_layers][H][W]
+  const uint8_t* layer_of;  // [n_stride] hard layer of each Gaussian
+  int n_layers;
+  uint32_t* layer_stop;     // [B][n_layers][H][W]: pair index + 1 that ended the layer, ~0u if none
 };
 hipError_t launch_raster_forward(const RasterArgs& a, hipStream_t s);
 hipError_t launch_raster_backward(const RasterArgs& a, hipStream_t s);
+
+// Multi-layer mode (hard plane assignment).
+constexpr int kMaxLayers = 4;
+hipError_t launch_assign_layers(const float* logits, int n, int n_layers, uint8_t* layer_of, hipStream_t s);
+hipError_t launch_raster_layers_forward(const RasterArgs& a, hipStream_t s);
+hipError_t launch_raster_layers_backward(const RasterArgs& a, hipStream_t s);
+hipError_t launch_logits_backward(const float* logits, const float* grad2d, int g2stride, int rho_offset,
+                                  const uint32_t* count, int n, int n_stride, int n_views, int n_layers, float tau,
+                                  float* d_logits, hipStream_t s);
 
 // Angular-spectrum passes (layout: rows of [bl][r] are contiguous complex64)
 hipError_t launch_rows_forward(const float2* in, float2* out, const AsmGeom& g, const FftDesc& fr, hipStream_t s);

@@ -12,79 +12,12 @@
 // Backward per pixel, from its last contributor down:  T_g = T / (1 - a),
 //   dL/da = T_g sum_l Re(conj(G_l)(v_l - B_l)),  B_l <- a v_l + (1 - a) B_l,
 // and the per-pair gradients (d mu, d conic, d opacity, d v) are summed over a
-// lane's pixels, then over the wave with DPP row shifts/broadcasts, and added
-// to the per-(view, Gaussian) accumulators with one atomic per value.
-#include "internal.h"
+// lane's pixels, then over the wave (32- and 16-lane swaps, then DPP row
+// shifts), and added to the per-(view, Gaussian) accumulators with one atomic
+// per value.
+#include "raster_common.h"
 
 namespace chrf {
-
-// One wave (64 lanes) per tile.  Lane l sits at (l % 8, l / 8) of an 8x8
-// block and owns the pixel at that position in each of the tile's
-// PPT = tile_w * tile_h / 64 blocks, so per-pair costs that do not depend on
-// the pixel (record loads, the gradient reduction over the wave) are shared by
-// PPT pixels.  Records are staged in LDS in batches of kBatch pairs.
-constexpr int kLanes = 64;
-constexpr int kBatch = 128;
-
-struct TileGeom {
-  int view, tx, ty;
-};
-
-__device__ inline TileGeom tile_of(const RasterArgs& a) {
-  const int n_tiles = a.tiles_x * a.tiles_y;
-  TileGeom t;
-  t.view = blockIdx.x / n_tiles;
-  const int tile = blockIdx.x % n_tiles;
-  t.tx = tile % a.tiles_x;
-  t.ty = tile / a.tiles_x;
-  return t;
-}
-
-// Origin of the 8x8 block that holds a lane's p-th pixel (the same for all lanes).
-__device__ inline void block_of(const RasterArgs& a, const TileGeom& t, int p, int& bx, int& by) {
-  const int bpr = a.tile_w >> 3;
-  bx = t.tx * a.tile_w + (p % bpr) * 8;
-  by = t.ty * a.tile_h + (p / bpr) * 8;
-}
-
-// Does the support rectangle rc = (c0, c1 - c0, r0, r1 - r0) reach the 8x8
-// block at (bx, by)?  Uniform over the wave, so a miss skips the block's
-// pixel work for every lane.
-__device__ inline bool rect_hits_block(const int4& rc, int bx, int by) {
-  return rc.x <= bx + 7 && bx <= rc.x + rc.y && rc.z <= by + 7 && by <= rc.z + rc.w;
-}
-
-template <int PPT>
-__device__ inline void pixel_of(const RasterArgs& a, const TileGeom& t, int p, int& px, int& py) {
-  const int lane = threadIdx.x;
-  const int bpr = a.tile_w >> 3;   // 8x8 blocks per tile row
-  px = t.tx * a.tile_w + (p % bpr) * 8 + (lane & 7);
-  py = t.ty * a.tile_h + (p / bpr) * 8 + (lane >> 3);
-}
-
-template <int NL>
-struct Stage {
-  float4 g0[kBatch];
-  float4 g1[kBatch];
-  int4 rc[kBatch];
-  float2 v[NL][kBatch];
-  uint32_t rid[kBatch];
-};
-
-template <int NL>
-__device__ inline void stage_records(Stage<NL>& st, const RasterArgs& a, uint32_t first, int cnt, bool reverse) {
-  for (int i = threadIdx.x; i < cnt; i += kLanes) {
-    const uint32_t idx = reverse ? first - i : first + i;
-    const uint32_t rid = a.pair_val[idx];
-    st.rid[i] = rid;
-    st.g0[i] = a.rec_g0[rid];
-    st.g1[i] = a.rec_g1[rid];
-    st.rc[i] = a.rec_rect[rid];
-    const uint32_t g = rid % (uint32_t)a.n_stride;
-#pragma unroll
-    for (int l = 0; l < NL; ++l) st.v[l][i] = a.v[(size_t)g * NL + l];
-  }
-}
 
 template <int NL, int PPT>
 __global__ __launch_bounds__(kLanes) void k_raster_fwd(RasterArgs a) {
@@ -159,20 +92,10 @@ __global__ __launch_bounds__(kLanes) void k_raster_fwd(RasterArgs a) {
   }
 }
 
-// Sum over the 64 lanes; the result is valid in lane 63.
-__device__ inline float wave_sum_to_last(float v) {
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));  // row_shr:1
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, true));  // row_shr:2
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, true));  // row_shr:4
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, true));  // row_shr:8
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false)); // row_bcast:15
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false)); // row_bcast:31
-  return v;
-}
-
 template <int NL, int PPT>
 __global__ __launch_bounds__(kLanes) void k_raster_bwd(RasterArgs a) {
   constexpr int G2 = 6 + 2 * NL;
+  constexpr int G2P = (G2 + 3) & ~3;   // padded for the row-wise wave reduction
   __shared__ Stage<NL> st;
   __shared__ float s_grad[kBatch][G2];
   const TileGeom t = tile_of(a);
@@ -228,9 +151,9 @@ __global__ __launch_bounds__(kLanes) void k_raster_bwd(RasterArgs a) {
       const float4 g0 = st.g0[j];
       const float4 g1 = st.g1[j];
       const int4 rc = st.rc[j];
-      float gr[G2];
+      float gr[G2P];
 #pragma unroll
-      for (int c = 0; c < G2; ++c) gr[c] = 0.f;
+      for (int c = 0; c < G2P; ++c) gr[c] = 0.f;
       bool any = false;
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
@@ -270,10 +193,14 @@ __global__ __launch_bounds__(kLanes) void k_raster_bwd(RasterArgs a) {
         }
       }
       if (__ballot(any) != 0ull) {
+        wave_sums_by_row<G2P>(gr);
+        if ((lane & 15) == 15) {
+          const int row = lane >> 4;
 #pragma unroll
-        for (int c = 0; c < G2; ++c) {
-          const float sum = wave_sum_to_last(gr[c]);
-          if (lane == 63) s_grad[j][c] = sum;
+          for (int k = 0; k < G2P / 4; ++k) {
+            const int c = k + row * (G2P / 4);
+            if (c < G2) s_grad[j][c] = gr[k];
+          }
         }
       }
     }

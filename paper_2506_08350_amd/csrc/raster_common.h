@@ -1,0 +1,112 @@
+// Tile walk helpers shared by the single-plane and the multi-layer raster
+// kernels: tile and pixel geometry, LDS staging of Gaussian records, and the
+// wave reductions of the backward passes.
+#pragma once
+#include "internal.h"
+
+namespace chrf {
+
+// One wave (64 lanes) per tile.  Lane l sits at (l % 8, l / 8) of an 8x8
+// block and owns the pixel at that position in each of the tile's
+// PPT = tile_w * tile_h / 64 blocks, so per-pair costs that do not depend on
+// the pixel (record loads, the gradient reduction over the wave) are shared by
+// PPT pixels.  Records are staged in LDS in batches of kBatch pairs.
+constexpr int kLanes = 64;
+constexpr int kBatch = 128;
+
+struct TileGeom {
+  int view, tx, ty;
+};
+
+__device__ inline TileGeom tile_of(const RasterArgs& a) {
+  const int n_tiles = a.tiles_x * a.tiles_y;
+  TileGeom t;
+  t.view = blockIdx.x / n_tiles;
+  const int tile = blockIdx.x % n_tiles;
+  t.tx = tile % a.tiles_x;
+  t.ty = tile / a.tiles_x;
+  return t;
+}
+
+// Origin of the 8x8 block that holds a lane's p-th pixel (the same for all lanes).
+__device__ inline void block_of(const RasterArgs& a, const TileGeom& t, int p, int& bx, int& by) {
+  const int bpr = a.tile_w >> 3;
+  bx = t.tx * a.tile_w + (p % bpr) * 8;
+  by = t.ty * a.tile_h + (p / bpr) * 8;
+}
+
+// Does the support rectangle rc = (c0, c1 - c0, r0, r1 - r0) reach the 8x8
+// block at (bx, by)?  Uniform over the wave, so a miss skips the block's
+// pixel work for every lane.
+__device__ inline bool rect_hits_block(const int4& rc, int bx, int by) {
+  return rc.x <= bx + 7 && bx <= rc.x + rc.y && rc.z <= by + 7 && by <= rc.z + rc.w;
+}
+
+template <int PPT>
+__device__ inline void pixel_of(const RasterArgs& a, const TileGeom& t, int p, int& px, int& py) {
+  const int lane = threadIdx.x;
+  const int bpr = a.tile_w >> 3;   // 8x8 blocks per tile row
+  px = t.tx * a.tile_w + (p % bpr) * 8 + (lane & 7);
+  py = t.ty * a.tile_h + (p / bpr) * 8 + (lane >> 3);
+}
+
+template <int NL>
+struct Stage {
+  float4 g0[kBatch];
+  float4 g1[kBatch];
+  int4 rc[kBatch];
+  float2 v[NL][kBatch];
+  uint32_t rid[kBatch];
+};
+
+template <int NL>
+__device__ inline void stage_records(Stage<NL>& st, const RasterArgs& a, uint32_t first, int cnt, bool reverse) {
+  for (int i = threadIdx.x; i < cnt; i += kLanes) {
+    const uint32_t idx = reverse ? first - i : first + i;
+    const uint32_t rid = a.pair_val[idx];
+    st.rid[i] = rid;
+    st.g0[i] = a.rec_g0[rid];
+    st.g1[i] = a.rec_g1[rid];
+    st.rc[i] = a.rec_rect[rid];
+    const uint32_t g = rid % (uint32_t)a.n_stride;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) st.v[l][i] = a.v[(size_t)g * NL + l];
+  }
+}
+
+// Sums over the 16 lanes of each row; the result is valid in the row's last lane.
+__device__ inline float row_sum_to_last(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));  // row_shr:1
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, true));  // row_shr:2
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, true));  // row_shr:4
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, true));  // row_shr:8
+  return v;
+}
+
+// Wave sums of M values (M a multiple of 4) by recursive halving.  The
+// 32-lane swap exchanges the upper half of one value with the lower half of
+// another, so one add leaves half the values summed over lane pairs (l, l+32);
+// the 16-lane swap does the same between neighbouring rows.  Afterwards row r
+// (lanes 16r..16r+15) holds values k + r*M/4, k < M/4, each summed over four
+// lanes; a row reduction finishes them.  Result: lane 16r+15 holds the wave
+// sum of value k + r*M/4 in v[k].
+template <int M>
+__device__ inline void wave_sums_by_row(float (&v)[M]) {
+  static_assert(M % 4 == 0, "pad the value count to a multiple of 4");
+#pragma unroll
+  for (int k = 0; k < M / 2; ++k) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(v[k + M / 2]), false,
+                                                    false);
+    v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int k = 0; k < M / 4; ++k) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[k]), __float_as_uint(v[k + M / 4]), false,
+                                                    false);
+    v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int k = 0; k < M / 4; ++k) v[k] = row_sum_to_last(v[k]);
+}
+
+}  // namespace chrf

@@ -1,0 +1,341 @@
+// Multi-layer complex compositing with hard plane assignment (Sec. 4.1,
+// Eqs. 12-13; per-layer transmittance of Supplementary D) and its backward,
+// including the straight-through gradient of the layer logits.
+//
+// Each Gaussian belongs to the layer of its largest logit (ties: lowest
+// index).  A pixel walks its tile's pair list once, front to back; a Gaussian
+// adds to and attenuates only its own layer:
+//   U_q += v a T_q,  T_q *= 1 - a,  layer q stops after T_q < T_min.
+// The walk ends when every layer has stopped.
+//
+// Backward, in reverse from where the walk ended.  For every layer q that had
+// not stopped before the pair, with T_q the transmittance of layer q in front
+// of the Gaussian and B_q the field of layer q behind it,
+//   s_q = T_q sum_l Re(conj(G_ql) (v_l - B_ql)),   dL/drho_q = a s_q,
+// which for the Gaussian's own layer is also dL/da; there T_q is recovered as
+// T_q / (1 - a) and B_q <- a v + (1 - a) B_q.  The per-pair gradient vector
+// (d mu, d conic, d opacity, d v, d rho) is reduced over the wave and added
+// to the per-(view, Gaussian) accumulators; k_logits_backward then applies
+// the straight-through weights softmax(logits / tau).
+//
+// One wave per 8x8 tile, one pixel per lane: the per-layer state (T, B, G per
+// wavelength) stays in registers.
+#include "raster_common.h"
+
+namespace chrf {
+
+__global__ void k_assign_layers(const float* __restrict__ logits, int n, int nlay, uint8_t* __restrict__ layer_of) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const float* r = logits + (size_t)g * nlay;
+  int best = 0;
+  float bv = r[0];
+  for (int q = 1; q < nlay; ++q)
+    if (r[q] > bv) {
+      bv = r[q];
+      best = q;
+    }
+  layer_of[g] = (uint8_t)best;
+}
+
+template <int NL>
+struct StageL {
+  Stage<NL> s;
+  int lay[kBatch];
+};
+
+template <int NL>
+__device__ inline void stage_records_l(StageL<NL>& st, const RasterArgs& a, uint32_t first, int cnt, bool reverse) {
+  stage_records<NL>(st.s, a, first, cnt, reverse);
+  for (int i = threadIdx.x; i < cnt; i += kLanes) {
+    const uint32_t idx = reverse ? first - i : first + i;
+    const uint32_t g = a.pair_val[idx] % (uint32_t)a.n_stride;
+    st.lay[i] = a.layer_of[g];
+  }
+}
+
+template <int NL, int NLAY>
+__global__ __launch_bounds__(kLanes) void k_raster_layers_fwd(RasterArgs a) {
+  __shared__ StageL<NL> st;
+  const TileGeom t = tile_of(a);
+  int px, py;
+  pixel_of<1>(a, t, 0, px, py);
+  const int bx = t.tx * 8, by = t.ty * 8;
+  const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
+  const bool inside = px < a.width && py < a.height;
+  float T[NLAY];
+  float2 U[NLAY][NL];
+  uint32_t stop[NLAY];
+#pragma unroll
+  for (int q = 0; q < NLAY; ++q) {
+    T[q] = 1.0f;
+    stop[q] = ~0u;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) U[q][l] = make_float2(0.f, 0.f);
+  }
+  uint32_t live = inside ? (1u << a.n_layers) - 1u : 0u;   // layers still accepting contributions
+  const uint2 rg = a.ranges[blockIdx.x];
+  uint32_t walk_end = inside ? rg.y : 0u;
+  const float half_k2 = 0.5f * a.k_sigma * a.k_sigma;
+  for (uint32_t start = rg.x; start < rg.y; start += kBatch) {
+    if (__all(live == 0u)) break;
+    const int cnt = (int)min(rg.y - start, (uint32_t)kBatch);
+    __syncthreads();
+    stage_records_l<NL>(st, a, start, cnt, false);
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const int4 rc = st.s.rc[j];
+      if (!rect_hits_block(rc, bx, by)) continue;
+      const int lay = __builtin_amdgcn_readfirstlane(st.lay[j]);
+      if (!((live >> lay) & 1u)) continue;
+      const float4 g0 = st.s.g0[j];
+      const float4 g1 = st.s.g1[j];
+      const float dx = pxf - g0.x, dy = pyf - g0.y;
+      const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
+      const bool in_rect = (unsigned)(px - rc.x) <= (unsigned)rc.y && (unsigned)(py - rc.z) <= (unsigned)rc.w;
+      const float aval = fminf(a.alpha_max, g1.y * __expf(-power));
+      if (in_rect && power <= half_k2 && aval >= a.alpha_min) {
+#pragma unroll
+        for (int q = 0; q < NLAY; ++q) {
+          if (q != lay) continue;   // wave-uniform
+          const float wgt = aval * T[q];
+#pragma unroll
+          for (int l = 0; l < NL; ++l) {
+            const float2 v = st.s.v[l][j];
+            U[q][l].x += v.x * wgt;
+            U[q][l].y += v.y * wgt;
+          }
+          T[q] *= 1.0f - aval;
+          if (T[q] < a.t_min) {
+            stop[q] = start + j + 1;
+            live &= ~(1u << q);
+            if (live == 0u) walk_end = start + j + 1;
+          }
+        }
+      }
+    }
+  }
+  if (!inside) return;
+  const size_t plane = (size_t)a.height * a.width;
+  const size_t pix = (size_t)py * a.width + px;
+#pragma unroll
+  for (int q = 0; q < NLAY; ++q) {
+    if (q >= a.n_layers) break;
+    const size_t lp = ((size_t)t.view * a.n_layers + q) * plane + pix;
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+      a.field[(((size_t)t.view * NL + l) * a.n_layers + q) * plane + pix] = U[q][l];
+    a.t_final[lp] = T[q];
+    a.layer_stop[lp] = stop[q];
+  }
+  a.last[(size_t)t.view * plane + pix] = walk_end;
+}
+
+template <int NL, int NLAY>
+__global__ __launch_bounds__(kLanes) void k_raster_layers_bwd(RasterArgs a) {
+  constexpr int G2 = 6 + 2 * NL + NLAY;
+  constexpr int G2P = (G2 + 3) & ~3;
+  __shared__ StageL<NL> st;
+  __shared__ float s_grad[kBatch][G2];
+  const TileGeom t = tile_of(a);
+  const int lane = threadIdx.x;
+  int px, py;
+  pixel_of<1>(a, t, 0, px, py);
+  const int bx = t.tx * 8, by = t.ty * 8;
+  const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
+  const bool inside = px < a.width && py < a.height;
+  const float scale = a.grad_scale ? *a.grad_scale : 1.0f;
+  const size_t plane = (size_t)a.height * a.width;
+  const size_t pix = (size_t)py * a.width + px;
+  float T[NLAY];
+  uint32_t stop[NLAY];
+  float2 G[NLAY][NL], Bacc[NLAY][NL];
+  uint32_t mylast = 0;
+#pragma unroll
+  for (int q = 0; q < NLAY; ++q) {
+    T[q] = 1.0f;
+    stop[q] = 0u;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      G[q][l] = make_float2(0.f, 0.f);
+      Bacc[q][l] = make_float2(0.f, 0.f);
+    }
+    if (inside && q < a.n_layers) {
+      const size_t lp = ((size_t)t.view * a.n_layers + q) * plane + pix;
+      T[q] = a.t_final[lp];
+      stop[q] = a.layer_stop[lp];
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        const float2 gg = a.grad_field[(((size_t)t.view * NL + l) * a.n_layers + q) * plane + pix];
+        G[q][l] = make_float2(gg.x * scale, gg.y * scale);
+      }
+    }
+  }
+  if (inside) mylast = a.last[(size_t)t.view * plane + pix];
+  uint32_t tile_last = mylast;
+  for (int off = 32; off > 0; off >>= 1) tile_last = max(tile_last, (uint32_t)__shfl_xor((int)tile_last, off, 64));
+  const uint2 rg = a.ranges[blockIdx.x];
+  const float half_k2 = 0.5f * a.k_sigma * a.k_sigma;
+  for (int i = lane; i < kBatch * G2; i += kLanes) (&s_grad[0][0])[i] = 0.f;
+
+  for (uint32_t top = tile_last; top > rg.x;) {
+    const int cnt = (int)min(top - rg.x, (uint32_t)kBatch);
+    __syncthreads();
+    stage_records_l<NL>(st, a, top - 1, cnt, true);   // st[j] is the j-th pair from the back
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const int4 rc = st.s.rc[j];
+      if (!rect_hits_block(rc, bx, by)) continue;
+      const uint32_t pidx = top - 1 - j;
+      const int lay = __builtin_amdgcn_readfirstlane(st.lay[j]);
+      const float4 g0 = st.s.g0[j];
+      const float4 g1 = st.s.g1[j];
+      float gr[G2P];
+#pragma unroll
+      for (int c = 0; c < G2P; ++c) gr[c] = 0.f;
+      const float dx = pxf - g0.x, dy = pyf - g0.y;
+      const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
+      const bool in_rect = (unsigned)(px - rc.x) <= (unsigned)rc.y && (unsigned)(py - rc.z) <= (unsigned)rc.w;
+      const float Gv = __expf(-power);
+      const float oG = g1.y * Gv;
+      const bool clamped = oG > a.alpha_max;
+      const float aval = clamped ? a.alpha_max : oG;
+      const bool sup = pidx < mylast && in_rect && power <= half_k2 && aval >= a.alpha_min;
+      if (sup) {
+        float dLda = 0.f;
+#pragma unroll
+        for (int q = 0; q < NLAY; ++q) {
+          if (pidx >= stop[q]) continue;   // layer q had stopped before this pair
+          const bool own = q == lay;       // wave-uniform
+          const float Tb = own ? T[q] * __builtin_amdgcn_rcpf(1.0f - aval) : T[q];
+          float sq = 0.f;
+#pragma unroll
+          for (int l = 0; l < NL; ++l) {
+            const float2 v = st.s.v[l][j];
+            sq += G[q][l].x * (v.x - Bacc[q][l].x) + G[q][l].y * (v.y - Bacc[q][l].y);
+          }
+          sq *= Tb;
+          gr[6 + 2 * NL + q] = aval * sq;
+          if (own) {
+            dLda = sq;
+            const float aT = aval * Tb;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+              const float2 v = st.s.v[l][j];
+              gr[6 + 2 * l] = aT * G[q][l].x;
+              gr[7 + 2 * l] = aT * G[q][l].y;
+              Bacc[q][l].x = aval * v.x + (1.0f - aval) * Bacc[q][l].x;
+              Bacc[q][l].y = aval * v.y + (1.0f - aval) * Bacc[q][l].y;
+            }
+            T[q] = Tb;
+          }
+        }
+        if (!clamped) {
+          gr[5] = Gv * dLda;
+          const float dpow = -aval * dLda;
+          gr[2] = 0.5f * dx * dx * dpow;
+          gr[3] = dx * dy * dpow;
+          gr[4] = 0.5f * dy * dy * dpow;
+          gr[0] = -(g0.z * dx + g0.w * dy) * dpow;
+          gr[1] = -(g0.w * dx + g1.x * dy) * dpow;
+        }
+      }
+      if (__ballot(sup) != 0ull) {
+        wave_sums_by_row<G2P>(gr);
+        if ((lane & 15) == 15) {
+          const int row = lane >> 4;
+#pragma unroll
+          for (int k = 0; k < G2P / 4; ++k) {
+            const int c = k + row * (G2P / 4);
+            if (c < G2) s_grad[j][c] = gr[k];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = lane; i < cnt * G2; i += kLanes) {
+      const int r = i / G2, c = i - r * G2;
+      const float sum = s_grad[r][c];
+      if (sum != 0.f) unsafeAtomicAdd(a.grad2d + (size_t)st.s.rid[r] * a.g2stride + c, sum);
+      s_grad[r][c] = 0.f;
+    }
+    top -= cnt;
+  }
+}
+
+// Straight-through estimator (Eq. 12, backward): the summed dL/drho of every
+// view times softmax(logits / tau).
+__global__ void k_logits_backward(const float* __restrict__ logits, const float* __restrict__ grad2d, int g2s,
+                                  int rho_off, const uint32_t* __restrict__ count, int n, int n_stride, int n_views,
+                                  int nlay, float inv_tau, float* __restrict__ d_logits) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  float drho[kMaxLayers], w[kMaxLayers];
+  float mx = logits[(size_t)g * nlay] * inv_tau;
+  for (int q = 0; q < nlay; ++q) {
+    drho[q] = 0.f;
+    w[q] = logits[(size_t)g * nlay + q] * inv_tau;
+    mx = fmaxf(mx, w[q]);
+  }
+  for (int b = 0; b < n_views; ++b) {
+    const size_t rid = (size_t)b * n_stride + g;
+    if (count[rid] == 0) continue;
+    for (int q = 0; q < nlay; ++q) drho[q] += grad2d[rid * g2s + rho_off + q];
+  }
+  float sum = 0.f;
+  for (int q = 0; q < nlay; ++q) {
+    w[q] = expf(w[q] - mx);
+    sum += w[q];
+  }
+  for (int q = 0; q < nlay; ++q) d_logits[(size_t)g * nlay + q] = drho[q] * (w[q] / sum);
+}
+
+hipError_t launch_assign_layers(const float* logits, int n, int n_layers, uint8_t* layer_of, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_assign_layers<<<(n + 255) / 256, 256, 0, s>>>(logits, n, n_layers, layer_of);
+  return hipGetLastError();
+}
+
+hipError_t launch_logits_backward(const float* logits, const float* grad2d, int g2stride, int rho_offset,
+                                  const uint32_t* count, int n, int n_stride, int n_views, int n_layers, float tau,
+                                  float* d_logits, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_logits_backward<<<(n + 255) / 256, 256, 0, s>>>(logits, grad2d, g2stride, rho_offset, count, n, n_stride,
+                                                    n_views, n_layers, 1.0f / tau, d_logits);
+  return hipGetLastError();
+}
+
+#define CHRF_LAYERS_DISPATCH(KERNEL)                                                          \
+  const int blocks = a.n_views * a.tiles_x * a.tiles_y;                                      \
+  if (blocks == 0) return hipSuccess;                                                        \
+  if (a.tile_w != 8 || a.tile_h != 8 || a.n_layers < 1 || a.n_layers > kMaxLayers ||         \
+      a.n_lambda < 1 || a.n_lambda > 4)                                                       \
+    return hipErrorInvalidValue;                                                             \
+  switch (a.n_lambda * 8 + a.n_layers) {                                                     \
+    case 9: KERNEL<1, 1><<<blocks, kLanes, 0, s>>>(a); break;                                \
+    case 10: KERNEL<1, 2><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    case 11: KERNEL<1, 3><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    case 12: KERNEL<1, 4><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    case 17: KERNEL<2, 1><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    case 18: KERNEL<2, 2><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    case 19: KERNEL<2, 3><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    case 20: KERNEL<2, 4><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    case 25: KERNEL<3, 1><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    case 26: KERNEL<3, 2><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    case 27: KERNEL<3, 3><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    case 28: KERNEL<3, 4><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    case 33: KERNEL<4, 1><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    case 34: KERNEL<4, 2><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    case 35: KERNEL<4, 3><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    case 36: KERNEL<4, 4><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    default: return hipErrorInvalidValue;                                                    \
+  }                                                                                          \
+  return hipGetLastError();
+
+hipError_t launch_raster_layers_forward(const RasterArgs& a, hipStream_t s) { CHRF_LAYERS_DISPATCH(k_raster_layers_fwd) }
+
+hipError_t launch_raster_layers_backward(const RasterArgs& a, hipStream_t s) {
+  CHRF_LAYERS_DISPATCH(k_raster_layers_bwd)
+}
+
+}  // namespace chrf

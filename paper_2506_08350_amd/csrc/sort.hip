@@ -10,9 +10,11 @@
 // starts from index order.  Depths are positive floats, whose bit patterns
 // order like their values.
 //
-// The radix sort is LSD with 8-bit digits: one kernel counts the digit
-// histograms of every pass per block, one exclusive scan covers all of them
-// (pass, digit, block), and each pass is a stable scatter.  Ranks inside a
+// The radix sort is LSD with 8-bit digits; every pass counts per-block digit
+// histograms of the keys in their current order, scans them over (digit,
+// block) and scatters stably.  (The per-block split of a pass depends on the
+// permutation the previous pass produced, so histograms of later passes
+// cannot be taken from the input order.)  Ranks inside a
 // block come from wave ballots: a lane's rank among equal digits is the
 // popcount of the lower lanes whose 8 digit bits all match, plus the counts of
 // earlier waves and earlier rounds held in LDS.  Counts that are only known on
@@ -134,14 +136,13 @@ __device__ inline int64_t live_count(int64_t n_max, const uint64_t* n_dev) {
   return v < (uint64_t)n_max ? (int64_t)v : n_max;
 }
 
-// Digit histograms of every pass in one read of the keys:
-// hist[(pass * 256 + digit) * nblocks + block].
+// Digit histogram of one pass per block: hist[digit * nblocks + block].
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* __restrict__ keys, int64_t n_max,
-                                                             const uint64_t* n_dev, int begin_bit, int npasses,
+                                                             const uint64_t* n_dev, int shift,
                                                              uint32_t* __restrict__ hist, int nblocks) {
-  __shared__ uint32_t cnt[kMaxSortPasses][256];
-  for (int p = 0; p < npasses; ++p) cnt[p][threadIdx.x] = 0;
+  __shared__ uint32_t cnt[256];
+  cnt[threadIdx.x] = 0;
   __syncthreads();
   const int64_t n = live_count(n_max, n_dev);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
@@ -149,15 +150,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* __restrict
 #pragma unroll 4
     for (int i = 0; i < kSortItems; ++i) {
       const int64_t idx = base + i * kSortThreads + threadIdx.x;
-      if (idx < n) {
-        const K key = keys[idx];
-        for (int p = 0; p < npasses; ++p) atomicAdd(&cnt[p][(uint32_t)(key >> (begin_bit + 8 * p)) & 255u], 1u);
-      }
+      if (idx < n) atomicAdd(&cnt[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
     }
   }
   __syncthreads();
-  for (int p = 0; p < npasses; ++p)
-    hist[((int64_t)p * 256 + threadIdx.x) * nblocks + blockIdx.x] = cnt[p][threadIdx.x];
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
 template <typename K>
@@ -165,10 +162,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
                                                                 const uint32_t* __restrict__ vals_in,
                                                                 K* __restrict__ keys_out,
                                                                 uint32_t* __restrict__ vals_out, int64_t n_max,
-                                                                const uint64_t* n_dev, int shift, int pass,
+                                                                const uint64_t* n_dev, int shift,
                                                                 const uint32_t* __restrict__ offsets, int nblocks) {
-  // offsets is the exclusive scan of every pass's histogram laid end to end;
-  // each pass counts n keys, so this pass's offsets start at pass * n
   constexpr int NW = kSortThreads / 64;
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[NW][256];
@@ -179,7 +174,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
   if (base >= n) return;   // uniform per block
   run[tid] = 0;
   for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
-  goff[tid] = offsets[((int64_t)pass * 256 + tid) * nblocks + blockIdx.x] - (uint32_t)(pass * n);
+  goff[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int r = 0; r < kSortItems; ++r) {
@@ -207,8 +202,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
       uint32_t before = 0;
       for (int w = 0; w < wave; ++w) before += wcnt[w][d];
       const uint32_t pos = goff[d] + run[d] + before + lower;
-      keys_out[pos] = key;
-      vals_out[pos] = val;
+      if (pos < (uint64_t)n) {   // always true for consistent offsets; keeps every write in bounds
+        keys_out[pos] = key;
+        vals_out[pos] = val;
+      }
     }
     __syncthreads();
     uint32_t add = 0;
@@ -223,7 +220,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
 
 int64_t radix_hist_elems(int64_t n_max) {
   const int64_t nb = (n_max + kSortTile - 1) / kSortTile;
-  return (int64_t)kMaxSortPasses * 256 * (nb > 0 ? nb : 1);
+  return 256 * (nb > 0 ? nb : 1);
 }
 
 template <typename K>
@@ -241,13 +238,12 @@ static hipError_t radix_sort_impl(K* keys, K* keys_alt, uint32_t* vals, uint32_t
   uint32_t* vin = vals;
   uint32_t* vout = vals_alt;
   bool alt = false;
-  k_radix_hist<K><<<nblocks, kSortThreads, 0, s>>>(keys, n_max, n_dev, begin_bit, npasses, hist, nblocks);
-  hipError_t e = launch_scan_u32(hist, hist, (int64_t)npasses * 256 * nblocks, scan_tmp, s);
-  if (e != hipSuccess) return e;
   for (int pass = 0; pass < npasses; ++pass) {
     const int shift = begin_bit + 8 * pass;
-    k_radix_scatter<K><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n_max, n_dev, shift, pass, hist,
-                                                        nblocks);
+    k_radix_hist<K><<<nblocks, kSortThreads, 0, s>>>(kin, n_max, n_dev, shift, hist, nblocks);
+    hipError_t e = launch_scan_u32(hist, hist, (int64_t)256 * nblocks, scan_tmp, s);
+    if (e != hipSuccess) return e;
+    k_radix_scatter<K><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n_max, n_dev, shift, hist, nblocks);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     K* tk = kin; kin = kout; kout = tk;

@@ -48,8 +48,9 @@ def test_struct_layout_matches_c():
 int main(void) {
   printf("%zu %zu %zu %zu %zu\n", sizeof(chrf_plan_desc), sizeof(chrf_camera), sizeof(chrf_gaussians),
          sizeof(chrf_grads), offsetof(chrf_plan_desc, k_sigma));
-  printf("%zu %zu %zu\n", offsetof(chrf_plan_desc, pitch), offsetof(chrf_plan_desc, distances),
-         offsetof(chrf_plan_desc, cols_per_block));
+  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(chrf_plan_desc, pitch), offsetof(chrf_plan_desc, distances),
+         offsetof(chrf_plan_desc, cols_per_block), offsetof(chrf_plan_desc, layered),
+         offsetof(chrf_gaussians, logits), offsetof(chrf_grads, logits));
   return 0;
 }
 """
@@ -62,7 +63,8 @@ int main(void) {
     P = _lib.PlanDesc
     assert vals == [ctypes.sizeof(P), ctypes.sizeof(_lib.Camera), ctypes.sizeof(_lib.Gaussians),
                     ctypes.sizeof(_lib.Grads), P.k_sigma.offset, P.pitch.offset, P.distances.offset,
-                    P.cols_per_block.offset]
+                    P.cols_per_block.offset, P.layered.offset, _lib.Gaussians.logits.offset,
+                    _lib.Grads.logits.offset]
 
 
 def test_camera_record_packing_matches_struct():

@@ -147,3 +147,34 @@ def test_batched_16_views_ring_500k():
     _tile_checks(w, r)
     for k in api.PARAM_NAMES:
         assert torch.isfinite(grads[k]).all(), k
+
+
+def test_four_views_2160p_2m_16_planes():
+    """The largest configuration: 2,000,000 Gaussians, four yawed views of
+    2160 x 3840, pitch 4 um, 16 planes (padded 4320 x 7680, the mixed-radix
+    generic transforms)."""
+    w = make_workload("c5")
+    announce("workload 4 views 2160p 2m 16 planes")
+    r, params, cam_t = _renderer(w, cap_factor=1.05)
+    B, L, K, H, W = r.B, r.L, r.K, r.H, r.W
+    gen = torch.Generator(device="cuda").manual_seed(1005 + 10_000)
+    target = torch.rand((B, L, K, H, W), generator=gen, device="cuda")
+    out = r.forward(params, cam_t, want_field=True, want_intensity=True, target=target)
+    grads = r.backward(params, cam_t)
+    torch.cuda.synchronize()
+    assert r.read_status()[0] == 0
+    I = out["intensity"]
+    ref_loss = sum(float(((I[b].double() - target[b].double()) ** 2).sum()) for b in range(B)) / I.numel()
+    assert abs(float(out["loss"]) - ref_loss) < 1e-5 * ref_loss
+    _window_checks(w, out["field"], r)
+    _tile_checks(w, r)
+    for k in api.PARAM_NAMES:
+        assert torch.isfinite(grads[k]).all(), k
+    # one (wavelength, plane) pair of one view through the full padded propagation
+    U = cplx(out["field"][1, 2])
+    del out, I
+    ref = oracle.propagate(U, w.optics.wavelengths[2], w.optics.distances[11], w.optics.pitch, w.optics.pad,
+                           w.optics.band_limit)
+    prop, _ = r.propagate(r.forward(params, cam_t, want_field=True, want_intensity=False)["field"],
+                          want_intensity=False)
+    assert rel_l2(cplx(prop[1, 2, 11]), ref) < 1e-4
