@@ -7,7 +7,9 @@ forward equations), band-limited angular-spectrum propagation (Eqs. 7, 14, 16),
 the focal-stack MSE (Eq. 17) and the analytic gradient of all of it
 (Supplementary D backward pass); ``layers.py`` adds the multi-layer hologram
 with hard plane assignment, forward recording and inverse propagation
-(Sec. 4.1, Eqs. 12-16) and its gradient with the straight-through estimator.
+(Sec. 4.1, Eqs. 12-16) and its gradient with the straight-through estimator;
+``losses.py`` the paper's training loss (masked three-term reconstruction
+loss plus the SSIM term) and its gradient.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the HIP library
@@ -23,11 +25,11 @@ from .binning import fp32_footprint, bin_pairs
 from .raster import render_field, render_field_backward, RasterResult
 from .asm import transfer_function, band_mask, propagate, propagate_adjoint
 from .pipeline import Thresholds, SMOOTH, DEFAULT, forward, backward, mse_loss
-from . import layers
+from . import layers, losses
 
 __all__ = [
     "quat_to_rotmat", "project", "ProjectedGaussians", "fp32_footprint", "bin_pairs",
     "render_field", "render_field_backward", "RasterResult", "transfer_function",
     "band_mask", "propagate", "propagate_adjoint", "Thresholds", "SMOOTH", "DEFAULT",
-    "forward", "backward", "mse_loss", "layers",
+    "forward", "backward", "mse_loss", "layers", "losses",
 ]
