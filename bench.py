@@ -26,13 +26,21 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 
 
-def kernel_bytes(name, B, L, K, H, W, pH, pW, train):
-    """Algorithmic HBM bytes of one launch of each propagation kernel."""
+def kernel_bytes(name, B, L, K, H, W, pH, pW, train, fused=True):
+    """Algorithmic HBM bytes of one launch of each propagation kernel.  train:
+    the inverse row pass reads the targets; fused: it also writes the
+    adjoint's row spectra (MSE), else it stores u and I for the loss."""
     c = 8  # complex64
+    if train and fused:
+        inv_row = pW * c + pW * c + W * 4
+    elif train:
+        inv_row = pW * c + W * c + W * 4
+    else:
+        inv_row = pW * c + W * 4
     table = {
         "rows_forward": B * L * H * (W + pW) * c,
         "cols_forward": B * L * (H * pW + K * H * pW) * c,
-        "rows_inverse": B * L * K * H * (pW * c + (pW * c + W * 4 if train else W * 4)),
+        "rows_inverse": B * L * K * H * inv_row,
         "cols_adjoint": B * L * (K * H * pW + H * pW) * c,
         "rows_adjoint_out": B * L * H * (pW + W) * c,
     }
@@ -42,37 +50,49 @@ def kernel_bytes(name, B, L, K, H, W, pH, pW, train):
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_step_c3_1080p_100k.md")
 
 
-def kernel_sources_sha256():
-    """Hash of every HIP source of the library (any change invalidates counters)."""
+# HIP sources each timed kernel is built from (a change invalidates its counters)
+KERNEL_SOURCES = {
+    "rows_forward": ("asm.hip", "asm_tuned.hip", "fft.h", "internal.h"),
+    "cols_forward": ("asm.hip", "asm_tuned.hip", "fft.h", "internal.h"),
+    "rows_inverse": ("asm.hip", "asm_tuned.hip", "fft.h", "internal.h"),
+    "cols_adjoint": ("asm.hip", "asm_tuned.hip", "fft.h", "internal.h"),
+    "rows_adjoint_out": ("asm.hip", "asm_tuned.hip", "fft.h", "internal.h"),
+    "raster_forward": ("raster.hip", "raster_common.h", "internal.h"),
+    "raster_backward": ("raster.hip", "raster_common.h", "internal.h"),
+}
+
+
+def source_sha256(name):
     import hashlib
-    csrc = os.path.join(ROOT, "paper_2506_08350_amd", "csrc")
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
-    return h.hexdigest()
+    with open(os.path.join(ROOT, "paper_2506_08350_amd", "csrc", name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
 def measured_traffic(kernel):
     """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or
-    None when that summary is missing or the sources changed since it was taken."""
+    None when that summary is missing, does not cover the kernel, or any of the
+    kernel's sources changed since the counters were taken."""
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
-    sha = None
+    shas = {}
     table = {}
     for line in text.splitlines():
-        if line.startswith("sources-sha256:"):
-            sha = line.split(":", 1)[1].strip()
+        if line.startswith("source-sha256 "):
+            _, name, sha = line.split()
+            shas[name] = sha
         cells = [c.strip(" `") for c in line.strip().strip("|").split("|")]
         if len(cells) == 5 and cells[0] and cells[4].isdigit():
             table[cells[0]] = int(cells[4])
-    if sha != kernel_sources_sha256():
+    files = KERNEL_SOURCES.get(kernel)
+    if kernel not in table or not files:
         return None
-    return table.get(kernel)
+    for f in files:
+        if shas.get(f) != source_sha256(f):
+            return None
+    return table[kernel]
 
 
 def cpu_baseline(w, seed=0):
@@ -187,6 +207,8 @@ def main(argv=None):
     ap.add_argument("--kernel-table", action="store_true", help="also print the per-kernel table to stderr")
     ap.add_argument("--cols-per-block", type=int, default=0, help="column FFT pass: 2 or 4 columns per workgroup")
     ap.add_argument("--tile", default=None, help="raster tile, e.g. 16x16, 16x8, 8x8 (default 16x16; 8x8 layered)")
+    ap.add_argument("--loss", default="mse", choices=["mse", "paper"],
+                    help="training loss: the MSE (default) or the paper's masked reconstruction + SSIM loss")
     ap.add_argument("--no-fwd-rate", action="store_true",
                     help="skip the separate forward-only timing (keeps every launch a training-step launch)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -226,6 +248,9 @@ def main(argv=None):
     if layered:
         params[api.LAYER_LOGITS] = torch.from_numpy(w.notes["logits"]).cuda()
     tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else ((8, 8) if layered else (16, 16))
+    masks = None
+    if args.loss == "paper":
+        masks = torch.from_numpy(scenegen.make_plane_masks(B, K, H, W, w.notes["masks_seed"])).cuda()
     cam_t = api.pack_cameras(cams)
     target = torch.from_numpy(w.targets).cuda()
 
@@ -236,11 +261,11 @@ def main(argv=None):
     cap = int(need * 1.25) + 4096
     del r
     r = api.Renderer(H, W, o, n_views=B, max_gaussians=sc.n, max_pairs=cap, tile=tile,
-                     cols_per_block=args.cols_per_block, layered=layered)
+                     cols_per_block=args.cols_per_block, layered=layered, loss=args.loss)
 
     def step():
         if train:
-            r.train_step(params, cam_t, target)
+            r.train_step(params, cam_t, target, masks=masks)
         else:
             r.forward(params, cam_t, want_field=False, want_intensity=True)
 
@@ -251,7 +276,7 @@ def main(argv=None):
         raise RuntimeError(f"pair list overflow: {need} > {cap}")
     torch.cuda.synchronize()
     if args.graph and train:
-        captured = api.CapturedTrainStep(r, params, cam_t, target)
+        captured = api.CapturedTrainStep(r, params, cam_t, target, masks=masks)
         step = captured.replay
         for _ in range(args.warmup):
             step()
@@ -266,7 +291,7 @@ def main(argv=None):
     if args.graph:       # per-kernel events cannot live inside a graph: time them eagerly
         r.timing(True)
         for _ in range(args.steps):
-            r.train_step(params, cam_t, target) if train else r.forward(params, cam_t, want_field=False)
+            r.train_step(params, cam_t, target, masks=masks) if train else r.forward(params, cam_t, want_field=False)
         torch.cuda.synchronize()
         r.timing(False)
     kt = r.timing_report()
@@ -287,10 +312,11 @@ def main(argv=None):
 
     # dominant propagation kernel against the HBM roofline
     per_launch = {n: (c, tot / c) for n, (c, tot) in kt.items()}
-    asm = {n: v for n, v in per_launch.items() if kernel_bytes(n, B, L, K, H, W, pH, pW, train) is not None}
+    fused = args.loss == "mse"
+    asm = {n: v for n, v in per_launch.items() if kernel_bytes(n, B, L, K, H, W, pH, pW, train, fused) is not None}
     dom = max(asm, key=lambda n: asm[n][0] * asm[n][1])
     dom_ms = asm[dom][1]
-    dom_bytes = kernel_bytes(dom, B, L, K, H, W, pH, pW, train)
+    dom_bytes = kernel_bytes(dom, B, L, K, H, W, pH, pW, train, fused)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
@@ -298,7 +324,7 @@ def main(argv=None):
     if args.kernel_table:
         tot = sum(c * m for c, m in per_launch.values())
         for n, (c, m) in sorted(per_launch.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
-            b = kernel_bytes(n, B, L, K, H, W, pH, pW, train)
+            b = kernel_bytes(n, B, L, K, H, W, pH, pW, train, fused)
             bw = f"{b / (m * 1e-3) / 1e9:8.1f} GB/s" if b else ""
             print(f"{n:18s} {c:4d} x {m:8.4f} ms  {100 * c * m / tot:5.1f}%  {bw}", file=sys.stderr)
 
@@ -310,7 +336,7 @@ def main(argv=None):
         "value": round(value, 3), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": workload, "tile": f"{tile[0]}x{tile[1]}",
+        "config": {"workload": workload, "tile": f"{tile[0]}x{tile[1]}", "loss": args.loss,
                    "gaussians": sc.n, "height": H, "width": W, "wavelengths": L, "planes": K,
                    "views_per_step": B, "pad": opt.pad, "pairs": int(need), "parallelism": "single-gpu"},
         "fwd_frames_per_s": round(1000.0 / fwd_ms * B, 3) if fwd_ms else None,

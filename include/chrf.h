@@ -132,6 +132,15 @@ typedef struct chrf_grads {
  *                      P = sum_l ASM(U_l; +Z_l) and propagated back to every
  *                      layer, u_k = ASM(P; -Z_k), I_k = |u_k|^2.  Needs
  *                      8 x 8 tiles (0, 0 selects them).
+ *   loss_kind          loss computed by chrf_forward when a target is given:
+ *                      0: MSE, the mean of (I - T)^2 over all elements (Eq. 17);
+ *                      1: the paper's training loss (Sec. 4.1): the
+ *                      three-term reconstruction loss with plane masks M,
+ *                      mean of (I - T)^2 (1 + M + T^2), plus
+ *                      ssim_weight * (1 - mean SSIM(I, T)) (11 x 11 Gaussian
+ *                      window, sigma 1.5, C1 = 0.01^2, C2 = 0.03^2, zero
+ *                      padding; one SSIM per view, wavelength and plane)
+ *   ssim_weight        lambda_1 of the SSIM term (0.005 in the paper)
  */
 typedef struct chrf_plan_desc {
   int32_t height, width;
@@ -147,7 +156,9 @@ typedef struct chrf_plan_desc {
   int32_t tile_w, tile_h;
   int32_t cols_per_block;
   int32_t layered;
-  int32_t reserved[6];
+  int32_t loss_kind;
+  float ssim_weight;
+  int32_t reserved[4];
 } chrf_plan_desc;
 
 /* Named regions of the workspace, for inspection by tests and tools. */
@@ -165,6 +176,7 @@ typedef enum chrf_region {
   CHRF_REGION_LAYER_T_FINAL = 9, /* float [n_views][n_planes][H][W] transmittance of each layer */
   CHRF_REGION_LAYER_STOP = 10,   /* uint32 [n_views][n_planes][H][W] pair + 1 that ended the layer, ~0 if none */
   CHRF_REGION_LAYER_GRAD = 11,   /* complex [n_views][n_lambda][n_planes][H][W] dL/dU_l after backward */
+  CHRF_REGION_LOSS_PARTIAL = 12, /* float [n_views][n_lambda][n_planes][H]: MSE row sums of the last forward */
   CHRF_REGION_COUNT
 } chrf_region;
 
@@ -200,22 +212,26 @@ chrf_status chrf_plan_region(const chrf_plan* plan, int region, size_t* offset, 
  *   prop_out        complex [n_views][n_lambda][n_planes][H][W] or NULL (u)
  *   intensity_out   float   [n_views][n_lambda][n_planes][H][W] or NULL (|u|^2)
  *   target          float   same shape as intensity, or NULL; when given,
- *                   loss_out (device float scalar) receives the MSE over all
- *                   elements (Eq. 17 with a mean) and the workspace is
- *                   prepared for chrf_backward with dL_dI = NULL.
+ *                   loss_out (device float scalar) receives the plan's loss
+ *                   (loss_kind) and the workspace is prepared for
+ *                   chrf_backward with dL_dI = NULL.  With loss_kind 1 the
+ *                   target, masks, prop_out and intensity_out buffers are read
+ *                   again by that chrf_backward and must stay unchanged.
+ *   masks           uint8 [n_views][n_planes][H][W] (0/1) plane masks of
+ *                   loss_kind 1, or NULL (all zero); ignored otherwise
  * A pair-list overflow is not reported here (no synchronisation); outputs are
  * then incomplete but every access stays in bounds, and chrf_read_status
  * reports CHRF_ECAPACITY.
  */
 chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_camera* cams, void* workspace,
                          float* field_out, float* prop_out, float* intensity_out, const float* target,
-                         float* loss_out, void* hip_stream);
+                         const uint8_t* masks, float* loss_out, void* hip_stream);
 
 /*
  * Backward pass (Supplementary D): gradients of the loss w.r.t. every
  * Gaussian parameter, summed over views.
  *   dL_dI      float [n_views][n_lambda][n_planes][H][W] or NULL.  NULL means:
- *              use the MSE of the last chrf_forward that had a target.
+ *              use the loss of the last chrf_forward that had a target.
  *   prop       complex u saved from chrf_forward (prop_out); required when
  *              dL_dI is given
  *   dL_dprop   complex, same shape as prop, or NULL

@@ -31,6 +31,7 @@ REGION_LAYER_FIELDS = 8
 REGION_LAYER_T_FINAL = 9
 REGION_LAYER_STOP = 10
 REGION_LAYER_GRAD = 11
+REGION_LOSS_PARTIAL = 12
 
 EXPORTED = [
     "chrf_create", "chrf_destroy", "chrf_last_error", "chrf_version", "chrf_plan_create",
@@ -62,7 +63,8 @@ class PlanDesc(C.Structure):
                 ("wavelengths", C.c_double * 4), ("distances", C.c_double * 64), ("k_sigma", C.c_float),
                 ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
                 ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("cols_per_block", C.c_int32),
-                ("layered", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("layered", C.c_int32), ("loss_kind", C.c_int32), ("ssim_weight", C.c_float),
+                ("reserved", C.c_int32 * 4)]
 
 
 class ChrfError(RuntimeError):
@@ -98,7 +100,7 @@ def load(path: str | None = None):
         "chrf_plan_destroy": (None, [vp]),
         "chrf_plan_workspace_bytes": (sz, [vp]),
         "chrf_plan_region": (i32, [vp, C.c_int, C.POINTER(sz), C.POINTER(sz)]),
-        "chrf_forward": (i32, [vp, C.POINTER(Gaussians), vp, vp, vp, vp, vp, vp, vp, vp]),
+        "chrf_forward": (i32, [vp, C.POINTER(Gaussians), vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "chrf_backward": (i32, [vp, C.POINTER(Gaussians), vp, vp, vp, vp, vp, vp, vp, C.POINTER(Grads), vp]),
         "chrf_propagate": (i32, [vp, vp, vp, vp, vp, vp]),
         "chrf_propagate_adjoint": (i32, [vp, vp, vp, vp, vp]),

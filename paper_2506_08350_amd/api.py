@@ -76,11 +76,12 @@ class Renderer:
 
     def __init__(self, height, width, optics: Optics, n_views=1, max_gaussians=1, n_lambda=None,
                  max_pairs=0, k_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
-                 tile=None, cols_per_block=0, layered=False, device=0):
+                 tile=None, cols_per_block=0, layered=False, loss="mse", ssim_weight=0.005, device=0):
         """layered=True: multi-layer hologram with one layer per entry of
         optics.distances (the layer-to-hologram distances Z_l); the Gaussians
         then carry "logits" [N, layers] and the forward's "field" is the
-        recorded hologram P."""
+        recorded hologram P.  loss: "mse" (Eq. 17) or "paper" (the masked
+        three-term reconstruction loss plus ssim_weight * (1 - SSIM))."""
         self.ctx = context(device)
         self.lib = self.ctx.lib
         d = _lib.PlanDesc()
@@ -104,6 +105,11 @@ class Renderer:
         d.cols_per_block = int(cols_per_block)
         d.layered = 1 if layered else 0
         self.layered = bool(layered)
+        if loss not in ("mse", "paper"):
+            raise ValueError(f"unknown loss {loss!r}")
+        d.loss_kind = 1 if loss == "paper" else 0
+        d.ssim_weight = float(ssim_weight)
+        self.loss = loss
         self.desc = d
         h = C.c_void_p()
         check(self.lib.chrf_plan_create(self.ctx.handle, C.byref(d), C.byref(h)))
@@ -163,7 +169,9 @@ class Renderer:
         return PARAM_NAMES + ((LAYER_LOGITS,) if self.layered else ())
 
     def forward(self, params: dict, cams: torch.Tensor, want_field=True, want_prop=False, want_intensity=True,
-                target=None):
+                target=None, masks=None):
+        """masks: uint8 [views, planes, H, W] plane masks of the "paper" loss
+        (kept alive until the backward, like target)."""
         B, L, K, H, W = self.B, self.L, self.K, self.H, self.W
         dev = self.device
         field = torch.empty((B, L, H, W, 2), dtype=torch.float32, device=dev) if want_field else None
@@ -172,9 +180,12 @@ class Renderer:
         loss = torch.empty((), dtype=torch.float32, device=dev) if target is not None else None
         if target is not None:
             assert target.shape == (B, L, K, H, W) and target.is_contiguous()
+        if masks is not None:
+            assert masks.shape == (B, K, H, W) and masks.dtype == torch.uint8 and masks.is_contiguous()
         g = self._gauss(params)
         check(self.lib.chrf_forward(self.plan, C.byref(g), _ptr(cams), _ptr(self.workspace), _ptr(field),
-                                    _ptr(prop), _ptr(inten), _ptr(target), _ptr(loss), _stream()))
+                                    _ptr(prop), _ptr(inten), _ptr(target), _ptr(masks), _ptr(loss), _stream()))
+        self._saved = (target, masks, prop, inten)   # read again by a backward of the "paper" loss
         return {"field": field, "prop": prop, "intensity": inten, "loss": loss}
 
     def backward(self, params: dict, cams: torch.Tensor, dL_dI=None, prop=None, dL_dprop=None, dL_dfield=None,
@@ -189,10 +200,10 @@ class Renderer:
                                      C.byref(gr), _stream()))
         return grads
 
-    def train_step(self, params: dict, cams: torch.Tensor, target: torch.Tensor, want_intensity=False):
-        """Forward with the fused MSE loss, then the backward: (loss, grads)."""
+    def train_step(self, params: dict, cams: torch.Tensor, target: torch.Tensor, want_intensity=False, masks=None):
+        """Forward with the plan's loss, then the backward: (loss, grads)."""
         out = self.forward(params, cams, want_field=False, want_prop=False, want_intensity=want_intensity,
-                           target=target)
+                           target=target, masks=masks)
         grads = self.backward(params, cams)
         return out["loss"], grads, out
 
@@ -212,28 +223,29 @@ class Renderer:
 
 
 class CapturedTrainStep:
-    """The fused training step (forward with the MSE, then the backward)
-    captured once in a HIP graph and replayed.
+    """The fused training step (forward with the plan's loss, then the
+    backward) captured once in a HIP graph and replayed.
 
-    The graph holds the pointers of ``params``, ``cams`` and ``target``: update
-    those tensors in place (``copy_``) between replays.  ``loss`` and ``grads``
+    The graph holds the pointers of ``params``, ``cams``, ``target`` and
+    ``masks``: update those tensors in place (``copy_``) between replays.  ``loss`` and ``grads``
     are overwritten by every replay.  The library's forward and backward
     enqueue no synchronisation, allocation or memset, so the whole sequence
     (projection, sorts, raster, propagation, backward) is capturable.
     """
 
-    def __init__(self, renderer: Renderer, params: dict, cams: torch.Tensor, target: torch.Tensor, warmup: int = 2):
+    def __init__(self, renderer: Renderer, params: dict, cams: torch.Tensor, target: torch.Tensor, warmup: int = 2,
+                 masks=None):
         self.renderer = renderer
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
             for _ in range(warmup):
-                renderer.train_step(params, cams, target)
+                renderer.train_step(params, cams, target, masks=masks)
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            self.loss, self.grads, _ = renderer.train_step(params, cams, target)
+            self.loss, self.grads, _ = renderer.train_step(params, cams, target, masks=masks)
 
     def replay(self):
         self.graph.replay()

@@ -21,7 +21,8 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libchrf.so")
 ARCH = os.environ.get("CHRF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["project.hip", "sort.hip", "raster.hip", "raster_layers.hip", "asm.hip", "asm_tuned.hip", "capi.cpp"]
+SOURCES = ["project.hip", "sort.hip", "raster.hip", "raster_layers.hip", "asm.hip", "asm_tuned.hip", "loss.hip",
+           "capi.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -38,6 +38,7 @@ enum Reg {
   R_HIST, R_PKEY, R_PKEY_ALT, R_PVAL, R_PVAL_ALT, R_RANGES, R_STATUS, R_TFINAL, R_LAST, R_FIELD, R_X1, R_Y,
   R_GRAD_FIELD, R_GRAD2D, R_LOSS_PARTIAL,
   R_LAYER_OF, R_LFIELD, R_LTFINAL, R_LSTOP, R_LGRAD,   // layered plans only
+  R_UPROP, R_INTEN, R_DMU, R_DEXX, R_DEXY, R_DLDI, R_LOSS2,   // loss_kind 1 only
   R_NUM
 };
 
@@ -65,6 +66,13 @@ struct chrf_plan {
   int cols_per_block = 0;
   int g2 = 0;
   bool layered = false;
+  int loss_kind = 0;
+  // loss_kind 1: buffers of the last forward that the backward reads again
+  bool paper_ready = false;
+  const float2* saved_prop = nullptr;
+  const float* saved_inten = nullptr;
+  const float* saved_target = nullptr;
+  const uint8_t* saved_masks = nullptr;
   int gsort_bits = 0, psort_bits = 0;
   bool gsort_alt = false, psort_alt = false;
   FftDesc frow{}, fcol{};
@@ -230,6 +238,8 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   if (!(d.k_sigma > 0) || !(d.alpha_max > 0 && d.alpha_max <= 1) || !(d.alpha_min >= 0) || !(d.t_min >= 0))
     return fail(CHRF_EINVAL, "plan: thresholds out of range");
   if (d.layered != 0 && d.layered != 1) return fail(CHRF_EINVAL, "plan: layered must be 0 or 1");
+  if (d.loss_kind != 0 && d.loss_kind != 1) return fail(CHRF_EINVAL, "plan: loss_kind must be 0 or 1");
+  if (!(d.ssim_weight >= 0) || !std::isfinite(d.ssim_weight)) return fail(CHRF_EINVAL, "plan: ssim_weight must be >= 0");
   if (d.layered && d.n_planes > kMaxLayers) return fail(CHRF_EUNSUPPORTED, "plan: a layered plan takes 1..4 layers");
   int tw = d.tile_w, th = d.tile_h;
   if (tw == 0 && th == 0) tw = th = d.layered ? 8 : 16;
@@ -255,6 +265,7 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   p->tiles_y = (d.height + th - 1) / th;
   p->n_tiles = p->tiles_x * p->tiles_y;
   p->layered = d.layered != 0;
+  p->loss_kind = d.loss_kind;
   // per-(view, Gaussian) gradient row: 6 + 2 n_lambda values (+ n_layers), padded
   // to 16 floats (one 64-byte row) or the next multiple of 4
   p->g2 = std::max(16, (6 + 2 * p->L + (p->layered ? p->K : 0) + 3) & ~3);
@@ -366,6 +377,10 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   sz[R_LFIELD] = sz[R_LGRAD] = sizeof(float2) * lpix * p->L;
   sz[R_LTFINAL] = sizeof(float) * lpix;
   sz[R_LSTOP] = sizeof(uint32_t) * lpix;
+  const size_t ipix = p->loss_kind == 1 ? (size_t)pix * p->L * p->K : 0;
+  sz[R_UPROP] = sizeof(float2) * ipix;
+  sz[R_INTEN] = sz[R_DMU] = sz[R_DEXX] = sz[R_DEXY] = sz[R_DLDI] = sizeof(float) * ipix;
+  sz[R_LOSS2] = p->loss_kind == 1 ? sizeof(float) * (size_t)loss_partial_elems(p->B * p->L * p->K, p->H, p->W) : 0;
   size_t o = 0;
   for (int r = 0; r < R_NUM; ++r) {
     p->off[r] = o;
@@ -406,6 +421,7 @@ chrf_status chrf_plan_region(const chrf_plan* p, int region, size_t* offset, siz
     case CHRF_REGION_LAYER_T_FINAL: r = R_LTFINAL; break;
     case CHRF_REGION_LAYER_STOP: r = R_LSTOP; break;
     case CHRF_REGION_LAYER_GRAD: r = R_LGRAD; break;
+    case CHRF_REGION_LOSS_PARTIAL: r = R_LOSS_PARTIAL; break;
     default: return fail(CHRF_EINVAL, "chrf_plan_region: unknown region");
   }
   *offset = p->off[r];
@@ -438,13 +454,14 @@ static chrf_status asm_forward(chrf_plan* plan, const float2* field, void* ws, f
 
 chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_camera* cams, void* ws,
                          float* field_out, float* prop_out, float* intensity_out, const float* target,
-                         float* loss_out, void* hip_stream) {
+                         const uint8_t* masks, float* loss_out, void* hip_stream) {
   if (!plan || !cams || !ws) return fail(CHRF_EINVAL, "chrf_forward: NULL plan, cameras or workspace");
   chrf_status st = check_gaussians(plan, g);
   if (st != CHRF_OK) return st;
   if (target && !loss_out) return fail(CHRF_EINVAL, "chrf_forward: target needs loss_out");
   hipStream_t s = (hipStream_t)hip_stream;
   plan->fused_ready = false;
+  plan->paper_ready = false;
   const int Nst = std::max(plan->N, 1);
   const int64_t BN = (int64_t)plan->B * Nst;
   float2* field = field_out ? reinterpret_cast<float2*>(field_out) : at<float2>(plan, ws, R_FIELD);
@@ -547,6 +564,24 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
     RUN("raster_forward", launch_raster_forward(ra, s));
   }
 
+  if (target && plan->loss_kind == 1) {
+    // unfused: keep u and I for the loss and its backward
+    float2* u = prop_out ? reinterpret_cast<float2*>(prop_out) : at<float2>(plan, ws, R_UPROP);
+    float* I = intensity_out ? intensity_out : at<float>(plan, ws, R_INTEN);
+    st = asm_forward(plan, field, ws, reinterpret_cast<float*>(u), I, nullptr, s);
+    if (st != CHRF_OK) return st;
+    const int n_img = plan->B * plan->L * plan->K;
+    RUN("loss_forward", launch_paper_loss_forward(I, target, masks, n_img, plan->L * plan->K, plan->K, plan->H,
+                                                  plan->W, plan->d.ssim_weight, at<float>(plan, ws, R_DMU),
+                                                  at<float>(plan, ws, R_DEXX), at<float>(plan, ws, R_DEXY),
+                                                  at<float>(plan, ws, R_LOSS2), loss_out, s));
+    plan->paper_ready = true;
+    plan->saved_prop = u;
+    plan->saved_inten = I;
+    plan->saved_target = target;
+    plan->saved_masks = masks;
+    return CHRF_OK;
+  }
   st = asm_forward(plan, field, ws, prop_out, intensity_out, target, s);
   if (st != CHRF_OK) return st;
   if (target) {
@@ -567,17 +602,28 @@ chrf_status chrf_backward(chrf_plan* plan, const chrf_gaussians* g, const chrf_c
   if (g->n > 0 && (!out->means || !out->log_scales || !out->quats || !out->opacity || !out->amp || !out->phase))
     return fail(CHRF_EINVAL, "chrf_backward: NULL gradient array");
   if (dL_dI && !prop) return fail(CHRF_EINVAL, "chrf_backward: dL_dI needs the saved prop");
-  const bool have_prop_grad = dL_dI || dL_dprop;
-  if (!have_prop_grad && !plan->fused_ready && !dL_dfield)
-    return fail(CHRF_EINVAL, "chrf_backward: no incoming gradient (no dL_dI/dL_dprop/dL_dfield and no fused loss)");
   hipStream_t s = (hipStream_t)hip_stream;
   const int Nst = std::max(plan->N, 1);
   const AsmGeom geo = geom(plan);
   float2* y = at<float2>(plan, ws, R_Y);
   float2* x1 = at<float2>(plan, ws, R_X1);
+  if (!dL_dI && !dL_dprop && plan->paper_ready) {
+    // gradient of the paper's loss w.r.t. the intensities of the last forward
+    float* dldi = at<float>(plan, ws, R_DLDI);
+    RUN("loss_backward", launch_paper_loss_backward(plan->saved_inten, plan->saved_target, plan->saved_masks,
+                                                    plan->B * plan->L * plan->K, plan->L * plan->K, plan->K,
+                                                    plan->H, plan->W, plan->d.ssim_weight,
+                                                    at<float>(plan, ws, R_DMU), at<float>(plan, ws, R_DEXX),
+                                                    at<float>(plan, ws, R_DEXY), nullptr, dldi, s));
+    dL_dI = dldi;
+    prop = reinterpret_cast<const float*>(plan->saved_prop);
+  }
+  const bool have_prop_grad = dL_dI || dL_dprop;
+  if (!have_prop_grad && !plan->fused_ready && !dL_dfield)
+    return fail(CHRF_EINVAL, "chrf_backward: no incoming gradient (no dL_dI/dL_dprop/dL_dfield and no fused loss)");
   const float2* grad_field = reinterpret_cast<const float2*>(dL_dfield);
   if (have_prop_grad || plan->fused_ready) {
-    if (have_prop_grad)
+    if (have_prop_grad)  // (the fused spectra of an MSE forward are used only when no gradient is passed)
       RUN("rows_adjoint_in", launch_rows_adjoint_in(reinterpret_cast<const float2*>(prop), dL_dI,
                                                     reinterpret_cast<const float2*>(dL_dprop), y, geo, plan->frow, s));
     RUN("cols_adjoint", launch_cols_adjoint(y, x1, geo, plan->fcol, plan->cols_per_block, s));
@@ -652,6 +698,7 @@ chrf_status chrf_propagate(chrf_plan* plan, const float* field, void* ws, float*
                            void* hip_stream) {
   if (!plan || !field || !ws) return fail(CHRF_EINVAL, "chrf_propagate: NULL argument");
   plan->fused_ready = false;
+  plan->paper_ready = false;
   return asm_forward(plan, reinterpret_cast<const float2*>(field), ws, prop_out, intensity_out, nullptr,
                      (hipStream_t)hip_stream);
 }

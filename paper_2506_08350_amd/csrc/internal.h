@@ -138,6 +138,16 @@ struct RasterArgs {
 hipError_t launch_raster_forward(const RasterArgs& a, hipStream_t s);
 hipError_t launch_raster_backward(const RasterArgs& a, hipStream_t s);
 
+// The paper's training loss (masked reconstruction loss + SSIM term).
+int64_t loss_partial_elems(int n_img, int H, int W);
+hipError_t launch_paper_loss_forward(const float* I, const float* T, const uint8_t* masks, int n_img, int per_view,
+                                     int planes, int H, int W, float ssim_weight, float* dmu, float* dexx,
+                                     float* dexy, float* partial, float* loss_out, hipStream_t s);
+hipError_t launch_paper_loss_backward(const float* I, const float* T, const uint8_t* masks, int n_img, int per_view,
+                                      int planes, int H, int W, float ssim_weight, const float* dmu,
+                                      const float* dexx, const float* dexy, const float* grad_scale, float* dL_dI,
+                                      hipStream_t s);
+
 // Multi-layer mode (hard plane assignment).
 constexpr int kMaxLayers = 4;
 hipError_t launch_assign_layers(const float* logits, int n, int n_layers, uint8_t* layer_of, hipStream_t s);

@@ -161,6 +161,26 @@ def make_targets(shape, seed) -> np.ndarray:
     return rng.random(shape, dtype=np.float32)
 
 
+def make_plane_masks(n_views, n_planes, height, width, seed) -> np.ndarray:
+    """Binary plane masks uint8 [views, planes, H, W]: a smooth synthetic depth
+    map per view (a tilted plane plus random bumps) cut into n_planes equal
+    depth bins, so every pixel belongs to exactly one plane."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:height, 0:width].astype(np.float64)
+    out = np.zeros((n_views, n_planes, height, width), np.uint8)
+    for v in range(n_views):
+        d = rng.uniform(-1, 1) * xx / width + rng.uniform(-1, 1) * yy / height
+        for _ in range(6):
+            cx, cy = rng.uniform(0, width), rng.uniform(0, height)
+            s = rng.uniform(0.05, 0.3) * max(height, width)
+            d += rng.uniform(-1.5, 1.5) * np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2) / (2 * s * s))
+        lo, hi = d.min(), d.max()
+        q = np.minimum(((d - lo) / max(hi - lo, 1e-12) * n_planes).astype(np.int64), n_planes - 1)
+        for k in range(n_planes):
+            out[v, k] = q == k
+    return out
+
+
 def _c1():
     scene = make_gaussians(1000, 1, 1001)
     cam = identity_camera(128, 128, f=128)
@@ -176,6 +196,7 @@ def _c2(backward=False, seed=1002):
     w = Workload(name, scene, [cam], opt, backward=backward)
     if backward:
         w.targets = make_targets((1, 3, 4, 1080, 1920), seed + 10_000)
+        w.notes["masks_seed"] = seed + 30_000
     return w
 
 

@@ -19,7 +19,7 @@ from tests.gpu_helpers import announce, cplx, make_renderer, rel_l2, to_device
 pytestmark = pytest.mark.gpu
 
 
-def _problem(n=300, H=40, W=56, nlay=3, seed=71, views=(0.0, 11.0), logit_scale=1.0, n_lambda=2):
+def _problem(n=300, H=40, W=60, nlay=3, seed=71, views=(0.0, 11.0), logit_scale=1.0, n_lambda=2):
     sc = make_gaussians(n, n_lambda, seed, log_scale_mean=-3.0, log_scale_std=0.4)
     cams = yaw_cameras(views, (0.0, 0.0, 2.0), W, H, f=0.8 * W)
     lams = (639e-9, 532e-9, 473e-9)[:n_lambda]
@@ -105,7 +105,7 @@ def test_recording_is_the_adjoint_of_inverse_propagation():
     chrf_propagate_adjoint records layer fields into P (+Z_l); both against
     the oracle, and their dot-product identity."""
     announce("layered propagate / record")
-    H, W = 36, 44
+    H, W = 36, 48
     opt = Optics((639e-9, 473e-9), (0.4e-3, 1.2e-3, 2.5e-3), 8e-6, 2, 2)
     r = make_renderer([identity_camera(W, H)], opt, 1, tile=None, layered=True)
     rng = np.random.default_rng(5)

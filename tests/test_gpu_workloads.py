@@ -160,12 +160,19 @@ def test_four_views_2160p_2m_16_planes():
     gen = torch.Generator(device="cuda").manual_seed(1005 + 10_000)
     target = torch.rand((B, L, K, H, W), generator=gen, device="cuda")
     out = r.forward(params, cam_t, want_field=True, want_intensity=True, target=target)
-    grads = r.backward(params, cam_t)
     torch.cuda.synchronize()
     assert r.read_status()[0] == 0
     I = out["intensity"]
-    ref_loss = sum(float(((I[b].double() - target[b].double()) ** 2).sum()) for b in range(B)) / I.numel()
+    assert torch.isfinite(out["field"]).all() and torch.isfinite(I).all()
+    # the fused loss: per-row sums first, then the reduction
+    rows = ((I - target) ** 2).sum(dim=-1).double().reshape(-1)
+    part = r.region(_lib.REGION_LOSS_PARTIAL, torch.float32)[:rows.numel()].double()
+    bad = torch.nonzero(~torch.isclose(part, rows, rtol=1e-4, atol=1e-3)).reshape(-1)
+    assert bad.numel() == 0, (bad.numel(), bad[:8].tolist(), part[bad[:4]].tolist(), rows[bad[:4]].tolist())
+    ref_loss = float(rows.sum()) / I.numel()
     assert abs(float(out["loss"]) - ref_loss) < 1e-5 * ref_loss
+    grads = r.backward(params, cam_t)
+    torch.cuda.synchronize()
     _window_checks(w, out["field"], r)
     _tile_checks(w, r)
     for k in api.PARAM_NAMES:
