@@ -206,7 +206,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-table", action="store_true", help="also print the per-kernel table to stderr")
     ap.add_argument("--cols-per-block", type=int, default=0, help="column FFT pass: 2 or 4 columns per workgroup")
-    ap.add_argument("--tile", default=None, help="raster tile, e.g. 16x16, 16x8, 8x8 (default 16x16; 8x8 layered)")
+    ap.add_argument("--tile", default=None, help="raster tile, e.g. 16x16, 16x8, 8x8 (default 16x16)")
     ap.add_argument("--loss", default="mse", choices=["mse", "paper"],
                     help="training loss: the MSE (default) or the paper's masked reconstruction + SSIM loss")
     ap.add_argument("--no-fwd-rate", action="store_true",
@@ -247,7 +247,7 @@ def main(argv=None):
     params = {k: torch.from_numpy(a).cuda() for k, a in zip(api.PARAM_NAMES, sc.arrays())}
     if layered:
         params[api.LAYER_LOGITS] = torch.from_numpy(w.notes["logits"]).cuda()
-    tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else ((8, 8) if layered else (16, 16))
+    tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else (16, 16)
     masks = None
     if args.loss == "paper":
         masks = torch.from_numpy(scenegen.make_plane_masks(B, K, H, W, w.notes["masks_seed"])).cuda()

@@ -130,8 +130,7 @@ typedef struct chrf_grads {
  *                      that layer (per-layer transmittance and early
  *                      termination); the hologram is recorded as
  *                      P = sum_l ASM(U_l; +Z_l) and propagated back to every
- *                      layer, u_k = ASM(P; -Z_k), I_k = |u_k|^2.  Needs
- *                      8 x 8 tiles (0, 0 selects them).
+ *                      layer, u_k = ASM(P; -Z_k), I_k = |u_k|^2.
  *   loss_kind          loss computed by chrf_forward when a target is given:
  *                      0: MSE, the mean of (I - T)^2 over all elements (Eq. 17);
  *                      1: the paper's training loss (Sec. 4.1): the

@@ -100,7 +100,7 @@ class Renderer:
             d.distances[i] = float(z)
         d.k_sigma, d.alpha_min, d.alpha_max, d.t_min = k_sigma, alpha_min, alpha_max, t_min
         if tile is None:
-            tile = (8, 8) if layered else (16, 16)
+            tile = (16, 16)
         d.tile_w, d.tile_h = int(tile[0]), int(tile[1])
         d.cols_per_block = int(cols_per_block)
         d.layered = 1 if layered else 0

@@ -242,8 +242,7 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   if (!(d.ssim_weight >= 0) || !std::isfinite(d.ssim_weight)) return fail(CHRF_EINVAL, "plan: ssim_weight must be >= 0");
   if (d.layered && d.n_planes > kMaxLayers) return fail(CHRF_EUNSUPPORTED, "plan: a layered plan takes 1..4 layers");
   int tw = d.tile_w, th = d.tile_h;
-  if (tw == 0 && th == 0) tw = th = d.layered ? 8 : 16;
-  if (d.layered && (tw != 8 || th != 8)) return fail(CHRF_EUNSUPPORTED, "plan: a layered plan needs 8 x 8 tiles");
+  if (tw == 0 && th == 0) tw = th = 16;
   if (tw <= 0 || th <= 0 || tw % 8 || th % 8 || (tw * th != 64 && tw * th != 128 && tw * th != 256))
     return fail(CHRF_EINVAL, "plan: tile_w, tile_h must be multiples of 8 with tile_w * tile_h in {64, 128, 256}");
 

@@ -12,7 +12,7 @@ namespace chrf {
 // the pixel (record loads, the gradient reduction over the wave) are shared by
 // PPT pixels.  Records are staged in LDS in batches of kBatch pairs.
 constexpr int kLanes = 64;
-constexpr int kBatch = 128;
+constexpr int kBatch = 64;
 
 struct TileGeom {
   int view, tx, ty;
@@ -61,7 +61,7 @@ struct Stage {
 
 template <int NL>
 __device__ inline void stage_records(Stage<NL>& st, const RasterArgs& a, uint32_t first, int cnt, bool reverse) {
-  for (int i = threadIdx.x; i < cnt; i += kLanes) {
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
     const uint32_t idx = reverse ? first - i : first + i;
     const uint32_t rid = a.pair_val[idx];
     st.rid[i] = rid;

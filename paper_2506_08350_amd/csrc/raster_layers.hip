@@ -18,8 +18,11 @@
 // to the per-(view, Gaussian) accumulators; k_logits_backward then applies
 // the straight-through weights softmax(logits / tau).
 //
-// One wave per 8x8 tile, one pixel per lane: the per-layer state (T, B, G per
-// wavelength) stays in registers.
+// One workgroup per tile with one wave per 8x8 block of the tile and one pixel
+// per lane, so the per-layer state (T, B, G per wavelength) stays in
+// registers; the waves share the LDS staging of the tile's records, and in
+// the backward each wave's reduced gradient of a pair is added to the
+// workgroup's LDS row of that pair before one global atomic per value.
 #include "raster_common.h"
 
 namespace chrf {
@@ -47,20 +50,29 @@ struct StageL {
 template <int NL>
 __device__ inline void stage_records_l(StageL<NL>& st, const RasterArgs& a, uint32_t first, int cnt, bool reverse) {
   stage_records<NL>(st.s, a, first, cnt, reverse);
-  for (int i = threadIdx.x; i < cnt; i += kLanes) {
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
     const uint32_t idx = reverse ? first - i : first + i;
     const uint32_t g = a.pair_val[idx] % (uint32_t)a.n_stride;
     st.lay[i] = a.layer_of[g];
   }
 }
 
-template <int NL, int NLAY>
-__global__ __launch_bounds__(kLanes) void k_raster_layers_fwd(RasterArgs a) {
+// Pixel of this lane: wave w covers the w-th 8x8 block of the tile.
+__device__ inline void layer_pixel(const RasterArgs& a, const TileGeom& t, int& px, int& py, int& bx, int& by) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int bpr = a.tile_w >> 3;
+  bx = t.tx * a.tile_w + (w % bpr) * 8;
+  by = t.ty * a.tile_h + (w / bpr) * 8;
+  px = bx + (lane & 7);
+  py = by + (lane >> 3);
+}
+
+template <int NL, int NLAY, int NWAVE>
+__global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_fwd(RasterArgs a) {
   __shared__ StageL<NL> st;
   const TileGeom t = tile_of(a);
-  int px, py;
-  pixel_of<1>(a, t, 0, px, py);
-  const int bx = t.tx * 8, by = t.ty * 8;
+  int px, py, bx, by;
+  layer_pixel(a, t, px, py, bx, by);
   const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
   const bool inside = px < a.width && py < a.height;
   float T[NLAY];
@@ -78,49 +90,50 @@ __global__ __launch_bounds__(kLanes) void k_raster_layers_fwd(RasterArgs a) {
   uint32_t walk_end = inside ? rg.y : 0u;
   const float half_k2 = 0.5f * a.k_sigma * a.k_sigma;
   for (uint32_t start = rg.x; start < rg.y; start += kBatch) {
-    if (__all(live == 0u)) break;
+    if (!__syncthreads_or(live != 0u)) break;   // every layer of every pixel has stopped
     const int cnt = (int)min(rg.y - start, (uint32_t)kBatch);
-    __syncthreads();
     stage_records_l<NL>(st, a, start, cnt, false);
     __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
-      const int4 rc = st.s.rc[j];
-      if (!rect_hits_block(rc, bx, by)) continue;
-      const int lay = __builtin_amdgcn_readfirstlane(st.lay[j]);
-      if (!((live >> lay) & 1u)) continue;
-      const float4 g0 = st.s.g0[j];
-      const float4 g1 = st.s.g1[j];
-      const float dx = pxf - g0.x, dy = pyf - g0.y;
-      const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
-      const bool in_rect = (unsigned)(px - rc.x) <= (unsigned)rc.y && (unsigned)(py - rc.z) <= (unsigned)rc.w;
-      const float aval = fminf(a.alpha_max, g1.y * __expf(-power));
-      if (in_rect && power <= half_k2 && aval >= a.alpha_min) {
+    if (__any(live != 0u)) {
+      for (int j = 0; j < cnt; ++j) {
+        const int4 rc = st.s.rc[j];
+        if (!rect_hits_block(rc, bx, by)) continue;
+        const int lay = __builtin_amdgcn_readfirstlane(st.lay[j]);
+        if (!((live >> lay) & 1u)) continue;
+        const float4 g0 = st.s.g0[j];
+        const float4 g1 = st.s.g1[j];
+        const float dx = pxf - g0.x, dy = pyf - g0.y;
+        const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
+        const bool in_rect = (unsigned)(px - rc.x) <= (unsigned)rc.y && (unsigned)(py - rc.z) <= (unsigned)rc.w;
+        const float aval = fminf(a.alpha_max, g1.y * __expf(-power));
+        if (in_rect && power <= half_k2 && aval >= a.alpha_min) {
 #pragma unroll
-        for (int q = 0; q < NLAY; ++q) {
-          if (q != lay) continue;   // wave-uniform
-          const float wgt = aval * T[q];
+          for (int q = 0; q < NLAY; ++q) {
+            if (q != lay) continue;   // wave-uniform
+            const float wgt = aval * T[q];
 #pragma unroll
-          for (int l = 0; l < NL; ++l) {
-            const float2 v = st.s.v[l][j];
-            U[q][l].x += v.x * wgt;
-            U[q][l].y += v.y * wgt;
-          }
-          T[q] *= 1.0f - aval;
-          if (T[q] < a.t_min) {
-            stop[q] = start + j + 1;
-            live &= ~(1u << q);
-            if (live == 0u) walk_end = start + j + 1;
+            for (int l = 0; l < NL; ++l) {
+              const float2 v = st.s.v[l][j];
+              U[q][l].x += v.x * wgt;
+              U[q][l].y += v.y * wgt;
+            }
+            T[q] *= 1.0f - aval;
+            if (T[q] < a.t_min) {
+              stop[q] = start + j + 1;
+              live &= ~(1u << q);
+              if (live == 0u) walk_end = start + j + 1;
+            }
           }
         }
       }
     }
+    __syncthreads();   // the next batch overwrites the staged records
   }
   if (!inside) return;
   const size_t plane = (size_t)a.height * a.width;
   const size_t pix = (size_t)py * a.width + px;
 #pragma unroll
   for (int q = 0; q < NLAY; ++q) {
-    if (q >= a.n_layers) break;
     const size_t lp = ((size_t)t.view * a.n_layers + q) * plane + pix;
 #pragma unroll
     for (int l = 0; l < NL; ++l)
@@ -131,17 +144,17 @@ __global__ __launch_bounds__(kLanes) void k_raster_layers_fwd(RasterArgs a) {
   a.last[(size_t)t.view * plane + pix] = walk_end;
 }
 
-template <int NL, int NLAY>
-__global__ __launch_bounds__(kLanes) void k_raster_layers_bwd(RasterArgs a) {
+template <int NL, int NLAY, int NWAVE>
+__global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_bwd(RasterArgs a) {
   constexpr int G2 = 6 + 2 * NL + NLAY;
   constexpr int G2P = (G2 + 3) & ~3;
   __shared__ StageL<NL> st;
   __shared__ float s_grad[kBatch][G2];
+  __shared__ uint32_t s_last[NWAVE];
   const TileGeom t = tile_of(a);
-  const int lane = threadIdx.x;
-  int px, py;
-  pixel_of<1>(a, t, 0, px, py);
-  const int bx = t.tx * 8, by = t.ty * 8;
+  const int lane = threadIdx.x & 63;
+  int px, py, bx, by;
+  layer_pixel(a, t, px, py, bx, by);
   const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
   const bool inside = px < a.width && py < a.height;
   const float scale = a.grad_scale ? *a.grad_scale : 1.0f;
@@ -160,7 +173,7 @@ __global__ __launch_bounds__(kLanes) void k_raster_layers_bwd(RasterArgs a) {
       G[q][l] = make_float2(0.f, 0.f);
       Bacc[q][l] = make_float2(0.f, 0.f);
     }
-    if (inside && q < a.n_layers) {
+    if (inside) {
       const size_t lp = ((size_t)t.view * a.n_layers + q) * plane + pix;
       T[q] = a.t_final[lp];
       stop[q] = a.layer_stop[lp];
@@ -172,93 +185,105 @@ __global__ __launch_bounds__(kLanes) void k_raster_layers_bwd(RasterArgs a) {
     }
   }
   if (inside) mylast = a.last[(size_t)t.view * plane + pix];
-  uint32_t tile_last = mylast;
-  for (int off = 32; off > 0; off >>= 1) tile_last = max(tile_last, (uint32_t)__shfl_xor((int)tile_last, off, 64));
+  uint32_t wave_last = mylast;
+  for (int off = 32; off > 0; off >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, off, 64));
+  if (lane == 0) s_last[threadIdx.x >> 6] = wave_last;
+  for (int i = threadIdx.x; i < kBatch * G2; i += blockDim.x) (&s_grad[0][0])[i] = 0.f;
+  __syncthreads();
+  uint32_t tile_last = 0;
+#pragma unroll
+  for (int w = 0; w < NWAVE; ++w) tile_last = max(tile_last, s_last[w]);
   const uint2 rg = a.ranges[blockIdx.x];
   const float half_k2 = 0.5f * a.k_sigma * a.k_sigma;
-  for (int i = lane; i < kBatch * G2; i += kLanes) (&s_grad[0][0])[i] = 0.f;
 
   for (uint32_t top = tile_last; top > rg.x;) {
     const int cnt = (int)min(top - rg.x, (uint32_t)kBatch);
-    __syncthreads();
     stage_records_l<NL>(st, a, top - 1, cnt, true);   // st[j] is the j-th pair from the back
     __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
-      const int4 rc = st.s.rc[j];
-      if (!rect_hits_block(rc, bx, by)) continue;
-      const uint32_t pidx = top - 1 - j;
-      const int lay = __builtin_amdgcn_readfirstlane(st.lay[j]);
-      const float4 g0 = st.s.g0[j];
-      const float4 g1 = st.s.g1[j];
-      float gr[G2P];
+    if (top - cnt < wave_last) {   // this wave has work in the batch
+      for (int j = 0; j < cnt; ++j) {
+        const int4 rc = st.s.rc[j];
+        if (!rect_hits_block(rc, bx, by)) continue;
+        const uint32_t pidx = top - 1 - j;
+        const int lay = __builtin_amdgcn_readfirstlane(st.lay[j]);
+        const float4 g0 = st.s.g0[j];
+        const float4 g1 = st.s.g1[j];
+        float gr[G2P];
 #pragma unroll
-      for (int c = 0; c < G2P; ++c) gr[c] = 0.f;
-      const float dx = pxf - g0.x, dy = pyf - g0.y;
-      const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
-      const bool in_rect = (unsigned)(px - rc.x) <= (unsigned)rc.y && (unsigned)(py - rc.z) <= (unsigned)rc.w;
-      const float Gv = __expf(-power);
-      const float oG = g1.y * Gv;
-      const bool clamped = oG > a.alpha_max;
-      const float aval = clamped ? a.alpha_max : oG;
-      const bool sup = pidx < mylast && in_rect && power <= half_k2 && aval >= a.alpha_min;
-      if (sup) {
-        float dLda = 0.f;
+        for (int c = 0; c < G2P; ++c) gr[c] = 0.f;
+        const float dx = pxf - g0.x, dy = pyf - g0.y;
+        const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
+        const bool in_rect = (unsigned)(px - rc.x) <= (unsigned)rc.y && (unsigned)(py - rc.z) <= (unsigned)rc.w;
+        const float Gv = __expf(-power);
+        const float oG = g1.y * Gv;
+        const bool clamped = oG > a.alpha_max;
+        const float aval = clamped ? a.alpha_max : oG;
+        const bool sup = pidx < mylast && in_rect && power <= half_k2 && aval >= a.alpha_min;
+        if (sup) {
+          float dLda = 0.f;
 #pragma unroll
-        for (int q = 0; q < NLAY; ++q) {
-          if (pidx >= stop[q]) continue;   // layer q had stopped before this pair
-          const bool own = q == lay;       // wave-uniform
-          const float Tb = own ? T[q] * __builtin_amdgcn_rcpf(1.0f - aval) : T[q];
-          float sq = 0.f;
-#pragma unroll
-          for (int l = 0; l < NL; ++l) {
-            const float2 v = st.s.v[l][j];
-            sq += G[q][l].x * (v.x - Bacc[q][l].x) + G[q][l].y * (v.y - Bacc[q][l].y);
-          }
-          sq *= Tb;
-          gr[6 + 2 * NL + q] = aval * sq;
-          if (own) {
-            dLda = sq;
-            const float aT = aval * Tb;
+          for (int q = 0; q < NLAY; ++q) {
+            if (pidx >= stop[q]) continue;   // layer q had stopped before this pair
+            const bool own = q == lay;       // wave-uniform
+            const float Tb = own ? T[q] * __builtin_amdgcn_rcpf(1.0f - aval) : T[q];
+            float sq = 0.f;
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
               const float2 v = st.s.v[l][j];
-              gr[6 + 2 * l] = aT * G[q][l].x;
-              gr[7 + 2 * l] = aT * G[q][l].y;
-              Bacc[q][l].x = aval * v.x + (1.0f - aval) * Bacc[q][l].x;
-              Bacc[q][l].y = aval * v.y + (1.0f - aval) * Bacc[q][l].y;
+              sq += G[q][l].x * (v.x - Bacc[q][l].x) + G[q][l].y * (v.y - Bacc[q][l].y);
             }
-            T[q] = Tb;
+            sq *= Tb;
+            gr[6 + 2 * NL + q] = aval * sq;
+            if (own) {
+              dLda = sq;
+              const float aT = aval * Tb;
+#pragma unroll
+              for (int l = 0; l < NL; ++l) {
+                const float2 v = st.s.v[l][j];
+                gr[6 + 2 * l] = aT * G[q][l].x;
+                gr[7 + 2 * l] = aT * G[q][l].y;
+                Bacc[q][l].x = aval * v.x + (1.0f - aval) * Bacc[q][l].x;
+                Bacc[q][l].y = aval * v.y + (1.0f - aval) * Bacc[q][l].y;
+              }
+              T[q] = Tb;
+            }
+          }
+          if (!clamped) {
+            gr[5] = Gv * dLda;
+            const float dpow = -aval * dLda;
+            gr[2] = 0.5f * dx * dx * dpow;
+            gr[3] = dx * dy * dpow;
+            gr[4] = 0.5f * dy * dy * dpow;
+            gr[0] = -(g0.z * dx + g0.w * dy) * dpow;
+            gr[1] = -(g0.w * dx + g1.x * dy) * dpow;
           }
         }
-        if (!clamped) {
-          gr[5] = Gv * dLda;
-          const float dpow = -aval * dLda;
-          gr[2] = 0.5f * dx * dx * dpow;
-          gr[3] = dx * dy * dpow;
-          gr[4] = 0.5f * dy * dy * dpow;
-          gr[0] = -(g0.z * dx + g0.w * dy) * dpow;
-          gr[1] = -(g0.w * dx + g1.x * dy) * dpow;
-        }
-      }
-      if (__ballot(sup) != 0ull) {
-        wave_sums_by_row<G2P>(gr);
-        if ((lane & 15) == 15) {
-          const int row = lane >> 4;
+        if (__ballot(sup) != 0ull) {
+          wave_sums_by_row<G2P>(gr);
+          if ((lane & 15) == 15) {
+            const int row = lane >> 4;
 #pragma unroll
-          for (int k = 0; k < G2P / 4; ++k) {
-            const int c = k + row * (G2P / 4);
-            if (c < G2) s_grad[j][c] = gr[k];
+            for (int k = 0; k < G2P / 4; ++k) {
+              const int c = k + row * (G2P / 4);
+              if (c < G2) {
+                if (NWAVE == 1)
+                  s_grad[j][c] = gr[k];
+                else
+                  atomicAdd(&s_grad[j][c], gr[k]);
+              }
+            }
           }
         }
       }
     }
     __syncthreads();
-    for (int i = lane; i < cnt * G2; i += kLanes) {
+    for (int i = threadIdx.x; i < cnt * G2; i += blockDim.x) {
       const int r = i / G2, c = i - r * G2;
       const float sum = s_grad[r][c];
       if (sum != 0.f) unsafeAtomicAdd(a.grad2d + (size_t)st.s.rid[r] * a.g2stride + c, sum);
       s_grad[r][c] = 0.f;
     }
+    __syncthreads();   // the next batch overwrites the staged records
     top -= cnt;
   }
 }
@@ -305,29 +330,29 @@ hipError_t launch_logits_backward(const float* logits, const float* grad2d, int 
   return hipGetLastError();
 }
 
+#define CHRF_LAYERS_CASE(KERNEL, NL, NLAY)                                                    \
+  case NL * 8 + NLAY:                                                                        \
+    if (nw == 1) KERNEL<NL, NLAY, 1><<<blocks, 64, 0, s>>>(a);                               \
+    else if (nw == 2) KERNEL<NL, NLAY, 2><<<blocks, 128, 0, s>>>(a);                         \
+    else KERNEL<NL, NLAY, 4><<<blocks, 256, 0, s>>>(a);                                      \
+    break;
+
 #define CHRF_LAYERS_DISPATCH(KERNEL)                                                          \
   const int blocks = a.n_views * a.tiles_x * a.tiles_y;                                      \
   if (blocks == 0) return hipSuccess;                                                        \
-  if (a.tile_w != 8 || a.tile_h != 8 || a.n_layers < 1 || a.n_layers > kMaxLayers ||         \
-      a.n_lambda < 1 || a.n_lambda > 4)                                                       \
+  const int nw = a.tile_w * a.tile_h / 64;                                                   \
+  if ((nw != 1 && nw != 2 && nw != 4) || a.tile_w % 8 || a.tile_h % 8 || a.n_layers < 1 ||   \
+      a.n_layers > kMaxLayers || a.n_lambda < 1 || a.n_lambda > 4)                            \
     return hipErrorInvalidValue;                                                             \
   switch (a.n_lambda * 8 + a.n_layers) {                                                     \
-    case 9: KERNEL<1, 1><<<blocks, kLanes, 0, s>>>(a); break;                                \
-    case 10: KERNEL<1, 2><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 11: KERNEL<1, 3><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 12: KERNEL<1, 4><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 17: KERNEL<2, 1><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 18: KERNEL<2, 2><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 19: KERNEL<2, 3><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 20: KERNEL<2, 4><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 25: KERNEL<3, 1><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 26: KERNEL<3, 2><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 27: KERNEL<3, 3><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 28: KERNEL<3, 4><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 33: KERNEL<4, 1><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 34: KERNEL<4, 2><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 35: KERNEL<4, 3><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 36: KERNEL<4, 4><<<blocks, kLanes, 0, s>>>(a); break;                               \
+    CHRF_LAYERS_CASE(KERNEL, 1, 1) CHRF_LAYERS_CASE(KERNEL, 1, 2)                            \
+    CHRF_LAYERS_CASE(KERNEL, 1, 3) CHRF_LAYERS_CASE(KERNEL, 1, 4)                            \
+    CHRF_LAYERS_CASE(KERNEL, 2, 1) CHRF_LAYERS_CASE(KERNEL, 2, 2)                            \
+    CHRF_LAYERS_CASE(KERNEL, 2, 3) CHRF_LAYERS_CASE(KERNEL, 2, 4)                            \
+    CHRF_LAYERS_CASE(KERNEL, 3, 1) CHRF_LAYERS_CASE(KERNEL, 3, 2)                            \
+    CHRF_LAYERS_CASE(KERNEL, 3, 3) CHRF_LAYERS_CASE(KERNEL, 3, 4)                            \
+    CHRF_LAYERS_CASE(KERNEL, 4, 1) CHRF_LAYERS_CASE(KERNEL, 4, 2)                            \
+    CHRF_LAYERS_CASE(KERNEL, 4, 3) CHRF_LAYERS_CASE(KERNEL, 4, 4)                            \
     default: return hipErrorInvalidValue;                                                    \
   }                                                                                          \
   return hipGetLastError();

@@ -12,7 +12,7 @@
 //
 // The radix sort is LSD with 8-bit digits; every pass counts per-block digit
 // histograms of the keys in their current order, scans them over (digit,
-// block) and scatters stably.  (The per-block split of a pass depends on the
+// block) and scatters stably through an LDS reorder.  (The per-block split of a pass depends on the
 // permutation the previous pass produced, so histograms of later passes
 // cannot be taken from the input order.)  Ranks inside a
 // block come from wave ballots: a lane's rank among equal digits is the
@@ -157,6 +157,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* __restrict
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// Stable scatter of one pass.  Each block ranks its 16 x 256 keys (wave
+// ballots per round, counts of earlier waves and rounds in LDS), places them
+// in LDS in block-local digit order, then writes them out in that order: the
+// keys of one digit leave the block as one contiguous run, so the stores are
+// coalesced instead of one scattered 4-byte store per key.
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restrict__ keys_in,
                                                                 const uint32_t* __restrict__ vals_in,
@@ -168,6 +173,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[NW][256];
   __shared__ uint32_t goff[256];
+  __shared__ uint32_t lstart[256];
+  __shared__ uint32_t wsum[NW];
+  __shared__ K skey[kSortTile];
+  __shared__ uint32_t sval[kSortTile];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n = live_count(n_max, n_dev);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
@@ -177,17 +186,21 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
   goff[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  K key[kSortItems];
+  uint32_t val[kSortItems], dig[kSortItems], rank[kSortItems];
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t idx = base + (int64_t)r * kSortThreads + tid;
     const bool valid = idx < n;
-    K key = 0;
-    uint32_t val = 0;
-    uint32_t d = 0;
+    key[r] = 0;
+    val[r] = 0;
+    dig[r] = 0;
     if (valid) {
-      key = keys_in[idx];
-      val = vals_in[idx];
-      d = (uint32_t)(key >> shift) & 255u;
+      key[r] = keys_in[idx];
+      val[r] = vals_in[idx];
+      dig[r] = (uint32_t)(key[r] >> shift) & 255u;
     }
+    const uint32_t d = dig[r];
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
@@ -198,15 +211,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
     const uint32_t lower = __popcll(peers & lt_mask);
     if (valid && lower == 0) wcnt[wave][d] = __popcll(peers);
     __syncthreads();
-    if (valid) {
-      uint32_t before = 0;
-      for (int w = 0; w < wave; ++w) before += wcnt[w][d];
-      const uint32_t pos = goff[d] + run[d] + before + lower;
-      if (pos < (uint64_t)n) {   // always true for consistent offsets; keeps every write in bounds
-        keys_out[pos] = key;
-        vals_out[pos] = val;
-      }
-    }
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wcnt[w][d];
+    rank[r] = valid ? run[d] + before + lower : ~0u;   // rank among the block's keys of digit d
     __syncthreads();
     uint32_t add = 0;
     for (int w = 0; w < NW; ++w) {
@@ -215,6 +222,29 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
     }
     run[tid] += add;
     __syncthreads();
+  }
+  // block-local start of every digit
+  uint32_t tot;
+  lstart[tid] = block_exclusive_scan<uint32_t>(run[tid], wsum, &tot);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (rank[r] != ~0u) {
+      const uint32_t p = lstart[dig[r]] + rank[r];
+      skey[p] = key[r];
+      sval[p] = val[r];
+    }
+  }
+  __syncthreads();
+  const int nv = (int)(n - base < kSortTile ? n - base : kSortTile);
+  for (int i = tid; i < nv; i += kSortThreads) {
+    const K k = skey[i];
+    const uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const uint32_t pos = goff[d] + (uint32_t)i - lstart[d];
+    if (pos < (uint64_t)n) {   // always true for consistent offsets; keeps every write in bounds
+      keys_out[pos] = k;
+      vals_out[pos] = sval[i];
+    }
   }
 }
 

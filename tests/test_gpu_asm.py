@@ -100,3 +100,34 @@ def test_full_size_workload_geometry():
         ref = oracle.propagate(U[0, li], lams[li], zs[ki], 8e-6, 2, 2)
         got = cplx(prop[0, li, ki])
         assert rel_l2(got, ref) < TOL
+
+
+@pytest.mark.parametrize("W", [2560, 3840])
+def test_wide_rows_propagation_and_fused_loss(W):
+    """Rows whose two LDS buffers exceed 64 KiB (generic transforms of 5120 and
+    7680 points): one propagated plane against the oracle, and the fused MSE
+    row sums of an empty scene, whose intensities are zero, against the sums of
+    the squared targets."""
+    from paper_2506_08350_amd import _lib, api
+    from scenegen import make_gaussians
+    from tests.gpu_helpers import to_device
+
+    announce(f"wide rows W={W}")
+    H = 6
+    opt = Optics((515e-9,), (1e-3, 2e-3), 8e-6, 2, 2)
+    cam = identity_camera(W, H)
+    r = make_renderer([cam], opt, 4)
+    U = _field((1, 1, H, W), 11)
+    prop, _ = r.propagate(_to_gpu(U), want_intensity=False)
+    torch.cuda.synchronize()
+    assert rel_l2(cplx(prop[0, 0, 1]), oracle.propagate(U[0, 0], 515e-9, 2e-3, 8e-6, 2, 2)) < TOL
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    tgt = torch.rand((1, 1, 2, H, W), generator=gen, device="cuda")
+    out = r.forward(to_device(make_gaussians(0, 1, 9)), api.pack_cameras([cam]), want_field=False,
+                    want_intensity=True, target=tgt)
+    torch.cuda.synchronize()
+    assert float(out["intensity"].abs().max()) == 0.0
+    part = r.region(_lib.REGION_LOSS_PARTIAL, torch.float32)[:2 * H].double()
+    rows = (tgt.double() ** 2).sum(-1).reshape(-1)
+    assert torch.allclose(part, rows, rtol=1e-5), (part[:4].tolist(), rows[:4].tolist())
+    assert abs(float(out["loss"]) - float((tgt.double() ** 2).mean())) < 1e-5

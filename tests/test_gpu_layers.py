@@ -129,10 +129,22 @@ def test_recording_is_the_adjoint_of_inverse_propagation():
     assert abs(lhs - rhs) / abs(lhs) < 1e-5
 
 
-def test_layered_plan_rejects_wide_tiles_and_too_many_layers():
-    opt3 = Optics((515e-9,), (1e-3, 2e-3, 3e-3), 8e-6, 2, 2)
-    with pytest.raises(_lib.ChrfError):
-        make_renderer([identity_camera(32, 32)], opt3, 10, tile=(16, 16), layered=True)
+@pytest.mark.parametrize("tile", [(8, 8), (16, 8), (32, 8)])
+def test_layered_fields_do_not_depend_on_the_tile(tile):
+    """Waves of one workgroup share a tile's records; every tile shape gives
+    the same layer fields, bit for bit, as 16 x 16."""
+    announce(f"layered tile invariance {tile}")
+    sc, cams, opt, logits, tg = _problem(seed=77)
+    outs = []
+    for tl in ((16, 16), tile):
+        r = make_renderer(cams, opt, sc.n, tile=tl, layered=True)
+        r.forward(_params(sc, logits), api.pack_cameras(cams), want_field=True)
+        torch.cuda.synchronize()
+        outs.append(r.region(_lib.REGION_LAYER_FIELDS, torch.float32).clone())
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_layered_plan_rejects_too_many_layers():
     opt5 = Optics((515e-9,), tuple(np.linspace(1e-3, 3e-3, 5)), 8e-6, 2, 2)
     with pytest.raises(_lib.ChrfError):
         make_renderer([identity_camera(32, 32)], opt5, 10, tile=None, layered=True)

@@ -170,9 +170,14 @@ def test_four_views_2160p_2m_16_planes():
     bad = torch.nonzero(~torch.isclose(part, rows, rtol=1e-4, atol=1e-3)).reshape(-1)
     assert bad.numel() == 0, (bad.numel(), bad[:8].tolist(), part[bad[:4]].tolist(), rows[bad[:4]].tolist())
     ref_loss = float(rows.sum()) / I.numel()
-    assert abs(float(out["loss"]) - ref_loss) < 1e-5 * ref_loss
+    loss_before = float(out["loss"])
+    assert abs(loss_before - ref_loss) < 1e-5 * ref_loss
+    sums_before = [float(t.double().sum()) for t in (I, target)]
     grads = r.backward(params, cam_t)
     torch.cuda.synchronize()
+    # the backward leaves every caller buffer it does not own untouched
+    assert float(out["loss"]) == loss_before
+    assert [float(t.double().sum()) for t in (I, target)] == sums_before
     _window_checks(w, out["field"], r)
     _tile_checks(w, r)
     for k in api.PARAM_NAMES:
