@@ -140,6 +140,7 @@ typedef struct chrf_grads {
  *                      window, sigma 1.5, C1 = 0.01^2, C2 = 0.03^2, zero
  *                      padding; one SSIM per view, wavelength and plane)
  *   ssim_weight        lambda_1 of the SSIM term (0.005 in the paper)
+ *   phase_only         1: reserve the workspace of chrf_phase_only_step
  */
 typedef struct chrf_plan_desc {
   int32_t height, width;
@@ -157,7 +158,8 @@ typedef struct chrf_plan_desc {
   int32_t layered;
   int32_t loss_kind;
   float ssim_weight;
-  int32_t reserved[4];
+  int32_t phase_only;
+  int32_t reserved[3];
 } chrf_plan_desc;
 
 /* Named regions of the workspace, for inspection by tests and tools. */
@@ -259,6 +261,32 @@ chrf_status chrf_propagate(chrf_plan* plan, const float* field, void* workspace,
  */
 chrf_status chrf_propagate_adjoint(chrf_plan* plan, const float* grad_prop, void* workspace, float* grad_field,
                                    void* hip_stream);
+
+/*
+ * Phase-only hologram conversion, one loss/gradient evaluation (the paper's
+ * phase-only conversion: a phase-only hologram P_phi = exp(j phi) and the
+ * complex hologram P are propagated to the same depth layers and compared).
+ * The plan's propagation (chrf_propagate) maps P_phi to
+ * V [n_views][n_lambda][n_planes][H][W]; the loss is
+ *   mean |V - U|^2 + ssim_weight * (1 - mean SSIM over the real and the
+ *   imaginary parts of every (view, wavelength, plane) image),
+ * and dphi = Im(G exp(-j phi)) with G the adjoint propagation of dL/dV.
+ *   targets   complex [n_views][n_lambda][n_planes][H][W]: U, e.g. chrf_propagate of P
+ *   phi       float [n_views][n_lambda][H][W]
+ *   loss_out  device float scalar;  dphi  float, same shape as phi
+ * Needs a plan created with phase_only = 1.  Overwrites the workspace state a
+ * chrf_forward left for chrf_backward.
+ */
+chrf_status chrf_phase_only_step(chrf_plan* plan, const float* targets, const float* phi, void* workspace,
+                                 float* loss_out, float* dphi, void* hip_stream);
+
+/*
+ * One Adam step (Kingma and Ba, 2015) on n device floats, in place:
+ * m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
+ * x -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), step t >= 1.
+ */
+chrf_status chrf_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, float lr, float beta1,
+                           float beta2, float eps, int32_t step, void* hip_stream);
 
 /* Synchronise the stream and report the last forward's pair-list status:
  * CHRF_OK, or CHRF_ECAPACITY with *pairs_needed set. */

@@ -37,7 +37,7 @@ EXPORTED = [
     "chrf_create", "chrf_destroy", "chrf_last_error", "chrf_version", "chrf_plan_create",
     "chrf_plan_destroy", "chrf_plan_workspace_bytes", "chrf_plan_region", "chrf_forward",
     "chrf_backward", "chrf_propagate", "chrf_propagate_adjoint", "chrf_read_status",
-    "chrf_timing_enable", "chrf_timing_report",
+    "chrf_timing_enable", "chrf_timing_report", "chrf_phase_only_step", "chrf_adam_step",
 ]
 
 
@@ -64,7 +64,7 @@ class PlanDesc(C.Structure):
                 ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
                 ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("cols_per_block", C.c_int32),
                 ("layered", C.c_int32), ("loss_kind", C.c_int32), ("ssim_weight", C.c_float),
-                ("reserved", C.c_int32 * 4)]
+                ("phase_only", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class ChrfError(RuntimeError):
@@ -105,6 +105,8 @@ def load(path: str | None = None):
         "chrf_propagate": (i32, [vp, vp, vp, vp, vp, vp]),
         "chrf_propagate_adjoint": (i32, [vp, vp, vp, vp, vp]),
         "chrf_read_status": (i32, [vp, vp, C.POINTER(i64), vp]),
+        "chrf_phase_only_step": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+        "chrf_adam_step": (i32, [vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp]),
         "chrf_timing_enable": (i32, [vp, C.c_int]),
         "chrf_timing_report": (i32, [vp, C.c_char_p, sz]),
     }

@@ -76,7 +76,8 @@ class Renderer:
 
     def __init__(self, height, width, optics: Optics, n_views=1, max_gaussians=1, n_lambda=None,
                  max_pairs=0, k_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
-                 tile=None, cols_per_block=0, layered=False, loss="mse", ssim_weight=0.005, device=0):
+                 tile=None, cols_per_block=0, layered=False, loss="mse", ssim_weight=0.005, phase_only=False,
+                 device=0):
         """layered=True: multi-layer hologram with one layer per entry of
         optics.distances (the layer-to-hologram distances Z_l); the Gaussians
         then carry "logits" [N, layers] and the forward's "field" is the
@@ -109,6 +110,7 @@ class Renderer:
             raise ValueError(f"unknown loss {loss!r}")
         d.loss_kind = 1 if loss == "paper" else 0
         d.ssim_weight = float(ssim_weight)
+        d.phase_only = 1 if phase_only else 0
         self.loss = loss
         self.desc = d
         h = C.c_void_p()
@@ -215,11 +217,47 @@ class Renderer:
                                       _stream()))
         return prop, inten
 
+    def phase_only_step(self, targets: torch.Tensor, phi: torch.Tensor):
+        """Loss and dL/dphi of the phase-only hologram exp(j phi) against the
+        propagated target fields (plan created with phase_only=True)."""
+        assert targets.shape == (self.B, self.L, self.K, self.H, self.W, 2) and targets.is_contiguous()
+        assert phi.shape == (self.B, self.L, self.H, self.W) and phi.is_contiguous()
+        loss = torch.empty((), dtype=torch.float32, device=self.device)
+        dphi = torch.empty_like(phi)
+        check(self.lib.chrf_phase_only_step(self.plan, _ptr(targets), _ptr(phi), _ptr(self.workspace), _ptr(loss),
+                                            _ptr(dphi), _stream()))
+        return loss, dphi
+
+    def convert_phase_only(self, hologram: torch.Tensor, steps=200, lr=0.05, phi0=None):
+        """Phase-only conversion of a complex hologram [B, L, H, W, 2]: Adam on
+        phi (library kernels for the loss, gradient and update), starting from
+        the hologram's own phase.  Returns (phi, losses)."""
+        targets, _ = self.propagate(hologram, want_intensity=False)
+        phi = (torch.atan2(hologram[..., 1], hologram[..., 0]) if phi0 is None else phi0).contiguous().clone()
+        m = torch.zeros_like(phi)
+        v = torch.zeros_like(phi)
+        losses = []
+        for t in range(1, steps + 1):
+            loss, dphi = self.phase_only_step(targets, phi)
+            adam_step(phi, dphi, m, v, lr, step=t)
+            losses.append(loss)
+        return phi, torch.stack(losses)
+
     def propagate_adjoint(self, grad_prop: torch.Tensor):
         out = torch.empty((self.B, self.L, self.H, self.W, 2), dtype=torch.float32, device=self.device)
         check(self.lib.chrf_propagate_adjoint(self.plan, _ptr(grad_prop), _ptr(self.workspace), _ptr(out),
                                               _stream()))
         return out
+
+
+def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, lr: float, step: int,
+              beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam update of a float32 device tensor by the library kernel."""
+    lib = _lib.load()
+    for t in (param, grad, m, v):
+        assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == param.numel()
+    check(lib.chrf_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), lr, beta1, beta2, eps,
+                             int(step), _stream()))
 
 
 class CapturedTrainStep:

@@ -80,8 +80,9 @@ __global__ __launch_bounds__(kFftThreads) void k_rows_inverse(float2* __restrict
                                                               const float* __restrict__ target,
                                                               float* __restrict__ loss_partial, float grad_coef,
                                                               int fuse) {
+  // the per-wave loss sums live in the dynamic allocation, behind the two rows
   extern __shared__ cpx buf[];
-  __shared__ float red[kFftThreads / 64];
+  float* red = reinterpret_cast<float*>(buf + 2 * g.pW);
   const size_t row = blockIdx.x;   // ((bl * K + k) * H + r)
   float2* yrow = y + row * g.pW;
   for (int e = threadIdx.x; e < g.pW; e += kFftThreads) buf[e] = ld(yrow + e);
@@ -297,8 +298,8 @@ hipError_t launch_rows_inverse(float2* y, const AsmGeom& g, const FftDesc& fr, f
   if (tuned_rows(g))
     return launch_rows_inverse_t(y, g, fr, prop_out, intensity, target, loss_partial, grad_coef, fuse_adjoint, s);
   const unsigned rows = (unsigned)(g.n_bl * g.K * g.H);
-  k_rows_inverse<<<rows, kFftThreads, row_lds(g), s>>>(y, g, fr, prop_out, intensity, target, loss_partial,
-                                                       grad_coef, fuse_adjoint ? 1 : 0);
+  k_rows_inverse<<<rows, kFftThreads, row_lds(g) + sizeof(float) * (kFftThreads / 64), s>>>(
+      y, g, fr, prop_out, intensity, target, loss_partial, grad_coef, fuse_adjoint ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -72,6 +72,30 @@ __device__ inline cpx transfer_col(const HParam& hp, const ColFreq& c, int ky, c
   return pass ? cpx{cs, sn} : cpx{0.f, 0.f};
 }
 
+// The same transfer function split into its plane-independent part, computed
+// once per bin before the plane loop: q = f^2 / (1/lambda + sqrt(1/lambda^2 -
+// f^2)), so that the residual phase of plane z is -z q revolutions; -1 marks a
+// bin beyond the evanescent cut.  Per plane only the carrier, one
+// multiply-add, the reduction, sine/cosine and the sampling band test remain.
+__device__ inline float transfer_q(const HParam& hp, const ColFreq& c, int ky, const AsmGeom& g) {
+  const int sy = sbin(ky, g.pH);
+  const long long lhs = c.cterm + (long long)(sy * sy) * (long long)(g.pW * g.pW);
+  const float fy = (float)sy * g.ay;
+  const float f2 = fy * fy + c.fx2;
+  const float root = __builtin_amdgcn_sqrtf(fmaxf(hp.inv_lam2 - f2, 0.0f));
+  const float q = f2 * __builtin_amdgcn_rcpf(hp.inv_lam + root);
+  return lhs <= hp.evan_bound ? q : -1.0f;
+}
+
+__device__ inline cpx transfer_from_q(const HParam& hp, bool col_pass, float q, int ky, const AsmGeom& g) {
+  const int sy = sbin(ky, g.pH);
+  const bool pass = col_pass && q >= 0.0f && (g.band_mode < 2 || abs(sy) <= hp.ky_max);
+  float rev = hp.frac_rev - hp.z * q;
+  rev -= __builtin_rintf(rev);
+  const float cs = __builtin_amdgcn_cosf(rev), sn = __builtin_amdgcn_sinf(rev);
+  return pass ? cpx{cs, sn} : cpx{0.f, 0.f};
+}
+
 template <int N_, int NT, int R1_, int R2, int R3_>
 struct RowT {
   static constexpr int N = N_, R1 = R1_, R3 = R3_;
@@ -219,10 +243,15 @@ __global__ __launch_bounds__(256) void k_rows_adjoint_out_t(const float2* __rest
 }
 
 // ---------------------------------------------------------------- columns ---
-// C adjacent columns per workgroup (C = 4: 1024 threads, one workgroup per CU;
-// C = 2: 512 threads, two per CU), one butterfly per thread.  LDS holds the
-// work buffer of the transforms, the twiddles and, in the forward pass, the
-// spectrum reused for every plane.
+// C adjacent columns per workgroup, one butterfly per thread.
+//   C = 4: 1024 threads, one workgroup per CU; LDS holds the work buffer, the
+//          twiddles and, in the forward pass, the spectrum reused for every
+//          plane.
+//   C = 2: 512 threads; the spectrum stays in registers (each thread keeps the
+//          9 values its forward transform produced, which are the inputs its
+//          inverse transforms read) and the twiddles are read through the
+//          vector cache, so the LDS holds only the work buffer and two
+//          workgroups share a CU.
 constexpr int kColN = 2160;
 
 template <int C>
@@ -233,6 +262,8 @@ struct ColT {
   static_assert(Fwd::M1 == 1 && Fwd::M3 == 1 && Inv::M1 == 1 && Inv::M3 == 1, "one butterfly per thread");
   static_assert(Fwd::B3 == Inv::B1, "forward outputs feed the inverse inputs");
   static constexpr int SPAN = 128 / (8 * C);   // column groups per 128-byte line
+  static constexpr bool kRegSpec = C == 2;      // spectrum in registers, twiddles from memory
+  static constexpr int kMinBlocks = kRegSpec ? 2 : 1;
 };
 
 __device__ inline int col_remap(int id, int nblocks, int span) {
@@ -255,13 +286,14 @@ __device__ inline const cpx* stage_twiddles(cpx* s_tw, const cpx* __restrict__ t
 }
 
 template <int C, bool HALF>
-__global__ __launch_bounds__(ColT<C>::NT) void k_cols_forward_t(const float2* __restrict__ x1,
-                                                                float2* __restrict__ y, AsmGeom g, FftDesc fc) {
+__global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forward_t(
+    const float2* __restrict__ x1, float2* __restrict__ y, AsmGeom g, FftDesc fc) {
   using CT = ColT<C>;
   __shared__ cpx lds[lds_padded_size(kColN * C)];
-  __shared__ cpx spec[kColN * C];
-  __shared__ cpx s_tw[kColN];
-  const cpx* twl = stage_twiddles<CT::NT>(s_tw, fc.tw);
+  __shared__ cpx spec[CT::kRegSpec ? 1 : kColN * C];
+  __shared__ cpx s_tw[CT::kRegSpec ? 1 : kColN];
+  const cpx* twl = CT::kRegSpec ? fc.tw : stage_twiddles<CT::NT>(s_tw, fc.tw);
+  cpx sreg[CT::kRegSpec ? 9 : 1];
   const int ngroups = g.pW / C;
   const int gid = col_remap(blockIdx.x, gridDim.x, CT::SPAN);
   const int bl = gid / ngroups;
@@ -279,23 +311,37 @@ __global__ __launch_bounds__(ColT<C>::NT) void k_cols_forward_t(const float2* __
         v1[0][r] = live ? ldc(x1 + ((size_t)bl * g.H + n) * g.pW + c0 + s) : cpx{0.f, 0.f};
       }
     }
-    CT::Fwd::run(v1, v3, lds, twl);
+    CT::Fwd::template run<!CT::kRegSpec>(v1, v3, lds, twl);
     if (b < CT::Fwd::B3) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) spec[b + q * CT::Fwd::B3] = v3[0][q] * g.norm;
+      for (int q = 0; q < 9; ++q) {
+        if constexpr (CT::kRegSpec)
+          sreg[q] = v3[0][q] * g.norm;
+        else
+          spec[b + q * CT::Fwd::B3] = v3[0][q] * g.norm;
+      }
     }
+  }
+  float qv[9];   // plane-independent transfer terms of this thread's 9 bins
+  if (b < CT::Inv::B1) {
+    const HParam hp0 = g.hp[lam * g.K];
+    const ColFreq cf = col_freq(hp0, c0 + s, g);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) qv[q] = transfer_q(hp0, cf, j + q * (kColN / 9), g);
   }
   for (int k = 0; k < g.K; ++k) {
     const HParam hp = g.hp[lam * g.K + k];
     const int jj = opaque_v(j), kx = opaque_v(c0 + s);
     cpx w1[1][9], w3[1][16];
     if (b < CT::Inv::B1) {
-      const ColFreq cf = col_freq(hp, kx, g);
+      const bool col_pass = g.band_mode < 2 || abs(sbin(kx, g.pW)) <= hp.kx_max;
 #pragma unroll
-      for (int q = 0; q < 9; ++q)
-        w1[0][q] = cmul(spec[b + q * CT::Inv::B1], transfer_col(hp, cf, jj + q * (kColN / 9), g));
+      for (int q = 0; q < 9; ++q) {
+        const cpx sv = CT::kRegSpec ? sreg[CT::kRegSpec ? q : 0] : spec[b + q * CT::Inv::B1];
+        w1[0][q] = cmul(sv, transfer_from_q(hp, col_pass, qv[q], jj + q * (kColN / 9), g));
+      }
     }
-    CT::Inv::run(w1, w3, lds, twl, opaque_v(b));
+    CT::Inv::template run<!CT::kRegSpec>(w1, w3, lds, twl, opaque_v(b));
     if (b < CT::Inv::B3) {
       float2* yk = y + ((size_t)bl * g.K + k) * g.H * g.pW + kx;
 #pragma unroll
@@ -308,13 +354,12 @@ __global__ __launch_bounds__(ColT<C>::NT) void k_cols_forward_t(const float2* __
 }
 
 template <int C, bool HALF>
-__global__ __launch_bounds__(ColT<C>::NT) void k_cols_adjoint_t(const float2* __restrict__ z,
-                                                                float2* __restrict__ w1out, AsmGeom g,
-                                                                FftDesc fc) {
+__global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoint_t(
+    const float2* __restrict__ z, float2* __restrict__ w1out, AsmGeom g, FftDesc fc) {
   using CT = ColT<C>;
   __shared__ cpx lds[lds_padded_size(kColN * C)];
-  __shared__ cpx s_tw[kColN];
-  const cpx* twl = stage_twiddles<CT::NT>(s_tw, fc.tw);
+  __shared__ cpx s_tw[CT::kRegSpec ? 1 : kColN];
+  const cpx* twl = CT::kRegSpec ? fc.tw : stage_twiddles<CT::NT>(s_tw, fc.tw);
   const int ngroups = g.pW / C;
   const int gid = col_remap(blockIdx.x, gridDim.x, CT::SPAN);
   const int bl = gid / ngroups;
@@ -336,7 +381,7 @@ __global__ __launch_bounds__(ColT<C>::NT) void k_cols_adjoint_t(const float2* __
         v1[0][r] = (HALF ? r < 8 : n < g.H) ? ldc(zk + (size_t)n * g.pW) : cpx{0.f, 0.f};
       }
     }
-    CT::Fwd::run(v1, v3, lds, twl, opaque_v(b));
+    CT::Fwd::template run<false>(v1, v3, lds, twl, opaque_v(b));   // (table twiddles here would spill)
     const HParam hp = g.hp[lam * g.K + k];
     if (b < CT::Fwd::B3) {
       const ColFreq cf = col_freq(hp, kx, g);
@@ -348,7 +393,7 @@ __global__ __launch_bounds__(ColT<C>::NT) void k_cols_adjoint_t(const float2* __
 #pragma unroll
   for (int q = 0; q < 9; ++q) acc[0][q] = acc[0][q] * g.norm;
   cpx w3[1][16];
-  CT::Inv::run(acc, w3, lds, twl);
+  CT::Inv::template run<!CT::kRegSpec>(acc, w3, lds, twl);
   if (b < CT::Inv::B3) {
     float2* dst = w1out + (size_t)bl * g.H * g.pW + c0 + s;
 #pragma unroll

@@ -39,6 +39,7 @@ enum Reg {
   R_GRAD_FIELD, R_GRAD2D, R_LOSS_PARTIAL,
   R_LAYER_OF, R_LFIELD, R_LTFINAL, R_LSTOP, R_LGRAD,   // layered plans only
   R_UPROP, R_INTEN, R_DMU, R_DEXX, R_DEXY, R_DLDI, R_LOSS2,   // loss_kind 1 only
+  R_PO_P, R_PO_V, R_PO_GV, R_PO_D, R_PO_GP, R_PO_PART,       // phase_only plans only
   R_NUM
 };
 
@@ -292,10 +293,10 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
     return bad(fail(CHRF_EUNSUPPORTED, "plan: a padded row does not fit the LDS"));
   int C = d.cols_per_block;
   if (tuned_cols(geom(p))) {
-    // tuned column pass: 4 columns x 1024 threads (default) or 2 x 512
+    // tuned column pass: 2 columns x 512 threads (default) or 4 x 1024
     if (C != 0 && C != 2 && C != 4)
       return bad(fail(CHRF_EUNSUPPORTED, "plan: cols_per_block must be 2 or 4 for this padded height"));
-    if (C == 0) C = 4;
+    if (C == 0) C = 2;
   } else {
     if (C == 0) {
       const int lds_cap = ctx->lds_per_block < 81920 ? ctx->lds_per_block : 81920;
@@ -380,6 +381,12 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   sz[R_UPROP] = sizeof(float2) * ipix;
   sz[R_INTEN] = sz[R_DMU] = sz[R_DEXX] = sz[R_DEXY] = sz[R_DLDI] = sizeof(float) * ipix;
   sz[R_LOSS2] = p->loss_kind == 1 ? sizeof(float) * (size_t)loss_partial_elems(p->B * p->L * p->K, p->H, p->W) : 0;
+  const bool po = d.phase_only != 0;
+  const size_t fpix = po ? (size_t)pix * p->L : 0;         // hologram elements
+  sz[R_PO_P] = sz[R_PO_GP] = sizeof(float2) * fpix;
+  sz[R_PO_V] = sz[R_PO_GV] = sizeof(float2) * fpix * p->K;
+  sz[R_PO_D] = sizeof(float) * fpix * p->K * 6;             // 3 SSIM derivative maps x (re, im)
+  sz[R_PO_PART] = po ? sizeof(float) * (size_t)loss_partial_elems(2 * p->B * p->L * p->K, p->H, p->W) : 0;
   size_t o = 0;
   for (int r = 0; r < R_NUM; ++r) {
     p->off[r] = o;
@@ -714,6 +721,48 @@ chrf_status chrf_propagate_adjoint(chrf_plan* plan, const float* grad_prop, void
   RUN("cols_adjoint", launch_cols_adjoint(y, x1, geo, plan->fcol, plan->cols_per_block, s));
   RUN("rows_adjoint_out", launch_rows_adjoint_out(x1, nullptr, reinterpret_cast<float2*>(grad_field), geo,
                                                   plan->frow, s));
+  return CHRF_OK;
+}
+
+chrf_status chrf_phase_only_step(chrf_plan* plan, const float* targets, const float* phi, void* ws, float* loss_out,
+                                 float* dphi, void* hip_stream) {
+  if (!plan || !targets || !phi || !ws || !loss_out || !dphi)
+    return fail(CHRF_EINVAL, "chrf_phase_only_step: NULL argument");
+  if (!plan->d.phase_only) return fail(CHRF_EINVAL, "chrf_phase_only_step: plan was not created with phase_only");
+  hipStream_t s = (hipStream_t)hip_stream;
+  plan->fused_ready = false;
+  plan->paper_ready = false;
+  const AsmGeom geo = geom(plan);
+  const int64_t n = (int64_t)plan->B * plan->L * plan->H * plan->W;
+  const int n_img = plan->B * plan->L * plan->K;
+  float2* P = at<float2>(plan, ws, R_PO_P);
+  float2* V = at<float2>(plan, ws, R_PO_V);
+  float2* GV = at<float2>(plan, ws, R_PO_GV);
+  float2* GP = at<float2>(plan, ws, R_PO_GP);
+  const float2* U = reinterpret_cast<const float2*>(targets);
+  RUN("phase_field", launch_phase_field(phi, n, P, s));
+  chrf_status st = asm_forward(plan, P, ws, reinterpret_cast<float*>(V), nullptr, nullptr, s);
+  if (st != CHRF_OK) return st;
+  RUN("field_loss_forward", launch_field_loss_forward(V, U, n_img, plan->H, plan->W, plan->d.ssim_weight,
+                                                      at<float>(plan, ws, R_PO_D), at<float>(plan, ws, R_PO_PART),
+                                                      loss_out, s));
+  RUN("field_loss_backward", launch_field_loss_backward(V, U, n_img, plan->H, plan->W, plan->d.ssim_weight,
+                                                        at<float>(plan, ws, R_PO_D), GV, s));
+  float2* y = at<float2>(plan, ws, R_Y);
+  float2* x1 = at<float2>(plan, ws, R_X1);
+  RUN("rows_adjoint_in", launch_rows_adjoint_in(nullptr, nullptr, GV, y, geo, plan->frow, s));
+  RUN("cols_adjoint", launch_cols_adjoint(y, x1, geo, plan->fcol, plan->cols_per_block, s));
+  RUN("rows_adjoint_out", launch_rows_adjoint_out(x1, nullptr, GP, geo, plan->frow, s));
+  RUN("phase_grad", launch_phase_grad(GP, phi, n, dphi, s));
+  return CHRF_OK;
+}
+
+chrf_status chrf_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, float lr, float beta1,
+                           float beta2, float eps, int32_t step, void* hip_stream) {
+  if (n < 0 || (n > 0 && (!param || !grad || !m || !v))) return fail(CHRF_EINVAL, "chrf_adam_step: bad argument");
+  if (step < 1 || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return fail(CHRF_EINVAL, "chrf_adam_step: step must be >= 1, betas in [0, 1), eps > 0");
+  HIP_TRY(launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)hip_stream));
   return CHRF_OK;
 }
 

@@ -294,8 +294,31 @@ struct Fft3 {
     return INV ? cpx{w.x, -w.y} : w;
   }
 
+  // Twiddle w^r applied to input r of a butterfly: TABLE reads every power
+  // from the table (index arithmetic and a load, for LDS-resident tables of
+  // VALU-bound callers); otherwise one table entry is raised by repeated
+  // multiplication (error grows by about one rounding per power, < 1e-6 for
+  // R <= 16), which keeps memory reads to one per stage.
+  template <int R, bool TABLE>
+  __device__ static inline void apply_twiddles(cpx (&v)[R], const cpx* __restrict__ tw, int step) {
+    if constexpr (TABLE) {
+      int m = step;
+#pragma unroll
+      for (int r = 1; r < R; ++r, m += step) v[r] = INV ? cmulc(v[r], tw[m]) : cmul(v[r], tw[m]);
+    } else {
+      const cpx w = twid(tw, step);
+      cpx wr = w;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        v[r] = cmul(v[r], wr);
+        wr = cmul(wr, w);
+      }
+    }
+  }
+
   // tid is the thread index; callers inside loops may pass an opaque copy so
   // that the per-stage LDS addresses are not hoisted and kept live.
+  template <bool TABLE = false>
   __device__ static inline void run(cpx (&v1)[M1][R1], cpx (&v3)[M3][R3], cpx* lds, const cpx* __restrict__ tw,
                                     int tid = threadIdx.x) {
     // stage 1 (Ns = 1): no twiddles; output q of butterfly j goes to j R1 + q
@@ -319,15 +342,7 @@ struct Fft3 {
         const int s = b % C, j = b / C, k = j % R1;
 #pragma unroll
         for (int r = 0; r < R2; ++r) v2[i][r] = lds[lds_pad((j + r * (N / R2)) * C + s)];
-        // w^r for r >= 1 from one table entry by repeated multiplication
-        // (error grows by about one rounding per power: < 1e-6 for R <= 16)
-        const cpx w = twid(tw, k * (N / (R1 * R2)));
-        cpx wr = w;
-#pragma unroll
-        for (int r = 1; r < R2; ++r) {
-          v2[i][r] = cmul(v2[i][r], wr);
-          wr = cmul(wr, w);
-        }
+        apply_twiddles<R2, TABLE>(v2[i], tw, k * (N / (R1 * R2)));
         Dft<R2, INV>::run(v2[i]);
       }
     }
@@ -351,13 +366,7 @@ struct Fft3 {
         const int s = b % C, j = b / C;
 #pragma unroll
         for (int r = 0; r < R3; ++r) v3[i][r] = lds[lds_pad((j + r * (N / R3)) * C + s)];
-        const cpx w = twid(tw, j);
-        cpx wr = w;
-#pragma unroll
-        for (int r = 1; r < R3; ++r) {
-          v3[i][r] = cmul(v3[i][r], wr);
-          wr = cmul(wr, w);
-        }
+        apply_twiddles<R3, TABLE>(v3[i], tw, j);
         Dft<R3, INV>::run(v3[i]);
       }
     }

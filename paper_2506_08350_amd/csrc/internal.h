@@ -148,6 +148,16 @@ hipError_t launch_paper_loss_backward(const float* I, const float* T, const uint
                                       const float* dexx, const float* dexy, const float* grad_scale, float* dL_dI,
                                       hipStream_t s);
 
+// Phase-only conversion and the Adam update.
+hipError_t launch_field_loss_forward(const float2* V, const float2* U, int n_img, int H, int W, float ssim_weight,
+                                     float* dmaps, float* partial, float* loss_out, hipStream_t s);
+hipError_t launch_field_loss_backward(const float2* V, const float2* U, int n_img, int H, int W, float ssim_weight,
+                                      const float* dmaps, float2* dL_dV, hipStream_t s);
+hipError_t launch_phase_field(const float* phi, int64_t n, float2* out, hipStream_t s);
+hipError_t launch_phase_grad(const float2* G, const float* phi, int64_t n, float* dphi, hipStream_t s);
+hipError_t launch_adam(float* x, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, int t, hipStream_t s);
+
 // Multi-layer mode (hard plane assignment).
 constexpr int kMaxLayers = 4;
 hipError_t launch_assign_layers(const float* logits, int n, int n_layers, uint8_t* layer_of, hipStream_t s);

@@ -32,11 +32,18 @@ struct LossGeom {
   int per_view;          // images per view (wavelengths x planes)
   int planes;
   int tiles_x, tiles_y;
+  int chan;              // 1: float images; 2: real and imaginary parts of complex images
+  int recon;             // 1: the (1 + M + T^2) weighting of the reconstruction loss; 0: plain squares
   float g[2 * kLR + 1];  // normalised 1-D Gaussian taps
 };
 
-__device__ inline float ld_or0(const float* img, int H, int W, int r, int c) {
-  return (r >= 0 && r < H && c >= 0 && c < W) ? img[(size_t)r * W + c] : 0.f;
+// Image i of the launch: element (r, c) sits at base(i) + (r W + c) chan.
+__device__ inline size_t img_base(const LossGeom& lg, int i) {
+  return ((size_t)(i / lg.chan) * lg.H * lg.W) * lg.chan + (size_t)(i % lg.chan);
+}
+
+__device__ inline float ld_or0(const float* img, int H, int W, int chan, int r, int c) {
+  return (r >= 0 && r < H && c >= 0 && c < W) ? img[((size_t)r * W + c) * chan] : 0.f;
 }
 
 __global__ __launch_bounds__(kLThreads) void k_loss_fwd(const float* __restrict__ I, const float* __restrict__ T,
@@ -49,13 +56,13 @@ __global__ __launch_bounds__(kLThreads) void k_loss_fwd(const float* __restrict_
   const int img = blockIdx.y;
   const int ty = blockIdx.x / lg.tiles_x, tx = blockIdx.x % lg.tiles_x;
   const int r0 = ty * kLT - kLR, c0 = tx * kLT - kLR;
-  const size_t base = (size_t)img * lg.H * lg.W;
+  const size_t base = img_base(lg, img);
   const float* x = I + base;
   const float* y = T + base;
   for (int i = threadIdx.x; i < kLE * kLE; i += kLThreads) {
     const int r = i / kLE, c = i % kLE;
-    sx[r][c] = ld_or0(x, lg.H, lg.W, r0 + r, c0 + c);
-    sy[r][c] = ld_or0(y, lg.H, lg.W, r0 + r, c0 + c);
+    sx[r][c] = ld_or0(x, lg.H, lg.W, lg.chan, r0 + r, c0 + c);
+    sy[r][c] = ld_or0(y, lg.H, lg.W, lg.chan, r0 + r, c0 + c);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kLE * kLT; i += kLThreads) {
@@ -98,7 +105,7 @@ __global__ __launch_bounds__(kLThreads) void k_loss_fwd(const float* __restrict_
     const float b2 = (m[2] - mx * mx) + (m[3] - my * my) + kC2;
     const float inv = 1.0f / (b1 * b2);
     const float S = a1 * a2 * inv;
-    const size_t o = base + (size_t)gr * lg.W + gc;
+    const size_t o = (size_t)img * lg.H * lg.W + (size_t)gr * lg.W + gc;   // maps are dense per image
     dmu[o] = (2.f * my * a2 - 2.f * my * a1) * inv - S * (2.f * mx / b1 - 2.f * mx / b2);
     dexx[o] = -S / b2;
     dexy[o] = 2.f * a1 * inv;
@@ -106,7 +113,7 @@ __global__ __launch_bounds__(kLThreads) void k_loss_fwd(const float* __restrict_
     const float xv = sx[r + kLR][c + kLR], yv = sy[r + kLR][c + kLR];
     const float d = xv - yv;
     const float mval = mk ? (float)mk[(size_t)gr * lg.W + gc] : 0.f;
-    r_sum += d * d * (1.f + mval + yv * yv);
+    r_sum += lg.recon ? d * d * (1.f + mval + yv * yv) : d * d;
   }
   for (int off = 32; off > 0; off >>= 1) {
     s_sum += __shfl_xor(s_sum, off, 64);
@@ -140,12 +147,13 @@ __global__ __launch_bounds__(kLThreads) void k_loss_bwd(const float* __restrict_
   const int img = blockIdx.y;
   const int ty = blockIdx.x / lg.tiles_x, tx = blockIdx.x % lg.tiles_x;
   const int r0 = ty * kLT - kLR, c0 = tx * kLT - kLR;
-  const size_t base = (size_t)img * lg.H * lg.W;
+  const size_t mbase = (size_t)img * lg.H * lg.W;   // derivative maps: dense per image
+  const size_t base = img_base(lg, img);
   for (int i = threadIdx.x; i < kLE * kLE; i += kLThreads) {
     const int r = i / kLE, c = i % kLE;
-    sd[0][r][c] = ld_or0(dmu + base, lg.H, lg.W, r0 + r, c0 + c);
-    sd[1][r][c] = ld_or0(dexx + base, lg.H, lg.W, r0 + r, c0 + c);
-    sd[2][r][c] = ld_or0(dexy + base, lg.H, lg.W, r0 + r, c0 + c);
+    sd[0][r][c] = ld_or0(dmu + mbase, lg.H, lg.W, 1, r0 + r, c0 + c);
+    sd[1][r][c] = ld_or0(dexx + mbase, lg.H, lg.W, 1, r0 + r, c0 + c);
+    sd[2][r][c] = ld_or0(dexy + mbase, lg.H, lg.W, 1, r0 + r, c0 + c);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kLE * kLT; i += kLThreads) {
@@ -178,11 +186,11 @@ __global__ __launch_bounds__(kLThreads) void k_loss_bwd(const float* __restrict_
       f1 += w * hs[1][r + k][c];
       f2 += w * hs[2][r + k][c];
     }
-    const size_t o = base + (size_t)gr * lg.W + gc;
+    const size_t o = base + ((size_t)gr * lg.W + gc) * lg.chan;
     const float xv = I[o], yv = T[o];
     const float mval = mk ? (float)mk[(size_t)gr * lg.W + gc] : 0.f;
     const float g_ssim = ssim_coef * (f0 + 2.f * xv * f1 + yv * f2);
-    const float g_rec = recon_coef * (xv - yv) * (1.f + mval + yv * yv);
+    const float g_rec = recon_coef * (xv - yv) * (lg.recon ? 1.f + mval + yv * yv : 1.f);
     dL_dI[o] = scale * (g_ssim + g_rec);
   }
 }
@@ -216,13 +224,15 @@ __global__ __launch_bounds__(1024) void k_loss_total(const float* __restrict__ p
   }
 }
 
-static LossGeom loss_geom(int n_img, int per_view, int planes, int H, int W) {
+static LossGeom loss_geom(int n_img, int per_view, int planes, int H, int W, int chan = 1, int recon = 1) {
   LossGeom lg{};
   lg.H = H;
   lg.W = W;
   lg.n_img = n_img;
   lg.per_view = per_view;
   lg.planes = planes;
+  lg.chan = chan;
+  lg.recon = recon;
   lg.tiles_x = (W + kLT - 1) / kLT;
   lg.tiles_y = (H + kLT - 1) / kLT;
   double g[2 * kLR + 1], sum = 0.0;
@@ -239,6 +249,60 @@ int64_t loss_partial_elems(int n_img, int H, int W) {
   return (int64_t)2 * n_img * ((W + kLT - 1) / kLT) * ((H + kLT - 1) / kLT);
 }
 
+// exp(j phi) and the phase gradient Im(G exp(-j phi)) of the phase-only hologram
+__global__ void k_phase_field(const float* __restrict__ phi, int64_t n, float2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float sn, cs;
+  sincosf(phi[i], &sn, &cs);
+  out[i] = make_float2(cs, sn);
+}
+
+__global__ void k_phase_grad(const float2* __restrict__ G, const float* __restrict__ phi, int64_t n,
+                             float* __restrict__ dphi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float sn, cs;
+  sincosf(phi[i], &sn, &cs);
+  const float2 g = G[i];
+  dphi[i] = g.y * cs - g.x * sn;
+}
+
+hipError_t launch_phase_field(const float* phi, int64_t n, float2* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_phase_field<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(phi, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_phase_grad(const float2* G, const float* phi, int64_t n, float* dphi, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_phase_grad<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(G, phi, n, dphi);
+  return hipGetLastError();
+}
+
+// Adam update (Kingma and Ba, 2015) with bias correction, step t >= 1.
+__global__ void k_adam(float* __restrict__ x, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  x[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+hipError_t launch_adam(float* x, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, int t, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, t)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, t)));
+  k_adam<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
 hipError_t launch_paper_loss_forward(const float* I, const float* T, const uint8_t* masks, int n_img, int per_view,
                                      int planes, int H, int W, float ssim_weight, float* dmu, float* dexx,
                                      float* dexy, float* partial, float* loss_out, hipStream_t s) {
@@ -248,6 +312,34 @@ hipError_t launch_paper_loss_forward(const float* I, const float* T, const uint8
   const double numel = (double)n_img * H * W;
   k_loss_total<<<1, 1024, 0, s>>>(partial, (int64_t)grid.x * grid.y, 1.0 / numel, (double)ssim_weight,
                                   1.0 / numel, loss_out);
+  return hipGetLastError();
+}
+
+// Phase-only conversion: mean |V - U|^2 over complex elements plus
+// w (1 - mean SSIM) over the real and the imaginary parts of every image.
+hipError_t launch_field_loss_forward(const float2* V, const float2* U, int n_img, int H, int W, float ssim_weight,
+                                     float* dmaps, float* partial, float* loss_out, hipStream_t s) {
+  const LossGeom lg = loss_geom(2 * n_img, 1, 1, H, W, 2, 0);
+  const size_t map = (size_t)2 * n_img * H * W;
+  const dim3 grid((unsigned)(lg.tiles_x * lg.tiles_y), (unsigned)(2 * n_img));
+  k_loss_fwd<<<grid, kLThreads, 0, s>>>(reinterpret_cast<const float*>(V), reinterpret_cast<const float*>(U),
+                                        nullptr, lg, dmaps, dmaps + map, dmaps + 2 * map, partial);
+  const double numel = (double)n_img * H * W;
+  k_loss_total<<<1, 1024, 0, s>>>(partial, (int64_t)grid.x * grid.y, 1.0 / numel, (double)ssim_weight,
+                                  1.0 / (2.0 * numel), loss_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_loss_backward(const float2* V, const float2* U, int n_img, int H, int W, float ssim_weight,
+                                      const float* dmaps, float2* dL_dV, hipStream_t s) {
+  const LossGeom lg = loss_geom(2 * n_img, 1, 1, H, W, 2, 0);
+  const size_t map = (size_t)2 * n_img * H * W;
+  const dim3 grid((unsigned)(lg.tiles_x * lg.tiles_y), (unsigned)(2 * n_img));
+  const double numel = (double)n_img * H * W;
+  k_loss_bwd<<<grid, kLThreads, 0, s>>>(reinterpret_cast<const float*>(V), reinterpret_cast<const float*>(U),
+                                        nullptr, lg, dmaps, dmaps + map, dmaps + 2 * map,
+                                        (float)(-ssim_weight / (2.0 * numel)), (float)(2.0 / numel), nullptr,
+                                        reinterpret_cast<float*>(dL_dV));
   return hipGetLastError();
 }
 

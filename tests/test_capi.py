@@ -51,7 +51,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", offsetof(chrf_plan_desc, pitch), offsetof(chrf_plan_desc, distances),
          offsetof(chrf_plan_desc, cols_per_block), offsetof(chrf_plan_desc, layered),
          offsetof(chrf_gaussians, logits), offsetof(chrf_grads, logits));
-  printf("%zu %zu\n", offsetof(chrf_plan_desc, loss_kind), offsetof(chrf_plan_desc, ssim_weight));
+  printf("%zu %zu %zu\n", offsetof(chrf_plan_desc, loss_kind), offsetof(chrf_plan_desc, ssim_weight),
+         offsetof(chrf_plan_desc, phase_only));
   return 0;
 }
 """
@@ -65,7 +66,7 @@ int main(void) {
     assert vals == [ctypes.sizeof(P), ctypes.sizeof(_lib.Camera), ctypes.sizeof(_lib.Gaussians),
                     ctypes.sizeof(_lib.Grads), P.k_sigma.offset, P.pitch.offset, P.distances.offset,
                     P.cols_per_block.offset, P.layered.offset, _lib.Gaussians.logits.offset,
-                    _lib.Grads.logits.offset, P.loss_kind.offset, P.ssim_weight.offset]
+                    _lib.Grads.logits.offset, P.loss_kind.offset, P.ssim_weight.offset, P.phase_only.offset]
 
 
 def test_camera_record_packing_matches_struct():
