@@ -10,7 +10,8 @@ with hard plane assignment, forward recording and inverse propagation
 (Sec. 4.1, Eqs. 12-16) and its gradient with the straight-through estimator;
 ``losses.py`` the paper's training loss (masked three-term reconstruction
 loss plus the SSIM term) and its gradient; ``phase_only.py`` the loss and
-phase gradient of the phase-only hologram conversion.
+phase gradient of the phase-only hologram conversion; ``training.py`` the
+Adan update and the densification of the optimisation loop.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the HIP library
@@ -26,11 +27,11 @@ from .binning import fp32_footprint, bin_pairs
 from .raster import render_field, render_field_backward, RasterResult
 from .asm import transfer_function, band_mask, propagate, propagate_adjoint
 from .pipeline import Thresholds, SMOOTH, DEFAULT, forward, backward, mse_loss
-from . import layers, losses, phase_only
+from . import layers, losses, phase_only, training
 
 __all__ = [
     "quat_to_rotmat", "project", "ProjectedGaussians", "fp32_footprint", "bin_pairs",
     "render_field", "render_field_backward", "RasterResult", "transfer_function",
     "band_mask", "propagate", "propagate_adjoint", "Thresholds", "SMOOTH", "DEFAULT",
-    "forward", "backward", "mse_loss", "layers", "losses", "phase_only",
+    "forward", "backward", "mse_loss", "layers", "losses", "phase_only", "training",
 ]

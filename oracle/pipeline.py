@@ -88,4 +88,5 @@ def backward(state, dL_dI=None, dL_du=None):
             m = vis.reshape((-1,) + (1,) * (g[k].ndim - 1))
             grads[k] += np.where(m, np.nan_to_num(g[k]), 0.0)
         view["G_U"] = G_U
+        view["d_mu"] = d_mu   # dL/d mu_2D of this view (pixels), the densification statistic
     return grads

@@ -17,7 +17,17 @@ import oracle
 from oracle import binning
 from scenegen import Optics, Scene, identity_camera, make_gaussians, make_targets, yaw_cameras
 
-torch.set_default_dtype(torch.float64)
+
+
+@pytest.fixture(autouse=True)
+def _float64_default():
+    """The dense torch formulation works in float64; the default dtype is set
+    for this module's tests only, so that no other test in the process
+    creates float64 tensors by accident."""
+    old = torch.get_default_dtype()
+    torch.set_default_dtype(torch.float64)
+    yield
+    torch.set_default_dtype(old)
 
 
 def _small_problem(n=30, H=40, W=48, seed=21, log_scale_mean=-2.8):
