@@ -288,6 +288,92 @@ chrf_status chrf_phase_only_step(chrf_plan* plan, const float* targets, const fl
 chrf_status chrf_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, float lr, float beta1,
                            float beta2, float eps, int32_t step, void* hip_stream);
 
+/*
+ * One Adan step (Xie et al., adaptive Nesterov momentum; the optimiser of
+ * Sec. 5) on n device floats, in place, in the decay-coefficient form:
+ *   d = g - g_prev (0 at step 1);  m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) d;
+ *   n = b3 n + (1 - b3) (g + b2 d)^2;  g_prev = g;
+ *   x = (x - lr (m / c1 + b2 v / c2) / (sqrt(n / c3) + eps)) / (1 + lr weight_decay)
+ * with c_i = 1 - b_i^step.  The paper's (0.9, 0.99) are b1 and b3; Adan's
+ * default b2 = 0.92 is the gradient-difference moment.  All five state
+ * arrays have n floats; m, v and nm start at zero; g_prev is overwritten at
+ * step 1.  Errors: CHRF_EINVAL for NULL arrays, step < 1, betas outside
+ * [0, 1) or eps <= 0.
+ */
+chrf_status chrf_adan_step(float* param, const float* grad, float* grad_prev, float* m, float* v, float* nm,
+                           int64_t n, float lr, float beta1, float beta2, float beta3, float eps, float weight_decay,
+                           int32_t step, void* hip_stream);
+
+/*
+ * Densification statistics (the 3DGS strategy the paper adopts): after a
+ * chrf_backward on a single-plane or layered plan, for each of the first n
+ * Gaussians, add to grad_accum[g] the norm of dL/d mu_2D (pixels) of every
+ * view that binned it and to grad_count[g] the number of such views.  Both
+ * are device float arrays of n entries, caller-owned, accumulated in place.
+ */
+chrf_status chrf_densify_stats(chrf_plan* plan, void* workspace, int32_t n, float* grad_accum, float* grad_count,
+                               void* hip_stream);
+
+/*
+ * Densification (the optimisation algorithm of the Supplementary: prune,
+ * clone and split with phase perturbation), all arrays device memory.
+ * Input Gaussian i grows if grad_count[i] > 0 and grad_accum[i] >= fl(tau_grad
+ * * grad_count[i]); it splits if it grows and its largest log-scale exceeds
+ * sigma_split, else it is kept and, if it grows, cloned.  Outputs, in input
+ * order: a kept Gaussian (kind 0) followed by its clone (kind 1, phases +
+ * phase_sigma zeta[i][0]); or, for a split, two children (kind 2) with means
+ * mu + R(q) (exp(s) * xi[i][c]), log-scales s - shrink and phases
+ * + phase_sigma zeta[i][c].  Any output with opacity < min_opacity or largest
+ * log-scale > sigma_prune is dropped.  Decisions are taken in single
+ * precision exactly as written (grow: one rounded product; a child's largest
+ * log-scale: fl(max s - shrink)).
+ */
+typedef struct {
+  int32_t n, n_lambda;
+  const float* means;       /* [n][3] */
+  const float* log_scales;  /* [n][3] */
+  const float* quats;       /* [n][4] (w, x, y, z), any norm */
+  const float* opacity;     /* [n] activated, for the pruning test only */
+  const float* phase;       /* [n][n_lambda] */
+  const float* grad_accum;  /* [n], from chrf_densify_stats */
+  const float* grad_count;  /* [n] */
+  const float* xi;          /* [n][2][3] standard normal draws (split offsets) */
+  const float* zeta;        /* [n][2][n_lambda] standard normal draws (phase perturbation) */
+  float tau_grad;           /* mean view-space gradient threshold */
+  float sigma_split;        /* log of the scale above which a growing Gaussian splits */
+  float sigma_prune;        /* log of the scale above which a Gaussian is pruned */
+  float min_opacity;        /* opacity below which a Gaussian is pruned */
+  float phase_sigma;        /* size of the phase perturbation of new Gaussians */
+  float shrink;             /* log-scale decrease of split children (log 1.6) */
+} chrf_densify_desc;
+
+/* Scratch bytes chrf_densify needs for n input Gaussians. */
+size_t chrf_densify_workspace_bytes(int64_t n);
+
+/*
+ * Runs the densification of desc into outputs of `capacity` rows:
+ *   src [capacity] int32 (input index of each output), kind [capacity] int32,
+ *   means_out [capacity][3], log_scales_out [capacity][3],
+ *   phase_out [capacity][n_lambda];
+ *   n_out: device int64, the number of outputs (written even when it exceeds
+ *   capacity, in which case rows past capacity are not written; capacity
+ *   2 n always suffices).
+ * scratch: chrf_densify_workspace_bytes(n) bytes of device memory.
+ */
+chrf_status chrf_densify(const chrf_densify_desc* desc, void* scratch, int64_t capacity, int32_t* src, int32_t* kind,
+                         float* means_out, float* log_scales_out, float* phase_out, int64_t* n_out,
+                         void* hip_stream);
+
+/*
+ * Carries a per-Gaussian array [n][row] through a densification: output row j
+ * < min(*n_out, capacity) is in[src[j]], or zero when zero_new != 0 and
+ * kind[j] != 0 (fresh optimiser state for new Gaussians).  out has
+ * capacity rows; rows past *n_out are left untouched.
+ */
+chrf_status chrf_gather_rows(const float* in, int64_t row, const int32_t* src, const int32_t* kind,
+                             const int64_t* n_out, int64_t capacity, int32_t zero_new, float* out,
+                             void* hip_stream);
+
 /* Synchronise the stream and report the last forward's pair-list status:
  * CHRF_OK, or CHRF_ECAPACITY with *pairs_needed set. */
 chrf_status chrf_read_status(chrf_plan* plan, void* workspace, int64_t* pairs_needed, void* hip_stream);

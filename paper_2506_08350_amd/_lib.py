@@ -38,6 +38,7 @@ EXPORTED = [
     "chrf_plan_destroy", "chrf_plan_workspace_bytes", "chrf_plan_region", "chrf_forward",
     "chrf_backward", "chrf_propagate", "chrf_propagate_adjoint", "chrf_read_status",
     "chrf_timing_enable", "chrf_timing_report", "chrf_phase_only_step", "chrf_adam_step",
+    "chrf_adan_step", "chrf_densify_stats", "chrf_densify_workspace_bytes", "chrf_densify", "chrf_gather_rows",
 ]
 
 
@@ -65,6 +66,14 @@ class PlanDesc(C.Structure):
                 ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("cols_per_block", C.c_int32),
                 ("layered", C.c_int32), ("loss_kind", C.c_int32), ("ssim_weight", C.c_float),
                 ("phase_only", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+class DensifyDesc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("n_lambda", C.c_int32), ("means", C.c_void_p), ("log_scales", C.c_void_p),
+                ("quats", C.c_void_p), ("opacity", C.c_void_p), ("phase", C.c_void_p),
+                ("grad_accum", C.c_void_p), ("grad_count", C.c_void_p), ("xi", C.c_void_p), ("zeta", C.c_void_p),
+                ("tau_grad", C.c_float), ("sigma_split", C.c_float), ("sigma_prune", C.c_float),
+                ("min_opacity", C.c_float), ("phase_sigma", C.c_float), ("shrink", C.c_float)]
 
 
 class ChrfError(RuntimeError):
@@ -107,6 +116,11 @@ def load(path: str | None = None):
         "chrf_read_status": (i32, [vp, vp, C.POINTER(i64), vp]),
         "chrf_phase_only_step": (i32, [vp, vp, vp, vp, vp, vp, vp]),
         "chrf_adam_step": (i32, [vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp]),
+        "chrf_adan_step": (i32, [vp, vp, vp, vp, vp, vp, i64] + [C.c_float] * 6 + [i32, vp]),
+        "chrf_densify_stats": (i32, [vp, vp, i32, vp, vp, vp]),
+        "chrf_densify_workspace_bytes": (sz, [i64]),
+        "chrf_densify": (i32, [C.POINTER(DensifyDesc), vp, i64, vp, vp, vp, vp, vp, vp, vp]),
+        "chrf_gather_rows": (i32, [vp, i64, vp, vp, vp, i64, i32, vp, vp]),
         "chrf_timing_enable": (i32, [vp, C.c_int]),
         "chrf_timing_report": (i32, [vp, C.c_char_p, sz]),
     }

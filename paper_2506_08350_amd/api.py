@@ -7,6 +7,7 @@ wires chrf_backward into torch.autograd.
 from __future__ import annotations
 
 import ctypes as C
+import math
 from dataclasses import dataclass
 
 import torch
@@ -20,6 +21,18 @@ LAYER_LOGITS = "logits"   # [N, layers] plane-assignment logits of a layered ren
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_tensor(t, name, shape=None, dtype=torch.float32):
+    """The library reads raw pointers, so every tensor handed to it must be a
+    contiguous device tensor of the expected element type and shape."""
+    if t is None:
+        return
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"{name}: expected a contiguous {dtype} device tensor, got "
+                        f"{getattr(t, 'dtype', type(t))} on {getattr(t, 'device', '?')}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
 
 
 def _stream():
@@ -83,6 +96,11 @@ class Renderer:
         then carry "logits" [N, layers] and the forward's "field" is the
         recorded hologram P.  loss: "mse" (Eq. 17) or "paper" (the masked
         three-term reconstruction loss plus ssim_weight * (1 - SSIM))."""
+        self._config = dict(height=height, width=width, optics=optics, n_views=n_views, max_gaussians=max_gaussians,
+                            n_lambda=n_lambda, max_pairs=max_pairs, k_sigma=k_sigma, alpha_min=alpha_min,
+                            alpha_max=alpha_max, t_min=t_min, tile=tile, cols_per_block=cols_per_block,
+                            layered=layered, loss=loss, ssim_weight=ssim_weight, phase_only=phase_only,
+                            device=device)
         self.ctx = context(device)
         self.lib = self.ctx.lib
         d = _lib.PlanDesc()
@@ -129,6 +147,15 @@ class Renderer:
             self.lib.chrf_plan_destroy(self.plan)
             self.plan = C.c_void_p()
 
+    def resized(self, max_gaussians=None, max_pairs=None):
+        """A new renderer with the same configuration and other capacities."""
+        cfg = dict(self._config)
+        if max_gaussians is not None:
+            cfg["max_gaussians"] = int(max_gaussians)
+        if max_pairs is not None:
+            cfg["max_pairs"] = int(max_pairs)
+        return Renderer(**cfg)
+
     # ---- inspection ----
     def region(self, region: int, dtype=torch.uint8):
         off, nb = C.c_size_t(), C.c_size_t()
@@ -156,15 +183,16 @@ class Renderer:
     # ---- calls ----
     def _gauss(self, p):
         g = _lib.Gaussians()
-        g.n = int(p["means"].shape[0])
+        n = int(p["means"].shape[0])
+        g.n = n
+        shapes = dict(means=(n, 3), log_scales=(n, 3), quats=(n, 4), opacity=(n,), amp=(n, self.L),
+                      phase=(n, self.L))
         for k in PARAM_NAMES:
-            t = p[k]
-            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous(), k
-            setattr(g, k, t.data_ptr())
+            _check_tensor(p[k], k, shapes[k])
+            setattr(g, k, p[k].data_ptr())
         if self.layered:
-            t = p[LAYER_LOGITS]
-            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.shape == (g.n, self.K)
-            g.logits = t.data_ptr()
+            _check_tensor(p[LAYER_LOGITS], LAYER_LOGITS, (n, self.K))
+            g.logits = p[LAYER_LOGITS].data_ptr()
         return g
 
     def param_names(self):
@@ -180,10 +208,9 @@ class Renderer:
         prop = torch.empty((B, L, K, H, W, 2), dtype=torch.float32, device=dev) if want_prop else None
         inten = torch.empty((B, L, K, H, W), dtype=torch.float32, device=dev) if want_intensity else None
         loss = torch.empty((), dtype=torch.float32, device=dev) if target is not None else None
-        if target is not None:
-            assert target.shape == (B, L, K, H, W) and target.is_contiguous()
-        if masks is not None:
-            assert masks.shape == (B, K, H, W) and masks.dtype == torch.uint8 and masks.is_contiguous()
+        _check_tensor(cams, "cams", (B, 20))
+        _check_tensor(target, "target", (B, L, K, H, W))
+        _check_tensor(masks, "masks", (B, K, H, W), torch.uint8)
         g = self._gauss(params)
         check(self.lib.chrf_forward(self.plan, C.byref(g), _ptr(cams), _ptr(self.workspace), _ptr(field),
                                     _ptr(prop), _ptr(inten), _ptr(target), _ptr(masks), _ptr(loss), _stream()))
@@ -192,6 +219,13 @@ class Renderer:
 
     def backward(self, params: dict, cams: torch.Tensor, dL_dI=None, prop=None, dL_dprop=None, dL_dfield=None,
                  grad_scale=None):
+        B, L, K, H, W = self.B, self.L, self.K, self.H, self.W
+        _check_tensor(cams, "cams", (B, 20))
+        _check_tensor(dL_dI, "dL_dI", (B, L, K, H, W))
+        _check_tensor(prop, "prop", (B, L, K, H, W, 2))
+        _check_tensor(dL_dprop, "dL_dprop", (B, L, K, H, W, 2))
+        _check_tensor(dL_dfield, "dL_dfield", (B, L, H, W, 2))
+        _check_tensor(grad_scale, "grad_scale", ())
         grads = {k: torch.empty_like(params[k]) for k in self.param_names()}
         gr = _lib.Grads(*[grads[k].data_ptr() for k in PARAM_NAMES])
         if self.layered:
@@ -211,6 +245,7 @@ class Renderer:
 
     def propagate(self, field: torch.Tensor, want_prop=True, want_intensity=True):
         B, L, K, H, W = self.B, self.L, self.K, self.H, self.W
+        _check_tensor(field, "field", (B, L, H, W, 2))
         prop = torch.empty((B, L, K, H, W, 2), dtype=torch.float32, device=self.device) if want_prop else None
         inten = torch.empty((B, L, K, H, W), dtype=torch.float32, device=self.device) if want_intensity else None
         check(self.lib.chrf_propagate(self.plan, _ptr(field), _ptr(self.workspace), _ptr(prop), _ptr(inten),
@@ -220,8 +255,8 @@ class Renderer:
     def phase_only_step(self, targets: torch.Tensor, phi: torch.Tensor):
         """Loss and dL/dphi of the phase-only hologram exp(j phi) against the
         propagated target fields (plan created with phase_only=True)."""
-        assert targets.shape == (self.B, self.L, self.K, self.H, self.W, 2) and targets.is_contiguous()
-        assert phi.shape == (self.B, self.L, self.H, self.W) and phi.is_contiguous()
+        _check_tensor(targets, "targets", (self.B, self.L, self.K, self.H, self.W, 2))
+        _check_tensor(phi, "phi", (self.B, self.L, self.H, self.W))
         loss = torch.empty((), dtype=torch.float32, device=self.device)
         dphi = torch.empty_like(phi)
         check(self.lib.chrf_phase_only_step(self.plan, _ptr(targets), _ptr(phi), _ptr(self.workspace), _ptr(loss),
@@ -243,7 +278,16 @@ class Renderer:
             losses.append(loss)
         return phi, torch.stack(losses)
 
+    def densify_stats(self, n: int, accum: torch.Tensor, count: torch.Tensor):
+        """After a backward: add ||dL/d mu_2D|| of every view that binned each of
+        the first n Gaussians to accum and the number of such views to count."""
+        for t in (accum, count):
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() >= n
+        check(self.lib.chrf_densify_stats(self.plan, _ptr(self.workspace), int(n), _ptr(accum), _ptr(count),
+                                          _stream()))
+
     def propagate_adjoint(self, grad_prop: torch.Tensor):
+        _check_tensor(grad_prop, "grad_prop", (self.B, self.L, self.K, self.H, self.W, 2))
         out = torch.empty((self.B, self.L, self.H, self.W, 2), dtype=torch.float32, device=self.device)
         check(self.lib.chrf_propagate_adjoint(self.plan, _ptr(grad_prop), _ptr(self.workspace), _ptr(out),
                                               _stream()))
@@ -258,6 +302,194 @@ def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch
         assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == param.numel()
     check(lib.chrf_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), lr, beta1, beta2, eps,
                              int(step), _stream()))
+
+
+ADAN_BETAS = (0.9, 0.92, 0.99)
+
+
+def adan_step(param: torch.Tensor, grad: torch.Tensor, state: dict, lr: float, step: int, betas=ADAN_BETAS,
+              eps=1e-8, weight_decay=0.0):
+    """In-place Adan update of a float32 device tensor by the library kernel;
+    ``state`` holds grad_prev, m, v, n (created zeroed on first use)."""
+    lib = _lib.load()
+    for k in ("grad_prev", "m", "v", "n"):
+        if k not in state:
+            state[k] = torch.zeros_like(param)
+    for t in (param, grad, *(state[k] for k in ("grad_prev", "m", "v", "n"))):
+        assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == param.numel()
+    check(lib.chrf_adan_step(_ptr(param), _ptr(grad), _ptr(state["grad_prev"]), _ptr(state["m"]), _ptr(state["v"]),
+                             _ptr(state["n"]), param.numel(), lr, betas[0], betas[1], betas[2], eps, weight_decay,
+                             int(step), _stream()))
+
+
+@dataclass
+class DensifyConfig:
+    """Thresholds of the densification (the 3DGS values; the phase perturbation
+    size is not given by the paper)."""
+    tau_grad: float = 2e-4 * 1080          # mean ||dL/d mu_2D|| in pixels
+    split_scale: float = 0.05              # world-space scale above which a growing Gaussian splits
+    prune_scale: float = 1.0               # world-space scale above which a Gaussian is pruned
+    min_opacity: float = 0.005
+    phase_sigma: float = 0.01              # radians
+    shrink: float = float(math.log(1.6))
+
+
+def densify(params: dict, opacity: torch.Tensor, accum: torch.Tensor, count: torch.Tensor, xi: torch.Tensor,
+            zeta: torch.Tensor, cfg: DensifyConfig = DensifyConfig(), capacity=None):
+    """Runs the library's densification.  params holds at least means,
+    log_scales, quats and phase (float32 device tensors of n rows); opacity is
+    the activated opacity used by the pruning test.  Returns (n_out, src, kind,
+    means, log_scales, phase) with the new arrays cut to n_out rows; xi
+    [n, 2, 3] and zeta [n, 2, n_lambda] are standard normal draws."""
+    lib = _lib.load()
+    n = int(params["means"].shape[0])
+    n_lam = int(params["phase"].shape[1])
+    cap = 2 * n if capacity is None else int(capacity)
+    dev = params["means"].device
+    d = _lib.DensifyDesc()
+    d.n, d.n_lambda = n, n_lam
+    arrays = dict(means=params["means"], log_scales=params["log_scales"], quats=params["quats"], opacity=opacity,
+                  phase=params["phase"], grad_accum=accum, grad_count=count, xi=xi, zeta=zeta)
+    for k, t in arrays.items():
+        assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.shape[0] == n, k
+        setattr(d, k, t.data_ptr())
+    d.tau_grad = cfg.tau_grad
+    d.sigma_split = math.log(cfg.split_scale)
+    d.sigma_prune = math.log(cfg.prune_scale)
+    d.min_opacity = cfg.min_opacity
+    d.phase_sigma = cfg.phase_sigma
+    d.shrink = cfg.shrink
+    scratch = torch.empty(int(lib.chrf_densify_workspace_bytes(n)), dtype=torch.uint8, device=dev)
+    src = torch.empty(cap, dtype=torch.int32, device=dev)
+    kind = torch.empty(cap, dtype=torch.int32, device=dev)
+    means = torch.empty((cap, 3), dtype=torch.float32, device=dev)
+    log_scales = torch.empty((cap, 3), dtype=torch.float32, device=dev)
+    phase = torch.empty((cap, n_lam), dtype=torch.float32, device=dev)
+    n_out = torch.empty((), dtype=torch.int64, device=dev)
+    check(lib.chrf_densify(C.byref(d), _ptr(scratch), cap, _ptr(src), _ptr(kind), _ptr(means), _ptr(log_scales),
+                           _ptr(phase), _ptr(n_out), _stream()))
+    m = int(n_out)   # synchronises
+    if m > cap:
+        raise RuntimeError(f"densify: {m} outputs exceed the capacity {cap}")
+    return m, src[:m], kind[:m], means[:m], log_scales[:m], phase[:m], n_out
+
+
+def gather_rows(values: torch.Tensor, src: torch.Tensor, kind: torch.Tensor, n_out: torch.Tensor, zero_new: bool):
+    """values [n, ...] carried through a densification: row j is values[src[j]]
+    (zero for new Gaussians when zero_new)."""
+    lib = _lib.load()
+    m = int(src.shape[0])
+    row = int(math.prod(values.shape[1:]))
+    out = torch.empty((m,) + tuple(values.shape[1:]), dtype=torch.float32, device=values.device)
+    assert values.dtype == torch.float32 and values.is_contiguous()
+    check(lib.chrf_gather_rows(_ptr(values), row, _ptr(src), _ptr(kind), _ptr(n_out), m, 1 if zero_new else 0,
+                               _ptr(out), _stream()))
+    return out
+
+
+def cosine_lr(step, total, lr0, lr_min):
+    """Cosine annealing from lr0 at step 0 to lr_min at step ``total``."""
+    t = min(max(step, 0), total) / float(total)
+    return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + math.cos(math.pi * t))
+
+
+class Trainer:
+    """The optimisation loop of the paper's training algorithm on given target
+    intensities.  Each step renders and differentiates with the library (the
+    plan's loss; straight-through plane assignment on a layered renderer),
+    applies Adan to every parameter tensor with the paper's per-parameter
+    learning rates (cosine annealing to lr_min for means and plane logits),
+    and accumulates the view-space gradient statistics; every
+    ``densify_every`` steps up to ``densify_until`` the Gaussians are pruned,
+    cloned and split by the library.
+
+    Parameters are kept raw: opacity as a logit (the library takes the
+    activated value, so the sigmoid and its derivative are applied here).
+    A renderer whose Gaussian or pair capacity becomes too small is replaced
+    by a larger one of the same configuration."""
+
+    LR = dict(means=0.01, log_scales=0.005, quats=0.001, opacity=0.025, amp=0.0025, phase=0.0025, logits=0.01)
+    ANNEALED = ("means", LAYER_LOGITS)
+
+    def __init__(self, renderer: Renderer, params: dict, cams: torch.Tensor, target: torch.Tensor, masks=None,
+                 total_steps=20000, densify_every=300, densify_until=None, densify_cfg: DensifyConfig = None,
+                 lr_min=1e-5, seed=0, pair_headroom=1.25):
+        self.r = renderer
+        self.cams, self.target, self.masks = cams, target, masks
+        self.p = {k: params[k].detach().clone().contiguous() for k in renderer.param_names()}
+        self.state = {k: {} for k in self.p}
+        self.total_steps = int(total_steps)
+        self.densify_every = int(densify_every)
+        self.densify_until = int(densify_until if densify_until is not None else total_steps // 2)
+        self.cfg = densify_cfg or DensifyConfig()
+        self.lr_min = lr_min
+        self.headroom = pair_headroom
+        self.gen = torch.Generator(device=self.p["means"].device).manual_seed(seed)
+        self.step_count = 0
+        self._reset_stats()
+        self._ensure_capacity()
+
+    @property
+    def n(self) -> int:
+        return int(self.p["means"].shape[0])
+
+    def _reset_stats(self):
+        dev = self.p["means"].device
+        self.accum = torch.zeros(self.n, dtype=torch.float32, device=dev)
+        self.count = torch.zeros(self.n, dtype=torch.float32, device=dev)
+
+    def render_params(self) -> dict:
+        d = dict(self.p)
+        d["opacity"] = torch.sigmoid(self.p["opacity"]).contiguous()
+        return d
+
+    def _ensure_capacity(self):
+        if self.n > self.r.max_gaussians:
+            self.r = self.r.resized(max_gaussians=int(math.ceil(1.5 * self.n)))
+        self.r.forward(self.render_params(), self.cams, want_field=False, want_intensity=False)
+        st, need = self.r.read_status()
+        if st != 0:
+            self.r = self.r.resized(max_pairs=int(need * self.headroom) + 4096)
+
+    def step(self):
+        """One training step; returns the loss (device scalar) before the update."""
+        self.step_count += 1
+        rp = self.render_params()
+        loss, grads, _ = self.r.train_step(rp, self.cams, self.target, masks=self.masks)
+        o = rp["opacity"]
+        grads["opacity"] = (grads["opacity"] * o * (1.0 - o)).contiguous()
+        self.r.densify_stats(self.n, self.accum, self.count)
+        for k, t in self.p.items():
+            lr = self.LR[k]
+            if k in self.ANNEALED:
+                lr = cosine_lr(self.step_count, self.total_steps, lr, self.lr_min)
+            adan_step(t, grads[k], self.state[k], lr, self.step_count)
+        if self.step_count % self.densify_every == 0 and self.step_count <= self.densify_until:
+            self.densify()
+        return loss
+
+    def densify(self):
+        """Prune, clone and split by the accumulated statistics; parameters and
+        optimiser state follow the library's index map (fresh state for new
+        Gaussians)."""
+        n = self.n
+        dev = self.p["means"].device
+        n_lam = int(self.p["phase"].shape[1])
+        xi = torch.randn((n, 2, 3), generator=self.gen, device=dev, dtype=torch.float32)
+        zeta = torch.randn((n, 2, n_lam), generator=self.gen, device=dev, dtype=torch.float32)
+        opacity = torch.sigmoid(self.p["opacity"]).contiguous()
+        m, src, kind, means, log_scales, phase, n_out = densify(self.p, opacity, self.accum, self.count, xi, zeta,
+                                                                self.cfg)
+        changed = {"means": means, "log_scales": log_scales, "phase": phase}
+        new_p = {}
+        for k, t in self.p.items():
+            new_p[k] = changed[k].contiguous() if k in changed else gather_rows(t, src, kind, n_out, False)
+        self.state = {k: {s: gather_rows(v, src, kind, n_out, True) for s, v in st.items()}
+                      for k, st in self.state.items()}
+        self.p = new_p
+        self._reset_stats()
+        self._ensure_capacity()
+        return m
 
 
 class CapturedTrainStep:

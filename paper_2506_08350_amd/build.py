@@ -22,6 +22,7 @@ LIB = os.path.join(HERE, "libchrf.so")
 ARCH = os.environ.get("CHRF_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["project.hip", "sort.hip", "raster.hip", "raster_layers.hip", "asm.hip", "asm_tuned.hip", "loss.hip",
+           "train.hip",
            "capi.cpp"]
 
 FLAGS = [

@@ -512,7 +512,7 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
                                               BN, at<uint64_t>(plan, ws, R_SCAN_TMP), total, s));
   uint2* ranges = at<uint2>(plan, ws, R_RANGES);
   RUN("ranges_clear", launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (int64_t)2 * plan->B * plan->n_tiles, s));
-  RUN("emit_pairs", launch_emit_pairs(gval, at<uint64_t>(plan, ws, R_OFFSETS), at<uint32_t>(plan, ws, R_GCOUNT),
+  RUN("emit_pairs", launch_emit_pairs(gval, at<uint64_t>(plan, ws, R_OFFSETS), at<uint32_t>(plan, ws, R_CNT_SORTED),
                                       at<int4>(plan, ws, R_RECT), BN, Nst, plan->d.tile_w, plan->d.tile_h,
                                       plan->tiles_x, plan->n_tiles, at<uint32_t>(plan, ws, R_PKEY),
                                       at<uint32_t>(plan, ws, R_PVAL), plan->cap, total, status + 2, s));
@@ -763,6 +763,97 @@ chrf_status chrf_adam_step(float* param, const float* grad, float* m, float* v, 
   if (step < 1 || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
     return fail(CHRF_EINVAL, "chrf_adam_step: step must be >= 1, betas in [0, 1), eps > 0");
   HIP_TRY(launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)hip_stream));
+  return CHRF_OK;
+}
+
+chrf_status chrf_adan_step(float* param, const float* grad, float* grad_prev, float* m, float* v, float* nm,
+                           int64_t n, float lr, float beta1, float beta2, float beta3, float eps, float weight_decay,
+                           int32_t step, void* hip_stream) {
+  if (n < 0 || (n > 0 && (!param || !grad || !grad_prev || !m || !v || !nm)))
+    return fail(CHRF_EINVAL, "chrf_adan_step: bad argument");
+  const bool betas_ok = beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && beta3 >= 0 && beta3 < 1;
+  if (step < 1 || !betas_ok || !(eps > 0) || !(weight_decay >= 0))
+    return fail(CHRF_EINVAL, "chrf_adan_step: step must be >= 1, betas in [0, 1), eps > 0, weight_decay >= 0");
+  HIP_TRY(launch_adan(param, grad, grad_prev, m, v, nm, n, lr, beta1, beta2, beta3, eps, weight_decay, step,
+                      (hipStream_t)hip_stream));
+  return CHRF_OK;
+}
+
+chrf_status chrf_densify_stats(chrf_plan* plan, void* ws, int32_t n, float* grad_accum, float* grad_count,
+                               void* hip_stream) {
+  if (!plan || !ws || (n > 0 && (!grad_accum || !grad_count))) return fail(CHRF_EINVAL, "chrf_densify_stats: NULL argument");
+  if (n < 0 || n > plan->N) return fail(CHRF_EINVAL, "chrf_densify_stats: n exceeds the plan's max_gaussians");
+  HIP_TRY(launch_densify_stats(at<float>(plan, ws, R_GRAD2D), plan->g2, at<uint32_t>(plan, ws, R_GCOUNT), n,
+                               std::max(plan->N, 1), plan->B, grad_accum, grad_count, (hipStream_t)hip_stream));
+  return CHRF_OK;
+}
+
+struct DensifyScratch {
+  size_t counts, offsets, tmp, bytes;
+};
+
+static DensifyScratch densify_scratch(int64_t n) {
+  DensifyScratch d;
+  const int64_t m = std::max<int64_t>(n, 1);
+  d.counts = 0;
+  d.offsets = align256(sizeof(uint32_t) * m);
+  d.tmp = d.offsets + align256(sizeof(uint64_t) * m);
+  d.bytes = d.tmp + align256(sizeof(uint64_t) * (scan_tmp_elems(m) + 16));
+  return d;
+}
+
+size_t chrf_densify_workspace_bytes(int64_t n) { return n < 0 ? 0 : densify_scratch(n).bytes; }
+
+chrf_status chrf_densify(const chrf_densify_desc* d, void* scratch, int64_t capacity, int32_t* src, int32_t* kind,
+                         float* means_out, float* log_scales_out, float* phase_out, int64_t* n_out,
+                         void* hip_stream) {
+  if (!d || !scratch || !n_out) return fail(CHRF_EINVAL, "chrf_densify: NULL argument");
+  if (d->n < 0 || d->n_lambda < 1 || d->n_lambda > kMaxLambda || capacity < 0)
+    return fail(CHRF_EINVAL, "chrf_densify: bad sizes");
+  if (d->n > 0 && (!d->means || !d->log_scales || !d->quats || !d->opacity || !d->phase || !d->grad_accum ||
+                   !d->grad_count || !d->xi || !d->zeta))
+    return fail(CHRF_EINVAL, "chrf_densify: NULL input array");
+  if (capacity > 0 && (!src || !kind || !means_out || !log_scales_out || !phase_out))
+    return fail(CHRF_EINVAL, "chrf_densify: NULL output array");
+  DensifyArgs a{};
+  a.n = d->n;
+  a.n_lambda = d->n_lambda;
+  a.means = d->means;
+  a.log_scales = d->log_scales;
+  a.quats = d->quats;
+  a.opacity = d->opacity;
+  a.phase = d->phase;
+  a.grad_accum = d->grad_accum;
+  a.grad_count = d->grad_count;
+  a.xi = d->xi;
+  a.zeta = d->zeta;
+  a.tau_grad = d->tau_grad;
+  a.sigma_split = d->sigma_split;
+  a.sigma_prune = d->sigma_prune;
+  a.min_opacity = d->min_opacity;
+  a.phase_sigma = d->phase_sigma;
+  a.shrink = d->shrink;
+  a.capacity = capacity;
+  a.src = src;
+  a.kind = kind;
+  a.means_out = means_out;
+  a.log_scales_out = log_scales_out;
+  a.phase_out = phase_out;
+  const DensifyScratch ds = densify_scratch(d->n);
+  char* base = static_cast<char*>(scratch);
+  HIP_TRY(launch_densify(a, reinterpret_cast<uint32_t*>(base + ds.counts), reinterpret_cast<uint64_t*>(base + ds.offsets),
+                         reinterpret_cast<uint64_t*>(base + ds.tmp), reinterpret_cast<uint64_t*>(n_out),
+                         (hipStream_t)hip_stream));
+  return CHRF_OK;
+}
+
+chrf_status chrf_gather_rows(const float* in, int64_t row, const int32_t* src, const int32_t* kind,
+                             const int64_t* n_out, int64_t capacity, int32_t zero_new, float* out,
+                             void* hip_stream) {
+  if (row < 1 || capacity < 0) return fail(CHRF_EINVAL, "chrf_gather_rows: bad sizes");
+  if (capacity > 0 && (!in || !src || !kind || !n_out || !out)) return fail(CHRF_EINVAL, "chrf_gather_rows: NULL argument");
+  HIP_TRY(launch_gather_rows(in, row, src, kind, reinterpret_cast<const uint64_t*>(n_out), capacity, zero_new,
+                             out, (hipStream_t)hip_stream));
   return CHRF_OK;
 }
 

@@ -104,7 +104,7 @@ int64_t radix_hist_elems(int64_t n_max);
 
 hipError_t launch_gather_counts(const uint32_t* sorted_val, const uint32_t* count, uint32_t* out, int64_t n,
                                 hipStream_t s);
-hipError_t launch_emit_pairs(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* count,
+hipError_t launch_emit_pairs(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* cnt_sorted,
                              const int4* rect, int64_t n, int n_stride, int tile_w, int tile_h, int tiles_x,
                              int n_tiles, uint32_t* pair_key, uint32_t* pair_val, int64_t capacity,
                              const uint64_t* total, uint32_t* status, hipStream_t s);
@@ -201,5 +201,24 @@ hipError_t launch_cols_adjoint_t(const float2* z, float2* w1, const AsmGeom& g, 
                                  hipStream_t s);
 size_t col_lds_bytes(int pH, int C);
 int fft_max_elems();
+
+// ------------------------------------------------------------ training ---
+hipError_t launch_adan(float* x, const float* g, float* g_prev, float* m, float* v, float* nn, int64_t n, float lr,
+                       float b1, float b2, float b3, float eps, float weight_decay, int step, hipStream_t s);
+hipError_t launch_densify_stats(const float* grad2d, int g2stride, const uint32_t* count, int n, int n_stride,
+                                int n_views, float* accum, float* seen, hipStream_t s);
+
+struct DensifyArgs {
+  int n, n_lambda;
+  const float *means, *log_scales, *quats, *opacity, *phase, *grad_accum, *grad_count, *xi, *zeta;
+  float tau_grad, sigma_split, sigma_prune, min_opacity, phase_sigma, shrink;
+  int64_t capacity;
+  int32_t *src, *kind;
+  float *means_out, *log_scales_out, *phase_out;
+};
+hipError_t launch_densify(const DensifyArgs& a, uint32_t* counts, uint64_t* offsets, uint64_t* scan_tmp,
+                          uint64_t* total, hipStream_t s);
+hipError_t launch_gather_rows(const float* in, int64_t row, const int32_t* src, const int32_t* kind,
+                              const uint64_t* live, int64_t capacity, int zero_new, float* out, hipStream_t s);
 
 }  // namespace chrf

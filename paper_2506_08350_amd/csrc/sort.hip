@@ -311,47 +311,54 @@ hipError_t launch_gather_counts(const uint32_t* sorted_val, const uint32_t* coun
   return hipGetLastError();
 }
 
-// One thread per pair.  Pair p belongs to the sorted (view, Gaussian) entry i
-// with offsets[i] <= p < offsets[i] + count (found by binary search over the
-// exclusive scan of the counts); its tiles are enumerated in row-major order
-// over the Gaussian's tile rectangle.  Pairs past the capacity are dropped and
-// flagged, so every write stays in bounds.
-__global__ void k_emit_pairs(const uint32_t* __restrict__ sorted_val, const uint64_t* __restrict__ offsets,
-                             const uint32_t* __restrict__ count, const int4* __restrict__ rect, int64_t n,
-                             int n_stride, int tile_w, int tile_h, int tiles_x, int n_tiles,
-                             uint32_t* __restrict__ pair_key, uint32_t* __restrict__ pair_val, int64_t capacity,
-                             const uint64_t* total, uint32_t* status) {
-  const uint64_t tot = *total;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p == 0 && tot > (uint64_t)capacity) status[0] = 1u;
-  const int64_t live = tot < (uint64_t)capacity ? (int64_t)tot : capacity;
-  if (p >= live) return;
-  // largest i with offsets[i] <= p; entries with zero count share the offset of
-  // the next one, so take the last of a run of equal offsets
-  int64_t lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (offsets[mid] <= (uint64_t)p) lo = mid; else hi = mid - 1;
-  }
-  const uint32_t rid = sorted_val[lo];
+// A team of kTeam consecutive lanes per sorted (view, Gaussian) entry i: its
+// count[i] pairs are the tiles of its rectangle in row-major order, written
+// to offsets[i] + local by consecutive lanes, so every store of a team is one
+// contiguous run.  Pairs past the capacity are dropped and flagged, so every
+// write stays in bounds.
+constexpr int kEmitTeam = 16;
+
+__global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ sorted_val,
+                                                    const uint64_t* __restrict__ offsets,
+                                                    const uint32_t* __restrict__ cnt_sorted,
+                                                    const int4* __restrict__ rect, int64_t n, int n_stride,
+                                                    int tile_w, int tile_h, int tiles_x, int n_tiles,
+                                                    uint32_t* __restrict__ pair_key, uint32_t* __restrict__ pair_val,
+                                                    int64_t capacity, const uint64_t* total, uint32_t* status) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kEmitTeam;
+  const int lane = threadIdx.x % kEmitTeam;
+  if (i == 0 && lane == 0 && *total > (uint64_t)capacity) status[0] = 1u;
+  if (i >= n) return;
+  const uint32_t cnt = cnt_sorted[i];
+  if (cnt == 0) return;
+  const uint64_t base = offsets[i];
+  if (base >= (uint64_t)capacity) return;
+  const int64_t room = capacity - (int64_t)base;
+  const int lim = room < (int64_t)cnt ? (int)room : (int)cnt;
+  const uint32_t rid = sorted_val[i];
   const int4 rc = rect[rid];
   const int tx0 = rc.x / tile_w, tx1 = (rc.x + rc.y) / tile_w;
   const int ty0 = rc.z / tile_h;
   const int wt = tx1 - tx0 + 1;
-  const int local = (int)(p - (int64_t)offsets[lo]);
   const uint32_t view = rid / (uint32_t)n_stride;
-  pair_key[p] = view * (uint32_t)n_tiles + (uint32_t)((ty0 + local / wt) * tiles_x + tx0 + local % wt);
-  pair_val[p] = rid;
+  const uint32_t k0 = view * (uint32_t)n_tiles + (uint32_t)(ty0 * tiles_x + tx0);
+  for (int local = lane; local < lim; local += kEmitTeam) {
+    const int dy = local / wt;
+    const int dx = local - dy * wt;
+    pair_key[base + local] = k0 + (uint32_t)(dy * tiles_x + dx);
+    pair_val[base + local] = rid;
+  }
 }
 
-hipError_t launch_emit_pairs(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* count,
+hipError_t launch_emit_pairs(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* cnt_sorted,
                              const int4* rect, int64_t n, int n_stride, int tile_w, int tile_h, int tiles_x,
                              int n_tiles, uint32_t* pair_key, uint32_t* pair_val, int64_t capacity,
                              const uint64_t* total, uint32_t* status, hipStream_t s) {
   if (n <= 0 || capacity <= 0) return hipSuccess;
-  k_emit_pairs<<<(unsigned)((capacity + 255) / 256), 256, 0, s>>>(sorted_val, offsets, count, rect, n, n_stride,
-                                                                  tile_w, tile_h, tiles_x, n_tiles, pair_key,
-                                                                  pair_val, capacity, total, status);
+  const int64_t threads = n * kEmitTeam;
+  k_emit_pairs<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(sorted_val, offsets, cnt_sorted, rect, n,
+                                                                  n_stride, tile_w, tile_h, tiles_x, n_tiles,
+                                                                  pair_key, pair_val, capacity, total, status);
   return hipGetLastError();
 }
 

@@ -53,6 +53,8 @@ int main(void) {
          offsetof(chrf_gaussians, logits), offsetof(chrf_grads, logits));
   printf("%zu %zu %zu\n", offsetof(chrf_plan_desc, loss_kind), offsetof(chrf_plan_desc, ssim_weight),
          offsetof(chrf_plan_desc, phase_only));
+  printf("%zu %zu %zu %zu\n", sizeof(chrf_densify_desc), offsetof(chrf_densify_desc, zeta),
+         offsetof(chrf_densify_desc, tau_grad), offsetof(chrf_densify_desc, shrink));
   return 0;
 }
 """
@@ -63,10 +65,12 @@ int main(void) {
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     P = _lib.PlanDesc
+    D = _lib.DensifyDesc
     assert vals == [ctypes.sizeof(P), ctypes.sizeof(_lib.Camera), ctypes.sizeof(_lib.Gaussians),
                     ctypes.sizeof(_lib.Grads), P.k_sigma.offset, P.pitch.offset, P.distances.offset,
                     P.cols_per_block.offset, P.layered.offset, _lib.Gaussians.logits.offset,
-                    _lib.Grads.logits.offset, P.loss_kind.offset, P.ssim_weight.offset, P.phase_only.offset]
+                    _lib.Grads.logits.offset, P.loss_kind.offset, P.ssim_weight.offset, P.phase_only.offset,
+                    ctypes.sizeof(D), D.zeta.offset, D.tau_grad.offset, D.shrink.offset]
 
 
 def test_camera_record_packing_matches_struct():

@@ -123,9 +123,12 @@ def test_wide_rows_propagation_and_fused_loss(W):
     assert rel_l2(cplx(prop[0, 0, 1]), oracle.propagate(U[0, 0], 515e-9, 2e-3, 8e-6, 2, 2)) < TOL
     gen = torch.Generator(device="cuda").manual_seed(3)
     tgt = torch.rand((1, 1, 2, H, W), generator=gen, device="cuda")
+    sums_before = [float(t.double().sum()) for t in (tgt, prop)]
     out = r.forward(to_device(make_gaussians(0, 1, 9)), api.pack_cameras([cam]), want_field=False,
                     want_intensity=True, target=tgt)
     torch.cuda.synchronize()
+    # the forward writes none of the caller's buffers it was not given
+    assert [float(t.double().sum()) for t in (tgt, prop)] == sums_before
     assert float(out["intensity"].abs().max()) == 0.0
     part = r.region(_lib.REGION_LOSS_PARTIAL, torch.float32)[:2 * H].double()
     rows = (tgt.double() ** 2).sum(-1).reshape(-1)

@@ -159,8 +159,10 @@ def test_four_views_2160p_2m_16_planes():
     B, L, K, H, W = r.B, r.L, r.K, r.H, r.W
     gen = torch.Generator(device="cuda").manual_seed(1005 + 10_000)
     target = torch.rand((B, L, K, H, W), generator=gen, device="cuda")
+    target_sum = float(target.double().sum())
     out = r.forward(params, cam_t, want_field=True, want_intensity=True, target=target)
     torch.cuda.synchronize()
+    assert float(target.double().sum()) == target_sum
     assert r.read_status()[0] == 0
     I = out["intensity"]
     assert torch.isfinite(out["field"]).all() and torch.isfinite(I).all()
