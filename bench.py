@@ -95,6 +95,34 @@ def measured_traffic(kernel):
     return table[kernel]
 
 
+VALU_PROFILE = os.path.join(ROOT, "profiles", "valu_step_c3_1080p_100k.md")
+VALU_NAMES = {"cols_adjoint": "k_cols_adjoint_t", "cols_forward": "k_cols_forward_t",
+              "raster_backward": "k_raster_bwd", "raster_forward": "k_raster_fwd"}
+
+
+def measured_valu_busy(kernel):
+    """VALU-busy fraction of ``kernel`` from the committed SQ counter summary
+    (SQ_INSTS_VALU x 4 cycles over the SIMD cycles of the launch), or None
+    when the summary is missing, does not cover the kernel, or any of the
+    kernel's sources changed since the counters were taken."""
+    try:
+        text = open(VALU_PROFILE).read()
+    except OSError:
+        return None
+    shas, busy = {}, None
+    for line in text.splitlines():
+        if line.startswith("source-sha256 "):
+            _, name, sha = line.split()
+            shas[name] = sha
+        cells = [c.strip(" `") for c in line.strip().strip("|").split("|")]
+        if len(cells) == 7 and kernel in VALU_NAMES and cells[0].startswith(VALU_NAMES[kernel] + "<"):
+            busy = float(cells[6])
+    files = KERNEL_SOURCES.get(kernel)
+    if busy is None or not files or any(shas.get(f) != source_sha256(f) for f in files):
+        return None
+    return busy
+
+
 def cpu_baseline(w, seed=0):
     """Time the CPU oracle on a bounded sample of the workload.
 
@@ -320,7 +348,9 @@ def main(argv=None):
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
-                "avg_ms": round(dom_ms, 4), "algorithmic_bytes": dom_bytes}
+                "avg_ms": round(dom_ms, 4), "algorithmic_bytes": dom_bytes,
+                # the kernel's vector-ALU occupancy from the SQ counters: the bound the HBM fraction leaves
+                "valu_busy": measured_valu_busy(dom)}
     if args.kernel_table:
         tot = sum(c * m for c, m in per_launch.values())
         for n, (c, m) in sorted(per_launch.items(), key=lambda kv: -kv[1][0] * kv[1][1]):

@@ -375,7 +375,9 @@ chrf_status chrf_gather_rows(const float* in, int64_t row, const int32_t* src, c
                              void* hip_stream);
 
 /* Synchronise the stream and report the last forward's pair-list status:
- * CHRF_OK, or CHRF_ECAPACITY with *pairs_needed set. */
+ * CHRF_OK, CHRF_ECAPACITY with *pairs_needed set, or CHRF_EHIP if a wait of
+ * the radix sort's look-back gave up (its output is then not valid; the
+ * wait is bounded so that no kernel can run forever). */
 chrf_status chrf_read_status(chrf_plan* plan, void* workspace, int64_t* pairs_needed, void* hip_stream);
 
 /*

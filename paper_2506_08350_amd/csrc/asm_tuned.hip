@@ -38,11 +38,11 @@ __device__ inline int opaque_v(int v) {
 }
 
 // Transfer function H_k at the bins of one column.  The column terms are
-// computed once per plane; per element the band tests are integer compares,
-// the residual phase is formed in revolutions with the hardware square root
-// and reciprocal, reduced to [-0.5, 0.5] (exact) and fed to the hardware
-// sine and cosine, which take their argument in revolutions.  The
-// 1 / (pH pW) normalisation is applied by the callers outside the plane loop.
+// computed once; per element the band tests are integer compares, the
+// residual phase is formed in revolutions with the hardware square root and
+// reciprocal, reduced to [-0.5, 0.5] (exact) and fed to the hardware sine and
+// cosine, which take their argument in revolutions.  The 1 / (pH pW)
+// normalisation is applied by the callers outside the plane loop.
 struct ColFreq {
   long long cterm;   // sx^2 pH^2 of the evanescent bin test
   float fx2;         // fx^2
@@ -59,20 +59,7 @@ __device__ inline ColFreq col_freq(const HParam& hp, int kx, const AsmGeom& g) {
   return c;
 }
 
-__device__ inline cpx transfer_col(const HParam& hp, const ColFreq& c, int ky, const AsmGeom& g) {
-  const int sy = sbin(ky, g.pH);
-  const long long lhs = c.cterm + (long long)(sy * sy) * (long long)(g.pW * g.pW);
-  const bool pass = c.pass && (g.band_mode < 2 || abs(sy) <= hp.ky_max) && lhs <= hp.evan_bound;
-  const float fy = (float)sy * g.ay;
-  const float f2 = fy * fy + c.fx2;
-  const float root = __builtin_amdgcn_sqrtf(fmaxf(hp.inv_lam2 - f2, 0.0f));
-  float rev = hp.frac_rev - (hp.z * f2) * __builtin_amdgcn_rcpf(hp.inv_lam + root);
-  rev -= __builtin_rintf(rev);
-  const float cs = __builtin_amdgcn_cosf(rev), sn = __builtin_amdgcn_sinf(rev);
-  return pass ? cpx{cs, sn} : cpx{0.f, 0.f};
-}
-
-// The same transfer function split into its plane-independent part, computed
+// The transfer function split into its plane-independent part, computed
 // once per bin before the plane loop: q = f^2 / (1/lambda + sqrt(1/lambda^2 -
 // f^2)), so that the residual phase of plane z is -z q revolutions; -1 marks a
 // bin beyond the evanescent cut.  Per plane only the carrier, one
@@ -254,6 +241,10 @@ __global__ __launch_bounds__(256) void k_rows_adjoint_out_t(const float2* __rest
 //          workgroups share a CU.
 constexpr int kColN = 2160;
 
+#ifndef CHRF_C2_LDS_TWIDDLES
+#define CHRF_C2_LDS_TWIDDLES 0
+#endif
+
 template <int C>
 struct ColT {
   static constexpr int NT = 256 * C;
@@ -262,7 +253,8 @@ struct ColT {
   static_assert(Fwd::M1 == 1 && Fwd::M3 == 1 && Inv::M1 == 1 && Inv::M3 == 1, "one butterfly per thread");
   static_assert(Fwd::B3 == Inv::B1, "forward outputs feed the inverse inputs");
   static constexpr int SPAN = 128 / (8 * C);   // column groups per 128-byte line
-  static constexpr bool kRegSpec = C == 2;      // spectrum in registers, twiddles from memory
+  static constexpr bool kRegSpec = C == 2;      // spectrum in registers
+  static constexpr bool kLdsTw = !kRegSpec || CHRF_C2_LDS_TWIDDLES;   // twiddle table in LDS, read per power
   static constexpr int kMinBlocks = kRegSpec ? 2 : 1;
 };
 
@@ -291,8 +283,8 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
   using CT = ColT<C>;
   __shared__ cpx lds[lds_padded_size(kColN * C)];
   __shared__ cpx spec[CT::kRegSpec ? 1 : kColN * C];
-  __shared__ cpx s_tw[CT::kRegSpec ? 1 : kColN];
-  const cpx* twl = CT::kRegSpec ? fc.tw : stage_twiddles<CT::NT>(s_tw, fc.tw);
+  __shared__ cpx s_tw[CT::kLdsTw ? kColN : 1];
+  const cpx* twl = CT::kLdsTw ? stage_twiddles<CT::NT>(s_tw, fc.tw) : fc.tw;
   cpx sreg[CT::kRegSpec ? 9 : 1];
   const int ngroups = g.pW / C;
   const int gid = col_remap(blockIdx.x, gridDim.x, CT::SPAN);
@@ -311,7 +303,7 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
         v1[0][r] = live ? ldc(x1 + ((size_t)bl * g.H + n) * g.pW + c0 + s) : cpx{0.f, 0.f};
       }
     }
-    CT::Fwd::template run<!CT::kRegSpec>(v1, v3, lds, twl);
+    CT::Fwd::template run<CT::kLdsTw>(v1, v3, lds, twl);
     if (b < CT::Fwd::B3) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
@@ -341,7 +333,7 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
         w1[0][q] = cmul(sv, transfer_from_q(hp, col_pass, qv[q], jj + q * (kColN / 9), g));
       }
     }
-    CT::Inv::template run<!CT::kRegSpec>(w1, w3, lds, twl, opaque_v(b));
+    CT::Inv::template run<CT::kLdsTw>(w1, w3, lds, twl, opaque_v(b));
     if (b < CT::Inv::B3) {
       float2* yk = y + ((size_t)bl * g.K + k) * g.H * g.pW + kx;
 #pragma unroll
@@ -358,8 +350,8 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoi
     const float2* __restrict__ z, float2* __restrict__ w1out, AsmGeom g, FftDesc fc) {
   using CT = ColT<C>;
   __shared__ cpx lds[lds_padded_size(kColN * C)];
-  __shared__ cpx s_tw[CT::kRegSpec ? 1 : kColN];
-  const cpx* twl = CT::kRegSpec ? fc.tw : stage_twiddles<CT::NT>(s_tw, fc.tw);
+  __shared__ cpx s_tw[CT::kLdsTw ? kColN : 1];
+  const cpx* twl = CT::kLdsTw ? stage_twiddles<CT::NT>(s_tw, fc.tw) : fc.tw;
   const int ngroups = g.pW / C;
   const int gid = col_remap(blockIdx.x, gridDim.x, CT::SPAN);
   const int bl = gid / ngroups;
@@ -370,6 +362,15 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoi
   cpx acc[1][9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) acc[0][q] = cpx{0.f, 0.f};
+  // plane-independent transfer terms of this thread's 9 bins, kept in LDS
+  // (each thread reads back only its own entries) to spare registers
+  __shared__ float s_q[9][CT::NT];
+  if (b < CT::Fwd::B3) {
+    const HParam hp0 = g.hp[lam * g.K];
+    const ColFreq cf = col_freq(hp0, c0 + s, g);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s_q[q][b] = transfer_q(hp0, cf, j + q * (kColN / 9), g);
+  }
   for (int k = 0; k < g.K; ++k) {
     const float2* zk = z + ((size_t)bl * g.K + k) * g.H * g.pW + c0 + s;
     const int jj = opaque_v(j), kx = opaque_v(c0 + s);
@@ -381,19 +382,19 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoi
         v1[0][r] = (HALF ? r < 8 : n < g.H) ? ldc(zk + (size_t)n * g.pW) : cpx{0.f, 0.f};
       }
     }
-    CT::Fwd::template run<false>(v1, v3, lds, twl, opaque_v(b));   // (table twiddles here would spill)
+    CT::Fwd::template run<CT::kLdsTw && CT::kRegSpec>(v1, v3, lds, twl, opaque_v(b));   // C = 4 would spill with the table
     const HParam hp = g.hp[lam * g.K + k];
     if (b < CT::Fwd::B3) {
-      const ColFreq cf = col_freq(hp, kx, g);
+      const bool col_pass = g.band_mode < 2 || abs(sbin(kx, g.pW)) <= hp.kx_max;
 #pragma unroll
       for (int q = 0; q < 9; ++q)
-        acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_col(hp, cf, jj + q * (kColN / 9), g));
+        acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_from_q(hp, col_pass, s_q[q][b], jj + q * (kColN / 9), g));
     }
   }
 #pragma unroll
   for (int q = 0; q < 9; ++q) acc[0][q] = acc[0][q] * g.norm;
   cpx w3[1][16];
-  CT::Inv::template run<!CT::kRegSpec>(acc, w3, lds, twl);
+  CT::Inv::template run<CT::kLdsTw>(acc, w3, lds, twl);
   if (b < CT::Inv::B3) {
     float2* dst = w1out + (size_t)bl * g.H * g.pW + c0 + s;
 #pragma unroll

@@ -505,7 +505,7 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
   RUN("sort_gaussians", radix_sort_u64(at<uint64_t>(plan, ws, R_GKEY), at<uint64_t>(plan, ws, R_GKEY_ALT),
                                        at<uint32_t>(plan, ws, R_GVAL), at<uint32_t>(plan, ws, R_GVAL_ALT), BN,
                                        nullptr, 0, plan->gsort_bits, at<uint32_t>(plan, ws, R_HIST),
-                                       at<uint32_t>(plan, ws, R_SCAN_TMP), &galt, s));
+                                       at<uint32_t>(plan, ws, R_SCAN_TMP), status + 3, &galt, s));
   const uint32_t* gval = at<uint32_t>(plan, ws, galt ? R_GVAL_ALT : R_GVAL);
   RUN("gather_counts", launch_gather_counts(gval, at<uint32_t>(plan, ws, R_GCOUNT), at<uint32_t>(plan, ws, R_CNT_SORTED), BN, s));
   RUN("scan_counts", launch_scan_u64_from_u32(at<uint32_t>(plan, ws, R_CNT_SORTED), at<uint64_t>(plan, ws, R_OFFSETS),
@@ -520,7 +520,7 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
   RUN("sort_pairs", radix_sort_u32(at<uint32_t>(plan, ws, R_PKEY), at<uint32_t>(plan, ws, R_PKEY_ALT),
                                    at<uint32_t>(plan, ws, R_PVAL), at<uint32_t>(plan, ws, R_PVAL_ALT), plan->cap,
                                    total, 0, plan->psort_bits, at<uint32_t>(plan, ws, R_HIST),
-                                   at<uint32_t>(plan, ws, R_SCAN_TMP), &palt, s));
+                                   at<uint32_t>(plan, ws, R_SCAN_TMP), status + 3, &palt, s));
   const uint32_t* pkey = at<uint32_t>(plan, ws, palt ? R_PKEY_ALT : R_PKEY);
   const uint32_t* pval = at<uint32_t>(plan, ws, palt ? R_PVAL_ALT : R_PVAL);
   RUN("tile_ranges", launch_tile_ranges(pkey, total, plan->cap, ranges, s));
@@ -865,6 +865,7 @@ chrf_status chrf_read_status(chrf_plan* plan, void* ws, int64_t* pairs_needed, v
   HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
   const uint64_t total = (uint64_t)h[0] | ((uint64_t)h[1] << 32);
   if (pairs_needed) *pairs_needed = (int64_t)total;
+  if (h[3] != 0) return fail(CHRF_EHIP, "radix sort: a look-back wait gave up; the pair lists are not valid");
   if (h[2] != 0 || total > (uint64_t)plan->cap)
     return fail(CHRF_ECAPACITY, "pair list needs " + std::to_string(total) + " entries, capacity " +
                                     std::to_string(plan->cap));

@@ -283,6 +283,18 @@ __device__ inline cpx* fft_lds(cpx* buf0, cpx* buf1, int N, int C, int logC, con
 __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 5); }
 __host__ __device__ constexpr int lds_padded_size(int n) { return n + (n >> 5) + 1; }
 
+// lds_pad(x + r S) from p0 = lds_pad(x): when the stride S is a multiple of
+// 32 the padding grows by exactly S / 32 per step, so the address is p0 plus
+// a compile-time offset (no per-access shift and add).
+template <int S>
+__device__ inline int strided_pad(int p0, int x, int r) {
+  if constexpr (S % 32 == 0) {
+    return p0 + r * (S + S / 32);
+  } else {
+    return lds_pad(x + r * S);
+  }
+}
+
 template <int N, int C, int NT, int R1, int R2, int R3, bool INV>
 struct Fft3 {
   static_assert(R1 * R2 * R3 == N, "radices must multiply to N");
@@ -328,8 +340,15 @@ struct Fft3 {
       if (B1 % NT == 0 || b < B1) {
         const int s = b % C, j = b / C;
         Dft<R1, INV>::run(v1[i]);
+        if constexpr ((R1 * C) % 32 == 0 && 32 % C == 0) {
+          // j R1 C is a multiple of 32 and q C + s never crosses one past it
+          const int p0 = lds_pad(j * R1 * C) + s;
 #pragma unroll
-        for (int q = 0; q < R1; ++q) lds[lds_pad((j * R1 + q) * C + s)] = v1[i][q];
+          for (int q = 0; q < R1; ++q) lds[p0 + q * C + ((q * C) >> 5)] = v1[i][q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < R1; ++q) lds[lds_pad((j * R1 + q) * C + s)] = v1[i][q];
+        }
       }
     }
     __syncthreads();
@@ -340,8 +359,10 @@ struct Fft3 {
       const int b = tid + i * NT;
       if (B2 % NT == 0 || b < B2) {
         const int s = b % C, j = b / C, k = j % R1;
+        const int p0 = lds_pad(j * C + s);
 #pragma unroll
-        for (int r = 0; r < R2; ++r) v2[i][r] = lds[lds_pad((j + r * (N / R2)) * C + s)];
+        for (int r = 0; r < R2; ++r)
+          v2[i][r] = lds[strided_pad<(N / R2) * C>(p0, j * C + s, r)];
         apply_twiddles<R2, TABLE>(v2[i], tw, k * (N / (R1 * R2)));
         Dft<R2, INV>::run(v2[i]);
       }
@@ -353,8 +374,9 @@ struct Fft3 {
       if (B2 % NT == 0 || b < B2) {
         const int s = b % C, j = b / C, k = j % R1;
         const int base = (j - k) * R2 + k;
+        const int p0 = lds_pad(base * C + s);
 #pragma unroll
-        for (int q = 0; q < R2; ++q) lds[lds_pad((base + q * R1) * C + s)] = v2[i][q];
+        for (int q = 0; q < R2; ++q) lds[strided_pad<R1 * C>(p0, base * C + s, q)] = v2[i][q];
       }
     }
     __syncthreads();
@@ -364,8 +386,9 @@ struct Fft3 {
       const int b = tid + i * NT;
       if (B3 % NT == 0 || b < B3) {
         const int s = b % C, j = b / C;
+        const int p0 = lds_pad(j * C + s);
 #pragma unroll
-        for (int r = 0; r < R3; ++r) v3[i][r] = lds[lds_pad((j + r * (N / R3)) * C + s)];
+        for (int r = 0; r < R3; ++r) v3[i][r] = lds[strided_pad<(N / R3) * C>(p0, j * C + s, r)];
         apply_twiddles<R3, TABLE>(v3[i], tw, j);
         Dft<R3, INV>::run(v3[i]);
       }

@@ -94,12 +94,13 @@ hipError_t launch_scan_u64_from_u32(const uint32_t* in, uint64_t* out, int64_t n
 int64_t scan_tmp_elems(int64_t n);
 
 // Stable LSD radix sort.  n_dev (device, may be null) caps the count at run time.
+// error: device word set to 1 if a look-back wait of the single-sweep passes gave up
 hipError_t radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t n_max,
                           const uint64_t* n_dev, int begin_bit, int end_bit, uint32_t* hist, uint32_t* scan_tmp,
-                          bool* result_in_alt, hipStream_t s);
+                          uint32_t* error, bool* result_in_alt, hipStream_t s);
 hipError_t radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t n_max,
                           const uint64_t* n_dev, int begin_bit, int end_bit, uint32_t* hist, uint32_t* scan_tmp,
-                          bool* result_in_alt, hipStream_t s);
+                          uint32_t* error, bool* result_in_alt, hipStream_t s);
 int64_t radix_hist_elems(int64_t n_max);
 
 hipError_t launch_gather_counts(const uint32_t* sorted_val, const uint32_t* count, uint32_t* out, int64_t n,

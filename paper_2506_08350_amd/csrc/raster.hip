@@ -1,10 +1,11 @@
 // Complex front-to-back compositing per tile (Algorithm 2 with one plane;
 // Sec. 4.2) and its reverse-order backward.
 //
-// One workgroup (a single wave) per (view, tile).  The tile's sorted pair list
-// is walked in batches: the lanes stage Gaussian records (centre, conic,
-// opacity, support rectangle and the per-wavelength value c exp(j phi)) in
-// LDS, then every pixel consumes the whole batch with broadcast reads.
+// One workgroup per (view, tile), its waves sharing the tile's 8x8 pixel
+// blocks.  The tile's sorted pair list is walked in batches: the lanes stage
+// Gaussian records (centre, conic, opacity, support rectangle and the
+// per-wavelength value c exp(j phi)) in LDS, then every pixel consumes the
+// whole batch with broadcast reads.
 //
 // Forward per pixel:  a = min(alpha_max, o exp(-power)); if the pixel is in
 // the support rectangle, power <= k^2/2 and a >= alpha_min:
@@ -13,16 +14,19 @@
 //   dL/da = T_g sum_l Re(conj(G_l)(v_l - B_l)),  B_l <- a v_l + (1 - a) B_l,
 // and the per-pair gradients (d mu, d conic, d opacity, d v) are summed over a
 // lane's pixels, then over the wave (32- and 16-lane swaps, then DPP row
-// shifts), and added to the per-(view, Gaussian) accumulators with one atomic
-// per value.
+// shifts), then over the tile's waves in LDS, and added to the per-(view,
+// Gaussian) accumulators with one atomic per value.
 #include "raster_common.h"
 
 namespace chrf {
 
-template <int NL, int PPT>
-__global__ __launch_bounds__(kLanes) void k_raster_fwd(RasterArgs a) {
+// NW waves per tile, each owning PPT of the tile's 8x8 blocks (NW * PPT =
+// tile_w * tile_h / 64); the staged records are shared by the waves.
+template <int NL, int PPT, int NW>
+__global__ __launch_bounds__(kLanes * NW) void k_raster_fwd(RasterArgs a) {
   __shared__ Stage<NL> st;
   const TileGeom t = tile_of(a);
+  const int lane = threadIdx.x & (kLanes - 1), wave = threadIdx.x / kLanes;
   int px[PPT], py[PPT], bx[PPT], by[PPT];
   float pxf[PPT], pyf[PPT];
   bool inside[PPT], done[PPT];
@@ -31,8 +35,10 @@ __global__ __launch_bounds__(kLanes) void k_raster_fwd(RasterArgs a) {
   uint32_t last[PPT];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    pixel_of<PPT>(a, t, p, px[p], py[p]);
-    block_of(a, t, p, bx[p], by[p]);
+    const int pb = wave * PPT + p;
+    block_of(a, t, pb, bx[p], by[p]);
+    px[p] = bx[p] + (lane & 7);
+    py[p] = by[p] + (lane >> 3);
     pxf[p] = (float)px[p] + 0.5f;
     pyf[p] = (float)py[p] + 0.5f;
     inside[p] = px[p] < a.width && py[p] < a.height;
@@ -48,9 +54,14 @@ __global__ __launch_bounds__(kLanes) void k_raster_fwd(RasterArgs a) {
     bool all_done = true;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) all_done = all_done && done[p];
-    if (__all(all_done)) break;
+    // also the barrier before the next batch overwrites the staged records
+    if constexpr (NW == 1) {
+      if (__all(all_done)) break;
+      __syncthreads();
+    } else {
+      if (!__syncthreads_or(!all_done)) break;
+    }
     const int cnt = (int)min(rg.y - start, (uint32_t)kBatch);
-    __syncthreads();
     stage_records<NL>(st, a, start, cnt, false);
     __syncthreads();
     for (int j = 0; j < cnt; ++j) {
@@ -92,14 +103,16 @@ __global__ __launch_bounds__(kLanes) void k_raster_fwd(RasterArgs a) {
   }
 }
 
-template <int NL, int PPT>
-__global__ __launch_bounds__(kLanes) void k_raster_bwd(RasterArgs a) {
+// NW waves per tile as in the forward; the waves' per-pair sums meet in LDS.
+template <int NL, int PPT, int NW>
+__global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
   constexpr int G2 = 6 + 2 * NL;
   constexpr int G2P = (G2 + 3) & ~3;   // padded for the row-wise wave reduction
   __shared__ Stage<NL> st;
   __shared__ float s_grad[kBatch][G2];
+  __shared__ uint32_t s_last[NW];
   const TileGeom t = tile_of(a);
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kLanes - 1), wave = threadIdx.x / kLanes;
   int px[PPT], py[PPT], bx[PPT], by[PPT];
   float pxf[PPT], pyf[PPT];
   bool inside[PPT];
@@ -111,8 +124,9 @@ __global__ __launch_bounds__(kLanes) void k_raster_bwd(RasterArgs a) {
   uint32_t tile_last = 0;
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    pixel_of<PPT>(a, t, p, px[p], py[p]);
-    block_of(a, t, p, bx[p], by[p]);
+    block_of(a, t, wave * PPT + p, bx[p], by[p]);
+    px[p] = bx[p] + (lane & 7);
+    py[p] = by[p] + (lane >> 3);
     pxf[p] = (float)px[p] + 0.5f;
     pyf[p] = (float)py[p] + 0.5f;
     inside[p] = px[p] < a.width && py[p] < a.height;
@@ -137,9 +151,15 @@ __global__ __launch_bounds__(kLanes) void k_raster_bwd(RasterArgs a) {
   }
   // one past the last pair any pixel of the tile used
   for (int off = 32; off > 0; off >>= 1) tile_last = max(tile_last, (uint32_t)__shfl_xor((int)tile_last, off, 64));
+  if constexpr (NW > 1) {
+    if (lane == 0) s_last[wave] = tile_last;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NW; ++w) tile_last = max(tile_last, s_last[w]);
+  }
   const uint2 rg = a.ranges[blockIdx.x];
   const float half_k2 = 0.5f * a.k_sigma * a.k_sigma;
-  for (int i = lane; i < kBatch * G2; i += kLanes) (&s_grad[0][0])[i] = 0.f;
+  for (int i = threadIdx.x; i < kBatch * G2; i += kLanes * NW) (&s_grad[0][0])[i] = 0.f;
 
   for (uint32_t top = tile_last; top > rg.x;) {
     const int cnt = (int)min(top - rg.x, (uint32_t)kBatch);
@@ -199,7 +219,12 @@ __global__ __launch_bounds__(kLanes) void k_raster_bwd(RasterArgs a) {
 #pragma unroll
           for (int k = 0; k < G2P / 4; ++k) {
             const int c = k + row * (G2P / 4);
-            if (c < G2) s_grad[j][c] = gr[k];
+            if (c < G2) {
+              if constexpr (NW == 1)
+                s_grad[j][c] = gr[k];
+              else
+                atomicAdd(&s_grad[j][c], gr[k]);
+            }
           }
         }
       }
@@ -207,7 +232,7 @@ __global__ __launch_bounds__(kLanes) void k_raster_bwd(RasterArgs a) {
     __syncthreads();
     // lanes take consecutive components of consecutive pairs, so one atomic
     // instruction touches a handful of 64-byte gradient rows, not 64 of them
-    for (int t = lane; t < cnt * G2; t += kLanes) {
+    for (int t = threadIdx.x; t < cnt * G2; t += kLanes * NW) {
       const int i = t / G2, c = t - i * G2;
       const float sum = s_grad[i][c];
       if (sum != 0.f) unsafeAtomicAdd(a.grad2d + (size_t)st.rid[i] * a.g2stride + c, sum);
@@ -217,31 +242,78 @@ __global__ __launch_bounds__(kLanes) void k_raster_bwd(RasterArgs a) {
   }
 }
 
-#define CHRF_RASTER_DISPATCH(KERNEL)                                                          \
-  const int blocks = a.n_views * a.tiles_x * a.tiles_y;                                      \
-  if (blocks == 0) return hipSuccess;                                                        \
-  const int ppt = a.tile_w * a.tile_h / kLanes;                                              \
-  if (a.n_lambda < 1 || a.n_lambda > 4 || (ppt != 1 && ppt != 2 && ppt != 4))                 \
-    return hipErrorInvalidValue;                                                             \
-  switch (a.n_lambda * 8 + ppt) {                                                            \
-    case 9: KERNEL<1, 1><<<blocks, kLanes, 0, s>>>(a); break;                                \
-    case 10: KERNEL<1, 2><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 12: KERNEL<1, 4><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 17: KERNEL<2, 1><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 18: KERNEL<2, 2><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 20: KERNEL<2, 4><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 25: KERNEL<3, 1><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 26: KERNEL<3, 2><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 28: KERNEL<3, 4><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 33: KERNEL<4, 1><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 34: KERNEL<4, 2><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    case 36: KERNEL<4, 4><<<blocks, kLanes, 0, s>>>(a); break;                               \
-    default: return hipErrorInvalidValue;                                                    \
-  }                                                                                          \
+// Waves per tile of the forward: up to kFwdWaves, one or more 8x8 blocks
+// each.  Two waves per 16x16 tile halve the serial walk of a wave and let
+// the CU overlap one wave's record loads with the other's compositing.
+#ifndef CHRF_FWD_WAVES
+#define CHRF_FWD_WAVES 2
+#endif
+constexpr int kFwdWaves = CHRF_FWD_WAVES;
+
+template <int NL, int BPT>
+static void launch_fwd_nl(const RasterArgs& a, int blocks, hipStream_t s) {
+  constexpr int NW = BPT < kFwdWaves ? BPT : kFwdWaves;
+  k_raster_fwd<NL, BPT / NW, NW><<<blocks, kLanes * NW, 0, s>>>(a);
+}
+
+// Waves per tile of the backward: one 8x8 block per wave at 16x16 tiles
+// (the per-pair wave reduction is then per block, but four waves per tile
+// hide the record gathers and atomics better than one wave with four blocks).
+#ifndef CHRF_BWD_WAVES
+#define CHRF_BWD_WAVES 4
+#endif
+constexpr int kBwdWaves = CHRF_BWD_WAVES;
+
+template <int NL, int BPT>
+static void launch_bwd_nl(const RasterArgs& a, int blocks, hipStream_t s) {
+  constexpr int NW = BPT < kBwdWaves ? BPT : kBwdWaves;
+  k_raster_bwd<NL, BPT / NW, NW><<<blocks, kLanes * NW, 0, s>>>(a);
+}
+
+hipError_t launch_raster_forward(const RasterArgs& a, hipStream_t s) {
+  const int blocks = a.n_views * a.tiles_x * a.tiles_y;
+  if (blocks == 0) return hipSuccess;
+  const int bpt = a.tile_w * a.tile_h / kLanes;   // 8x8 blocks per tile
+  if (a.n_lambda < 1 || a.n_lambda > 4 || (bpt != 1 && bpt != 2 && bpt != 4)) return hipErrorInvalidValue;
+  switch (a.n_lambda * 8 + bpt) {
+    case 9: launch_fwd_nl<1, 1>(a, blocks, s); break;
+    case 10: launch_fwd_nl<1, 2>(a, blocks, s); break;
+    case 12: launch_fwd_nl<1, 4>(a, blocks, s); break;
+    case 17: launch_fwd_nl<2, 1>(a, blocks, s); break;
+    case 18: launch_fwd_nl<2, 2>(a, blocks, s); break;
+    case 20: launch_fwd_nl<2, 4>(a, blocks, s); break;
+    case 25: launch_fwd_nl<3, 1>(a, blocks, s); break;
+    case 26: launch_fwd_nl<3, 2>(a, blocks, s); break;
+    case 28: launch_fwd_nl<3, 4>(a, blocks, s); break;
+    case 33: launch_fwd_nl<4, 1>(a, blocks, s); break;
+    case 34: launch_fwd_nl<4, 2>(a, blocks, s); break;
+    case 36: launch_fwd_nl<4, 4>(a, blocks, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
 
-hipError_t launch_raster_forward(const RasterArgs& a, hipStream_t s) { CHRF_RASTER_DISPATCH(k_raster_fwd) }
-
-hipError_t launch_raster_backward(const RasterArgs& a, hipStream_t s) { CHRF_RASTER_DISPATCH(k_raster_bwd) }
+hipError_t launch_raster_backward(const RasterArgs& a, hipStream_t s) {
+  const int blocks = a.n_views * a.tiles_x * a.tiles_y;
+  if (blocks == 0) return hipSuccess;
+  const int bpt = a.tile_w * a.tile_h / kLanes;   // 8x8 blocks per tile
+  if (a.n_lambda < 1 || a.n_lambda > 4 || (bpt != 1 && bpt != 2 && bpt != 4)) return hipErrorInvalidValue;
+  switch (a.n_lambda * 8 + bpt) {
+    case 9: launch_bwd_nl<1, 1>(a, blocks, s); break;
+    case 10: launch_bwd_nl<1, 2>(a, blocks, s); break;
+    case 12: launch_bwd_nl<1, 4>(a, blocks, s); break;
+    case 17: launch_bwd_nl<2, 1>(a, blocks, s); break;
+    case 18: launch_bwd_nl<2, 2>(a, blocks, s); break;
+    case 20: launch_bwd_nl<2, 4>(a, blocks, s); break;
+    case 25: launch_bwd_nl<3, 1>(a, blocks, s); break;
+    case 26: launch_bwd_nl<3, 2>(a, blocks, s); break;
+    case 28: launch_bwd_nl<3, 4>(a, blocks, s); break;
+    case 33: launch_bwd_nl<4, 1>(a, blocks, s); break;
+    case 34: launch_bwd_nl<4, 2>(a, blocks, s); break;
+    case 36: launch_bwd_nl<4, 4>(a, blocks, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 }  // namespace chrf

@@ -6,13 +6,16 @@
 
 namespace chrf {
 
-// One wave (64 lanes) per tile.  Lane l sits at (l % 8, l / 8) of an 8x8
-// block and owns the pixel at that position in each of the tile's
-// PPT = tile_w * tile_h / 64 blocks, so per-pair costs that do not depend on
-// the pixel (record loads, the gradient reduction over the wave) are shared by
-// PPT pixels.  Records are staged in LDS in batches of kBatch pairs.
+// A tile's 8x8 blocks are shared out among the waves (64 lanes) of its
+// workgroup.  Lane l sits at (l % 8, l / 8) of an 8x8 block and owns the
+// pixel at that position in each of its wave's PPT blocks, so per-pair costs
+// that do not depend on the pixel (the gradient reduction over the wave) are
+// shared by PPT pixels.  Records are staged in LDS in batches of kBatch pairs.
 constexpr int kLanes = 64;
-constexpr int kBatch = 64;
+#ifndef CHRF_RASTER_BATCH
+#define CHRF_RASTER_BATCH 64
+#endif
+constexpr int kBatch = CHRF_RASTER_BATCH;
 
 struct TileGeom {
   int view, tx, ty;
@@ -40,14 +43,6 @@ __device__ inline void block_of(const RasterArgs& a, const TileGeom& t, int p, i
 // pixel work for every lane.
 __device__ inline bool rect_hits_block(const int4& rc, int bx, int by) {
   return rc.x <= bx + 7 && bx <= rc.x + rc.y && rc.z <= by + 7 && by <= rc.z + rc.w;
-}
-
-template <int PPT>
-__device__ inline void pixel_of(const RasterArgs& a, const TileGeom& t, int p, int& px, int& py) {
-  const int lane = threadIdx.x;
-  const int bpr = a.tile_w >> 3;   // 8x8 blocks per tile row
-  px = t.tx * a.tile_w + (p % bpr) * 8 + (lane & 7);
-  py = t.ty * a.tile_h + (p / bpr) * 8 + (lane >> 3);
 }
 
 template <int NL>

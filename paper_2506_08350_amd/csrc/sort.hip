@@ -10,9 +10,10 @@
 // starts from index order.  Depths are positive floats, whose bit patterns
 // order like their values.
 //
-// The radix sort is LSD with 8-bit digits; every pass counts per-block digit
-// histograms of the keys in their current order, scans them over (digit,
-// block) and scatters stably through an LDS reorder.  (The per-block split of a pass depends on the
+// The radix sort is LSD with 8-bit digits.  Long sorts count per-block digit
+// histograms of the keys in their current order each pass, scan them over
+// (digit, block) and scatter stably through an LDS reorder; short sorts use
+// single-sweep passes with decoupled look-back (below).  (The per-block split of a pass depends on the
 // permutation the previous pass produced, so histograms of later passes
 // cannot be taken from the input order.)  Ranks inside a
 // block come from wave ballots: a lane's rank among equal digits is the
@@ -248,15 +249,189 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
   }
 }
 
+// ------------------------------------------------- single-sweep passes ---
+// The per-pass histogram and scan kernels above cost two extra sweeps and
+// four launches per pass, which dominate short sorts (the per-view depth
+// sort of 10^5 Gaussians).  A single-sweep pass instead takes each block's
+// digit offsets from the blocks before it by decoupled look-back: blocks
+// draw partition numbers from a counter in launch order, publish their
+// per-digit counts, and add up the counts of earlier partitions until one
+// that already holds its inclusive prefix.  The global digit totals of every
+// pass do not depend on the order of the keys, so one counting sweep over
+// the input serves all passes.
+//
+// Status word of (partition, digit): bits 30-31 a flag (0: not published,
+// 1: this partition's count only, 2: inclusive prefix through this
+// partition), bits 0-29 the value.  Needs fewer than 2^30 keys.
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagInc = 2u << 30;
+constexpr uint32_t kValMask = (1u << 30) - 1u;
+constexpr int kLookbackPolls = 1 << 22;   // a wait that never ends sets the error word and stops
+constexpr int kCountBlocks = 1024;
+constexpr int kSweepMaxBlocks = 128;        // up to 512 Ki keys
+
+__device__ inline uint32_t load_status(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void store_status(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Global digit counts of every pass: counts[pass][digit].
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_digit_counts(const K* __restrict__ keys, int64_t n_max,
+                                                               const uint64_t* n_dev, int begin_bit, int npasses,
+                                                               uint32_t* __restrict__ counts) {
+  __shared__ uint32_t c[kMaxSortPasses][256];
+  for (int p = 0; p < npasses; ++p) c[p][threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t n = live_count(n_max, n_dev);
+  for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSortThreads) {
+    const K k = keys[i];
+    for (int p = 0; p < npasses; ++p) atomicAdd(&c[p][(uint32_t)(k >> (begin_bit + 8 * p)) & 255u], 1u);
+  }
+  __syncthreads();
+  for (int p = 0; p < npasses; ++p) {
+    const uint32_t v = c[p][threadIdx.x];
+    if (v) atomicAdd(&counts[p * 256 + threadIdx.x], v);
+  }
+}
+
+// One pass: count the partition's digits and publish them at once (so that
+// later partitions rarely wait), look back for the digit offsets, rank the
+// keys (as k_radix_scatter), then write through the LDS reorder.
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_onesweep(const K* __restrict__ keys_in,
+                                                           const uint32_t* __restrict__ vals_in,
+                                                           K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                                                           int64_t n_max, const uint64_t* n_dev, int shift,
+                                                           const uint32_t* __restrict__ counts, uint32_t* status,
+                                                           uint32_t* ticket, uint32_t* error) {
+  constexpr int NW = kSortThreads / 64;
+  __shared__ uint32_t hcnt[256];
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[NW][256];
+  __shared__ uint32_t goff[256];
+  __shared__ uint32_t lstart[256];
+  __shared__ uint32_t wsum[NW];
+  __shared__ uint32_t s_part;
+  __shared__ K skey[kSortTile];
+  __shared__ uint32_t sval[kSortTile];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_part = atomicAdd(ticket, 1u);
+  hcnt[tid] = 0;
+  run[tid] = 0;
+  for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
+  __syncthreads();
+  const uint32_t part = s_part;
+  const int64_t n = live_count(n_max, n_dev);
+  const int64_t base = (int64_t)part * kSortTile;
+  if (base >= n) return;   // uniform per block; later partitions are empty too, so nobody waits on this one
+  K key[kSortItems];
+  uint32_t val[kSortItems], dig[kSortItems], rank[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t idx = base + (int64_t)r * kSortThreads + tid;
+    key[r] = 0;
+    val[r] = 0;
+    dig[r] = 0;
+    if (idx < n) {
+      key[r] = keys_in[idx];
+      val[r] = vals_in[idx];
+      dig[r] = (uint32_t)(key[r] >> shift) & 255u;
+      atomicAdd(&hcnt[dig[r]], 1u);
+    }
+  }
+  __syncthreads();
+  // publish this partition's count of digit tid, then look back
+  const uint32_t mine = hcnt[tid];
+  uint32_t* my = status + (size_t)part * 256 + tid;
+  store_status(my, (part == 0 ? kFlagInc : kFlagAgg) | mine);
+  uint32_t excl = 0;
+  if (part > 0) {
+    int64_t k = (int64_t)part - 1;
+    int polls = 0;
+    while (true) {
+      const uint32_t w = load_status(status + (size_t)k * 256 + tid);
+      const uint32_t f = w & ~kValMask;
+      if (f == 0u) {
+        if (++polls > kLookbackPolls) {
+          store_status(error, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      excl += w & kValMask;
+      if (f == kFlagInc) break;
+      --k;   // partition 0 always publishes an inclusive value, so k stays >= 0
+    }
+    store_status(my, kFlagInc | (excl + mine));
+  }
+  uint32_t tot;
+  goff[tid] = block_exclusive_scan<uint32_t>(counts[tid], wsum, &tot) + excl;
+  lstart[tid] = block_exclusive_scan<uint32_t>(mine, wsum, &tot);
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const bool valid = base + (int64_t)r * kSortThreads + tid < n;
+    const uint32_t d = dig[r];
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const uint64_t m = __ballot(on);
+      peers &= on ? m : ~m;
+    }
+    const uint32_t lower = __popcll(peers & lt_mask);
+    if (valid && lower == 0) wcnt[wave][d] = __popcll(peers);
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wcnt[w][d];
+    rank[r] = valid ? run[d] + before + lower : ~0u;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < NW; ++w) {
+      add += wcnt[w][tid];
+      wcnt[w][tid] = 0;
+    }
+    run[tid] += add;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (rank[r] != ~0u) {
+      const uint32_t p = lstart[dig[r]] + rank[r];
+      skey[p] = key[r];
+      sval[p] = val[r];
+    }
+  }
+  __syncthreads();
+  const int nv = (int)(n - base < kSortTile ? n - base : kSortTile);
+  for (int i = tid; i < nv; i += kSortThreads) {
+    const K k = skey[i];
+    const uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const uint32_t pos = goff[d] + (uint32_t)i - lstart[d];
+    if (pos < (uint64_t)n) {   // always true for consistent offsets; keeps every write in bounds
+      keys_out[pos] = k;
+      vals_out[pos] = sval[i];
+    }
+  }
+}
+
+// Workspace of a sort of up to n_max keys, in 32-bit words: per pass the
+// (partition, digit) status words, the digit counts and a partition
+// counter.  The multi-kernel fallback (n_max >= 2^30) uses the first
+// 256 * nblocks words as its histogram.
 int64_t radix_hist_elems(int64_t n_max) {
-  const int64_t nb = (n_max + kSortTile - 1) / kSortTile;
-  return 256 * (nb > 0 ? nb : 1);
+  const int64_t nb = std::max<int64_t>((n_max + kSortTile - 1) / kSortTile, 1);
+  return (int64_t)kMaxSortPasses * (256 * nb + 256 + 64);
 }
 
 template <typename K>
 static hipError_t radix_sort_impl(K* keys, K* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t n_max,
                                   const uint64_t* n_dev, int begin_bit, int end_bit, uint32_t* hist,
-                                  uint32_t* scan_tmp, bool* result_in_alt, hipStream_t s) {
+                                  uint32_t* scan_tmp, uint32_t* error, bool* result_in_alt, hipStream_t s) {
   *result_in_alt = false;
   if (n_max <= 0) return hipSuccess;
   const int nblocks = (int)((n_max + kSortTile - 1) / kSortTile);
@@ -267,34 +442,53 @@ static hipError_t radix_sort_impl(K* keys, K* keys_alt, uint32_t* vals, uint32_t
   K* kout = keys_alt;
   uint32_t* vin = vals;
   uint32_t* vout = vals_alt;
-  bool alt = false;
+  // single sweeps pay off for short sorts, where the launches of the
+  // histogram and scan kernels dominate; long ones keep the three-kernel pass
+  const bool sweep = nblocks <= kSweepMaxBlocks;
+  hipError_t e = hipSuccess;
+  uint32_t* status = hist;
+  uint32_t* counts = hist + (size_t)npasses * 256 * nblocks;
+  uint32_t* tickets = counts + (size_t)npasses * 256;
+  if (sweep) {
+    e = launch_fill_u32(hist, 0u, (int64_t)npasses * (256 * (int64_t)nblocks + 256) + npasses, s);
+    if (e != hipSuccess) return e;
+    const int cb = nblocks < kCountBlocks ? nblocks : kCountBlocks;
+    k_digit_counts<K><<<cb, kSortThreads, 0, s>>>(kin, n_max, n_dev, begin_bit, npasses, counts);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   for (int pass = 0; pass < npasses; ++pass) {
     const int shift = begin_bit + 8 * pass;
-    k_radix_hist<K><<<nblocks, kSortThreads, 0, s>>>(kin, n_max, n_dev, shift, hist, nblocks);
-    hipError_t e = launch_scan_u32(hist, hist, (int64_t)256 * nblocks, scan_tmp, s);
-    if (e != hipSuccess) return e;
-    k_radix_scatter<K><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n_max, n_dev, shift, hist, nblocks);
+    if (sweep) {
+      k_onesweep<K><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n_max, n_dev, shift, counts + pass * 256,
+                                                     status + (size_t)pass * 256 * nblocks, tickets + pass, error);
+    } else {
+      k_radix_hist<K><<<nblocks, kSortThreads, 0, s>>>(kin, n_max, n_dev, shift, hist, nblocks);
+      e = launch_scan_u32(hist, hist, (int64_t)256 * nblocks, scan_tmp, s);
+      if (e != hipSuccess) return e;
+      k_radix_scatter<K><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n_max, n_dev, shift, hist,
+                                                          nblocks);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     K* tk = kin; kin = kout; kout = tk;
     uint32_t* tv = vin; vin = vout; vout = tv;
-    alt = !alt;
+    *result_in_alt = !*result_in_alt;
   }
-  *result_in_alt = alt;
   return hipGetLastError();
 }
 
 hipError_t radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t n_max,
                           const uint64_t* n_dev, int begin_bit, int end_bit, uint32_t* hist, uint32_t* scan_tmp,
-                          bool* result_in_alt, hipStream_t s) {
+                          uint32_t* error, bool* result_in_alt, hipStream_t s) {
   return radix_sort_impl<uint64_t>(keys, keys_alt, vals, vals_alt, n_max, n_dev, begin_bit, end_bit, hist,
-                                   scan_tmp, result_in_alt, s);
+                                   scan_tmp, error, result_in_alt, s);
 }
 hipError_t radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t n_max,
                           const uint64_t* n_dev, int begin_bit, int end_bit, uint32_t* hist, uint32_t* scan_tmp,
-                          bool* result_in_alt, hipStream_t s) {
+                          uint32_t* error, bool* result_in_alt, hipStream_t s) {
   return radix_sort_impl<uint32_t>(keys, keys_alt, vals, vals_alt, n_max, n_dev, begin_bit, end_bit, hist,
-                                   scan_tmp, result_in_alt, s);
+                                   scan_tmp, error, result_in_alt, s);
 }
 
 // -------------------------------------------------------- pair emission ---
