@@ -241,10 +241,6 @@ __global__ __launch_bounds__(256) void k_rows_adjoint_out_t(const float2* __rest
 //          workgroups share a CU.
 constexpr int kColN = 2160;
 
-#ifndef CHRF_C2_LDS_TWIDDLES
-#define CHRF_C2_LDS_TWIDDLES 0
-#endif
-
 template <int C>
 struct ColT {
   static constexpr int NT = 256 * C;
@@ -253,8 +249,8 @@ struct ColT {
   static_assert(Fwd::M1 == 1 && Fwd::M3 == 1 && Inv::M1 == 1 && Inv::M3 == 1, "one butterfly per thread");
   static_assert(Fwd::B3 == Inv::B1, "forward outputs feed the inverse inputs");
   static constexpr int SPAN = 128 / (8 * C);   // column groups per 128-byte line
-  static constexpr bool kRegSpec = C == 2;      // spectrum in registers
-  static constexpr bool kLdsTw = !kRegSpec || CHRF_C2_LDS_TWIDDLES;   // twiddle table in LDS, read per power
+  static constexpr bool kRegSpec = C == 2;      // spectrum in registers, twiddles from memory
+  static constexpr bool kLdsTw = !kRegSpec;     // twiddle table in LDS, read per power
   static constexpr int kMinBlocks = kRegSpec ? 2 : 1;
 };
 

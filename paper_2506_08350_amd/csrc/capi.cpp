@@ -347,7 +347,7 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   p->psort_alt = ((p->psort_bits + 7) / 8) % 2 == 1;
   // workspace layout
   const int64_t BN = (int64_t)p->B * (p->N > 0 ? p->N : 1);
-  const int64_t hist = radix_hist_elems(std::max<int64_t>(cap, BN));
+  const int64_t hist = std::max(radix_hist_elems(cap), radix_hist_elems(BN));   // both sorts share it
   const int64_t scan_tmp = scan_tmp_elems(std::max<int64_t>(hist, BN)) + 16;
   const int64_t pix = (int64_t)p->B * p->H * p->W;
   size_t sz[R_NUM];

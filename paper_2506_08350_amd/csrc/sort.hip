@@ -268,7 +268,9 @@ constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1u;
 constexpr int kLookbackPolls = 1 << 22;   // a wait that never ends sets the error word and stops
 constexpr int kCountBlocks = 1024;
-constexpr int kSweepMaxBlocks = 128;        // up to 512 Ki keys
+constexpr int kSweepMaxKeys = 1 << 19;      // sorts of up to 512 Ki keys take single sweeps
+constexpr int kSweepItems = 4;              // keys per thread of a sweep partition
+constexpr int kSweepTile = kSortThreads * kSweepItems;
 
 __device__ inline uint32_t load_status(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -300,7 +302,7 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_counts(const K* __restri
 // One pass: count the partition's digits and publish them at once (so that
 // later partitions rarely wait), look back for the digit offsets, rank the
 // keys (as k_radix_scatter), then write through the LDS reorder.
-template <typename K>
+template <typename K, int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_onesweep(const K* __restrict__ keys_in,
                                                            const uint32_t* __restrict__ vals_in,
                                                            K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
@@ -315,8 +317,9 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const K* __restrict__
   __shared__ uint32_t lstart[256];
   __shared__ uint32_t wsum[NW];
   __shared__ uint32_t s_part;
-  __shared__ K skey[kSortTile];
-  __shared__ uint32_t sval[kSortTile];
+  constexpr int TILE = kSortThreads * ITEMS;
+  __shared__ K skey[TILE];
+  __shared__ uint32_t sval[TILE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) s_part = atomicAdd(ticket, 1u);
   hcnt[tid] = 0;
@@ -325,12 +328,12 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const K* __restrict__
   __syncthreads();
   const uint32_t part = s_part;
   const int64_t n = live_count(n_max, n_dev);
-  const int64_t base = (int64_t)part * kSortTile;
+  const int64_t base = (int64_t)part * TILE;
   if (base >= n) return;   // uniform per block; later partitions are empty too, so nobody waits on this one
-  K key[kSortItems];
-  uint32_t val[kSortItems], dig[kSortItems], rank[kSortItems];
+  K key[ITEMS];
+  uint32_t val[ITEMS], dig[ITEMS], rank[ITEMS];
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const int64_t idx = base + (int64_t)r * kSortThreads + tid;
     key[r] = 0;
     val[r] = 0;
@@ -373,7 +376,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const K* __restrict__
   lstart[tid] = block_exclusive_scan<uint32_t>(mine, wsum, &tot);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const bool valid = base + (int64_t)r * kSortThreads + tid < n;
     const uint32_t d = dig[r];
     uint64_t peers = __ballot(valid);
@@ -399,7 +402,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const K* __restrict__
     __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     if (rank[r] != ~0u) {
       const uint32_t p = lstart[dig[r]] + rank[r];
       skey[p] = key[r];
@@ -407,7 +410,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const K* __restrict__
     }
   }
   __syncthreads();
-  const int nv = (int)(n - base < kSortTile ? n - base : kSortTile);
+  const int nv = (int)(n - base < TILE ? n - base : TILE);
   for (int i = tid; i < nv; i += kSortThreads) {
     const K k = skey[i];
     const uint32_t d = (uint32_t)(k >> shift) & 255u;
@@ -419,13 +422,18 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const K* __restrict__
   }
 }
 
-// Workspace of a sort of up to n_max keys, in 32-bit words: per pass the
-// (partition, digit) status words, the digit counts and a partition
-// counter.  The multi-kernel fallback (n_max >= 2^30) uses the first
-// 256 * nblocks words as its histogram.
+// Workspace of a sort of up to n_max keys, in 32-bit words: the three-kernel
+// passes use 256 * nblocks words of histogram; single sweeps use, per pass,
+// the (partition, digit) status words, the digit counts and a partition
+// counter.
 int64_t radix_hist_elems(int64_t n_max) {
   const int64_t nb = std::max<int64_t>((n_max + kSortTile - 1) / kSortTile, 1);
-  return (int64_t)kMaxSortPasses * (256 * nb + 256 + 64);
+  int64_t words = 256 * nb;
+  if (n_max <= kSweepMaxKeys) {
+    const int64_t parts = std::max<int64_t>((n_max + kSweepTile - 1) / kSweepTile, 1);
+    words = std::max<int64_t>(words, (int64_t)kMaxSortPasses * (256 * parts + 256 + 1));
+  }
+  return words;
 }
 
 template <typename K>
@@ -434,7 +442,10 @@ static hipError_t radix_sort_impl(K* keys, K* keys_alt, uint32_t* vals, uint32_t
                                   uint32_t* scan_tmp, uint32_t* error, bool* result_in_alt, hipStream_t s) {
   *result_in_alt = false;
   if (n_max <= 0) return hipSuccess;
-  const int nblocks = (int)((n_max + kSortTile - 1) / kSortTile);
+  // single sweeps pay off for short sorts, where the launches of the
+  // histogram and scan kernels dominate; long ones keep the three-kernel pass
+  const bool sweep = n_max <= kSweepMaxKeys;
+  const int nblocks = (int)((n_max + (sweep ? kSweepTile : kSortTile) - 1) / (sweep ? kSweepTile : kSortTile));
   const int npasses = (end_bit - begin_bit + 7) / 8;
   if (npasses <= 0) return hipSuccess;
   if (npasses > kMaxSortPasses) return hipErrorInvalidValue;
@@ -442,9 +453,6 @@ static hipError_t radix_sort_impl(K* keys, K* keys_alt, uint32_t* vals, uint32_t
   K* kout = keys_alt;
   uint32_t* vin = vals;
   uint32_t* vout = vals_alt;
-  // single sweeps pay off for short sorts, where the launches of the
-  // histogram and scan kernels dominate; long ones keep the three-kernel pass
-  const bool sweep = nblocks <= kSweepMaxBlocks;
   hipError_t e = hipSuccess;
   uint32_t* status = hist;
   uint32_t* counts = hist + (size_t)npasses * 256 * nblocks;
@@ -460,8 +468,10 @@ static hipError_t radix_sort_impl(K* keys, K* keys_alt, uint32_t* vals, uint32_t
   for (int pass = 0; pass < npasses; ++pass) {
     const int shift = begin_bit + 8 * pass;
     if (sweep) {
-      k_onesweep<K><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n_max, n_dev, shift, counts + pass * 256,
-                                                     status + (size_t)pass * 256 * nblocks, tickets + pass, error);
+      k_onesweep<K, kSweepItems><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n_max, n_dev, shift,
+                                                                  counts + pass * 256,
+                                                                  status + (size_t)pass * 256 * nblocks,
+                                                                  tickets + pass, error);
     } else {
       k_radix_hist<K><<<nblocks, kSortThreads, 0, s>>>(kin, n_max, n_dev, shift, hist, nblocks);
       e = launch_scan_u32(hist, hist, (int64_t)256 * nblocks, scan_tmp, s);
