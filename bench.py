@@ -98,29 +98,32 @@ def measured_traffic(kernel):
 VALU_PROFILE = os.path.join(ROOT, "profiles", "valu_step_c3_1080p_100k.md")
 VALU_NAMES = {"cols_adjoint": "k_cols_adjoint_t", "cols_forward": "k_cols_forward_t",
               "raster_backward": "k_raster_bwd", "raster_forward": "k_raster_fwd"}
+# Vector-ALU issue peak: 2 wave64 VALU instructions per CU per cycle (the FP32
+# vector rate, 157.3 TFLOP/s = 256 CUs x 2.4 GHz x 2 x 64 lanes x 2 flops), in
+# lane-operations per second.
+VALU_PEAK_GOPS = 256 * 2.4 * 2 * 64
 
 
-def measured_valu_busy(kernel):
-    """VALU-busy fraction of ``kernel`` from the committed SQ counter summary
-    (SQ_INSTS_VALU x 4 cycles over the SIMD cycles of the launch), or None
-    when the summary is missing, does not cover the kernel, or any of the
-    kernel's sources changed since the counters were taken."""
+def measured_valu_instructions(kernel):
+    """VALU instructions per launch of ``kernel`` (SQ_INSTS_VALU) from the
+    committed counter summary, or None when the summary is missing, does not
+    cover the kernel, or any of the kernel's sources changed since."""
     try:
         text = open(VALU_PROFILE).read()
     except OSError:
         return None
-    shas, busy = {}, None
+    shas, count = {}, None
     for line in text.splitlines():
         if line.startswith("source-sha256 "):
             _, name, sha = line.split()
             shas[name] = sha
         cells = [c.strip(" `") for c in line.strip().strip("|").split("|")]
         if len(cells) == 7 and kernel in VALU_NAMES and cells[0].startswith(VALU_NAMES[kernel] + "<"):
-            busy = float(cells[6])
+            count = int(cells[2])
     files = KERNEL_SOURCES.get(kernel)
-    if busy is None or not files or any(shas.get(f) != source_sha256(f) for f in files):
+    if count is None or not files or any(shas.get(f) != source_sha256(f) for f in files):
         return None
-    return busy
+    return count
 
 
 def cpu_baseline(w, seed=0):
@@ -338,19 +341,32 @@ def main(argv=None):
         torch.cuda.synchronize()
         fwd_ms = (time.perf_counter() - f0) * 1000.0 / args.steps
 
-    # dominant propagation kernel against the HBM roofline
+    # The dominant kernel of the step is a raster kernel, bound by its vector
+    # ALU work: it is reported against the VALU issue peak (lane-operations
+    # issued per second, from its counted VALU instructions and the live
+    # launch time).  The dominant propagation kernel is reported against HBM.
     per_launch = {n: (c, tot / c) for n, (c, tot) in kt.items()}
     fused = args.loss == "mse"
     asm = {n: v for n, v in per_launch.items() if kernel_bytes(n, B, L, K, H, W, pH, pW, train, fused) is not None}
-    dom = max(asm, key=lambda n: asm[n][0] * asm[n][1])
-    dom_ms = asm[dom][1]
-    dom_bytes = kernel_bytes(dom, B, L, K, H, W, pH, pW, train, fused)
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
-                "avg_ms": round(dom_ms, 4), "algorithmic_bytes": dom_bytes,
-                # the kernel's vector-ALU occupancy from the SQ counters: the bound the HBM fraction leaves
-                "valu_busy": measured_valu_busy(dom)}
+    pdom = max(asm, key=lambda n: asm[n][0] * asm[n][1])
+    pdom_ms = asm[pdom][1]
+    pdom_bytes = kernel_bytes(pdom, B, L, K, H, W, pH, pW, train, fused)
+    p_achieved = pdom_bytes / (pdom_ms * 1e-3) / 1e9
+    hbm = {"bound": "hbm", "kernel": pdom, "achieved": round(p_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(p_achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(pdom),
+           "avg_ms": round(pdom_ms, 4), "algorithmic_bytes": pdom_bytes}
+    dom = max(per_launch, key=lambda n: per_launch[n][0] * per_launch[n][1])
+    if dom in VALU_NAMES and not layered:
+        dom_ms = per_launch[dom][1]
+        instr = measured_valu_instructions(dom)
+        achieved = instr * 64 / (dom_ms * 1e-3) / 1e9 if instr else None
+        roofline = {"bound": "alu", "kernel": dom,
+                    "achieved": round(achieved, 1) if achieved else None, "peak": VALU_PEAK_GOPS,
+                    "unit": "G VALU lane-ops/s", "frac": round(achieved / VALU_PEAK_GOPS, 4) if achieved else None,
+                    "traffic": measured_traffic(dom), "avg_ms": round(dom_ms, 4), "valu_instructions": instr,
+                    "hbm_dominant_propagation": hbm}
+    else:
+        roofline = hbm
     if args.kernel_table:
         tot = sum(c * m for c, m in per_launch.values())
         for n, (c, m) in sorted(per_launch.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
