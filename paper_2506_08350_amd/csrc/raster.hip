@@ -64,7 +64,8 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_fwd(RasterArgs a) {
     const int cnt = (int)min(rg.y - start, (uint32_t)kBatch);
     stage_records<NL>(st, a, start, cnt, false);
     __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
+    const int jend = __all(all_done) ? 0 : cnt;   // a finished wave only keeps the barriers
+    for (int j = 0; j < jend; ++j) {
       const float4 g0 = st.g0[j];
       const float4 g1 = st.g1[j];
       const int4 rc = st.rc[j];
@@ -151,6 +152,7 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
   }
   // one past the last pair any pixel of the tile used
   for (int off = 32; off > 0; off >>= 1) tile_last = max(tile_last, (uint32_t)__shfl_xor((int)tile_last, off, 64));
+  const uint32_t wave_last = tile_last;   // this wave's pixels used no pair at or past it
   if constexpr (NW > 1) {
     if (lane == 0) s_last[wave] = tile_last;
     __syncthreads();
@@ -166,7 +168,9 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
     __syncthreads();
     stage_records<NL>(st, a, top - 1, cnt, true);   // st[j] is the j-th pair from the back
     __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
+    // pairs at or past wave_last touch none of this wave's pixels
+    const int j0 = top > wave_last ? (int)min(top - wave_last, (uint32_t)cnt) : 0;
+    for (int j = j0; j < cnt; ++j) {
       const uint32_t pidx = top - 1 - j;
       const float4 g0 = st.g0[j];
       const float4 g1 = st.g1[j];

@@ -201,7 +201,9 @@ __global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_bwd(RasterArgs a) 
     stage_records_l<NL>(st, a, top - 1, cnt, true);   // st[j] is the j-th pair from the back
     __syncthreads();
     if (top - cnt < wave_last) {   // this wave has work in the batch
-      for (int j = 0; j < cnt; ++j) {
+      // pairs at or past wave_last touch none of this wave's pixels
+      const int j0 = top > wave_last ? (int)min(top - wave_last, (uint32_t)cnt) : 0;
+      for (int j = j0; j < cnt; ++j) {
         const int4 rc = st.s.rc[j];
         if (!rect_hits_block(rc, bx, by)) continue;
         const uint32_t pidx = top - 1 - j;
