@@ -20,7 +20,7 @@ from . import api
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "chrf_autotune.json")
 
 TILES = ((16, 16), (16, 8), (8, 16), (32, 8), (8, 8))
-COLS = (4, 2)
+COLS = (4, 2, 1)
 
 
 def shape_key(height, width, n_lambda, n_planes, n_views, n_gaussians, pad):

@@ -249,9 +249,9 @@ struct ColT {
   static_assert(Fwd::M1 == 1 && Fwd::M3 == 1 && Inv::M1 == 1 && Inv::M3 == 1, "one butterfly per thread");
   static_assert(Fwd::B3 == Inv::B1, "forward outputs feed the inverse inputs");
   static constexpr int SPAN = 128 / (8 * C);   // column groups per 128-byte line
-  static constexpr bool kRegSpec = C == 2;      // spectrum in registers, twiddles from memory
+  static constexpr bool kRegSpec = C <= 2;      // spectrum in registers, twiddles from memory
   static constexpr bool kLdsTw = !kRegSpec;     // twiddle table in LDS, read per power
-  static constexpr int kMinBlocks = kRegSpec ? 2 : 1;
+  static constexpr int kMinBlocks = C == 1 ? 4 : (C == 2 ? 2 : 1);
 };
 
 __device__ inline int col_remap(int id, int nblocks, int span) {
@@ -466,7 +466,9 @@ static void cols_adjoint_c(const float2* z, float2* w1, const AsmGeom& g, const 
 
 hipError_t launch_cols_forward_t(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, int C,
                                  hipStream_t s) {
-  if (C == 2)
+  if (C == 1)
+    cols_forward_c<1>(x1, y, g, fc, s);
+  else if (C == 2)
     cols_forward_c<2>(x1, y, g, fc, s);
   else
     cols_forward_c<4>(x1, y, g, fc, s);
@@ -474,7 +476,9 @@ hipError_t launch_cols_forward_t(const float2* x1, float2* y, const AsmGeom& g, 
 }
 hipError_t launch_cols_adjoint_t(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, int C,
                                  hipStream_t s) {
-  if (C == 2)
+  if (C == 1)
+    cols_adjoint_c<1>(z, w1, g, fc, s);
+  else if (C == 2)
     cols_adjoint_c<2>(z, w1, g, fc, s);
   else
     cols_adjoint_c<4>(z, w1, g, fc, s);

@@ -293,9 +293,9 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
     return bad(fail(CHRF_EUNSUPPORTED, "plan: a padded row does not fit the LDS"));
   int C = d.cols_per_block;
   if (tuned_cols(geom(p))) {
-    // tuned column pass: 2 columns x 512 threads (default) or 4 x 1024
-    if (C != 0 && C != 2 && C != 4)
-      return bad(fail(CHRF_EUNSUPPORTED, "plan: cols_per_block must be 2 or 4 for this padded height"));
+    // tuned column pass: 2 columns x 512 threads (default), 1 x 256 or 4 x 1024
+    if (C != 0 && C != 1 && C != 2 && C != 4)
+      return bad(fail(CHRF_EUNSUPPORTED, "plan: cols_per_block must be 1, 2 or 4 for this padded height"));
     if (C == 0) C = 2;
   } else {
     if (C == 0) {

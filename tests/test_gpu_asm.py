@@ -84,14 +84,17 @@ def test_adjoint_matches_oracle_and_dot_product():
     assert abs(lhs - rhs) / abs(lhs) < 1e-5
 
 
-def test_full_size_workload_geometry():
-    """1080 x 1920 field, padded 2160 x 3840, three wavelengths, four planes;
-    one wavelength and two planes are checked against the oracle in full."""
-    announce("propagate 1080x1920")
+@pytest.mark.parametrize("cols", [1, 2, 4])
+def test_full_size_workload_geometry(cols):
+    """1080 x 1920 field, padded 2160 x 3840, three wavelengths, four planes,
+    with each column-pass variant (columns per workgroup); one wavelength and
+    two planes of the propagation, and the adjoint of one wavelength, are
+    checked against the oracle in full."""
+    announce(f"propagate 1080x1920, {cols} columns per workgroup")
     H, W = 1080, 1920
     lams, zs = (639e-9, 515e-9, 473e-9), (0.5e-3, 1e-3, 1.5e-3, 2e-3)
     opt = Optics(lams, zs, 8e-6, 2, 2)
-    r = make_renderer([identity_camera(W, H)], opt, 1)
+    r = make_renderer([identity_camera(W, H)], opt, 1, cols_per_block=cols)
     rng = np.random.default_rng(3)
     U = (rng.uniform(0, 1, (1, 3, H, W)) * np.exp(2j * np.pi * rng.uniform(0, 1, (1, 3, H, W))))
     prop, inten = r.propagate(_to_gpu(U))
@@ -100,6 +103,11 @@ def test_full_size_workload_geometry():
         ref = oracle.propagate(U[0, li], lams[li], zs[ki], 8e-6, 2, 2)
         got = cplx(prop[0, li, ki])
         assert rel_l2(got, ref) < TOL
+    G = (rng.normal(size=(1, 3, 4, H, W)) + 1j * rng.normal(size=(1, 3, 4, H, W)))
+    back = r.propagate_adjoint(torch.from_numpy(np.stack([G.real, G.imag], -1).astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    ref = sum(oracle.propagate_adjoint(G[0, 1, k], lams[1], zs[k], 8e-6, 2, 2) for k in range(4))
+    assert rel_l2(cplx(back[0, 1]), ref) < TOL
 
 
 @pytest.mark.parametrize("W", [2560, 3840])
