@@ -550,7 +550,7 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
     const AsmGeom geo = geom(plan);
     uint8_t* layer_of = at<uint8_t>(plan, ws, R_LAYER_OF);
     float2* lfield = at<float2>(plan, ws, R_LFIELD);
-    RUN("assign_layers", launch_assign_layers(g->logits, g->n, plan->K, layer_of, s));
+    RUN("assign_layers", launch_assign_layers(g->logits, g->n, plan->K, kSteTau, layer_of, s));
     ra.layer_of = layer_of;
     ra.n_layers = plan->K;
     ra.layer_stop = at<uint32_t>(plan, ws, R_LSTOP);
@@ -696,7 +696,7 @@ chrf_status chrf_backward(chrf_plan* plan, const chrf_gaussians* g, const chrf_c
   if (plan->layered && out->logits)
     RUN("logits_backward", launch_logits_backward(g->logits, grad2d, plan->g2, 6 + 2 * plan->L,
                                                   at<uint32_t>(plan, ws, R_GCOUNT), g->n, Nst, plan->B, plan->K,
-                                                  1e-3f, out->logits, s));
+                                                  kSteTau, out->logits, s));
   return CHRF_OK;
 }
 

@@ -161,7 +161,12 @@ hipError_t launch_adam(float* x, const float* g, float* m, float* v, int64_t n, 
 
 // Multi-layer mode (hard plane assignment).
 constexpr int kMaxLayers = 4;
-hipError_t launch_assign_layers(const float* logits, int n, int n_layers, uint8_t* layer_of, hipStream_t s);
+// temperature of the straight-through softmax over the layer logits (Sec. 4.1, Eq. 12)
+constexpr float kSteTau = 1e-3f;
+// layer_of[g]: bits 0-2 the argmax layer, bits 4-7 the layers of nonzero
+// straight-through weight softmax(logits / tau) in single precision
+hipError_t launch_assign_layers(const float* logits, int n, int n_layers, float tau, uint8_t* layer_of,
+                                hipStream_t s);
 hipError_t launch_raster_layers_forward(const RasterArgs& a, hipStream_t s);
 hipError_t launch_raster_layers_backward(const RasterArgs& a, hipStream_t s);
 hipError_t launch_logits_backward(const float* logits, const float* grad2d, int g2stride, int rho_offset,

@@ -27,7 +27,22 @@
 
 namespace chrf {
 
-__global__ void k_assign_layers(const float* __restrict__ logits, int n, int nlay, uint8_t* __restrict__ layer_of) {
+// Layer byte of each Gaussian: bits 0-2 its hard layer (argmax of the
+// logits, ties to the lowest), bits 4-7 the layers whose straight-through
+// weight softmax(logits / tau)_q is nonzero in single precision.  The
+// logits gradient is dL/drho_q times that weight, so the backward need not
+// form dL/drho_q for a layer outside the mask: its product is exactly zero.
+__device__ inline uint32_t ste_live_layers(const float* r, int nlay, float inv_tau) {
+  float mx = r[0] * inv_tau;
+  for (int q = 1; q < nlay; ++q) mx = fmaxf(mx, r[q] * inv_tau);
+  uint32_t live = 0;
+  for (int q = 0; q < nlay; ++q)
+    if (expf(r[q] * inv_tau - mx) != 0.0f) live |= 1u << q;
+  return live;
+}
+
+__global__ void k_assign_layers(const float* __restrict__ logits, int n, int nlay, float inv_tau,
+                                uint8_t* __restrict__ layer_of) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const float* r = logits + (size_t)g * nlay;
@@ -38,7 +53,7 @@ __global__ void k_assign_layers(const float* __restrict__ logits, int n, int nla
       bv = r[q];
       best = q;
     }
-  layer_of[g] = (uint8_t)best;
+  layer_of[g] = (uint8_t)(best | (ste_live_layers(r, nlay, inv_tau) << 4));
 }
 
 template <int NL>
@@ -98,7 +113,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_fwd(RasterArgs a) 
       for (int j = 0; j < cnt; ++j) {
         const int4 rc = st.s.rc[j];
         if (!rect_hits_block(rc, bx, by)) continue;
-        const int lay = __builtin_amdgcn_readfirstlane(st.lay[j]);
+        const int lay = __builtin_amdgcn_readfirstlane(st.lay[j]) & 7;
         if (!((live >> lay) & 1u)) continue;
         const float4 g0 = st.s.g0[j];
         const float4 g1 = st.s.g1[j];
@@ -207,7 +222,16 @@ __global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_bwd(RasterArgs a) 
         const int4 rc = st.s.rc[j];
         if (!rect_hits_block(rc, bx, by)) continue;
         const uint32_t pidx = top - 1 - j;
-        const int lay = __builtin_amdgcn_readfirstlane(st.lay[j]);
+        const int packed = __builtin_amdgcn_readfirstlane(st.lay[j]);
+        const int lay = packed & 7;
+        const uint32_t ste_live = (uint32_t)packed >> 4;
+        // a pixel gains nothing from this pair past its own layer's stop unless it
+        // is still live in another layer with a nonzero straight-through weight
+        bool useful = pidx < stop[lay];
+#pragma unroll
+        for (int q = 0; q < NLAY; ++q)
+          useful = useful || (q != lay && ((ste_live >> q) & 1u) && pidx < stop[q]);
+        if (!__any(useful)) continue;
         const float4 g0 = st.s.g0[j];
         const float4 g1 = st.s.g1[j];
         float gr[G2P];
@@ -227,6 +251,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_bwd(RasterArgs a) 
           for (int q = 0; q < NLAY; ++q) {
             if (pidx >= stop[q]) continue;   // layer q had stopped before this pair
             const bool own = q == lay;       // wave-uniform
+            if (!own && !((ste_live >> q) & 1u)) continue;   // zero straight-through weight
             const float Tb = own ? T[q] * __builtin_amdgcn_rcpf(1.0f - aval) : T[q];
             float sq = 0.f;
 #pragma unroll
@@ -314,12 +339,16 @@ __global__ void k_logits_backward(const float* __restrict__ logits, const float*
     w[q] = expf(w[q] - mx);
     sum += w[q];
   }
-  for (int q = 0; q < nlay; ++q) d_logits[(size_t)g * nlay + q] = drho[q] * (w[q] / sum);
+  const uint32_t live = ste_live_layers(logits + (size_t)g * nlay, nlay, inv_tau);
+  for (int q = 0; q < nlay; ++q)
+    d_logits[(size_t)g * nlay + q] = ((live >> q) & 1u) ? drho[q] * (w[q] / sum) : 0.0f;
 }
 
-hipError_t launch_assign_layers(const float* logits, int n, int n_layers, uint8_t* layer_of, hipStream_t s) {
+hipError_t launch_assign_layers(const float* logits, int n, int n_layers, float tau, uint8_t* layer_of,
+                                hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_assign_layers<<<(n + 255) / 256, 256, 0, s>>>(logits, n, n_layers, layer_of);
+  if (n_layers < 1 || n_layers > kMaxLayers) return hipErrorInvalidValue;
+  k_assign_layers<<<(n + 255) / 256, 256, 0, s>>>(logits, n, n_layers, 1.0f / tau, layer_of);
   return hipGetLastError();
 }
 
