@@ -26,10 +26,11 @@ template <int NL, int PPT, int NW>
 __global__ __launch_bounds__(kLanes * NW) void k_raster_fwd(RasterArgs a) {
   __shared__ Stage<NL> st;
   const TileGeom t = tile_of(a);
-  const int lane = threadIdx.x & (kLanes - 1), wave = threadIdx.x / kLanes;
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kLanes));
   int px[PPT], py[PPT], bx[PPT], by[PPT];
   float pxf[PPT], pyf[PPT];
-  bool inside[PPT], done[PPT];
+  bool inside[PPT];
   float T[PPT];
   float2 U[PPT][NL];
   uint32_t last[PPT];
@@ -42,8 +43,7 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_fwd(RasterArgs a) {
     pxf[p] = (float)px[p] + 0.5f;
     pyf[p] = (float)py[p] + 0.5f;
     inside[p] = px[p] < a.width && py[p] < a.height;
-    done[p] = !inside[p];
-    T[p] = 1.0f;
+    T[p] = inside[p] ? 1.0f : -1.0f;   // finished once T < T_min (which is >= 0)
     last[p] = 0;
 #pragma unroll
     for (int l = 0; l < NL; ++l) U[p][l] = make_float2(0.f, 0.f);
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_fwd(RasterArgs a) {
   for (uint32_t start = rg.x; start < rg.y; start += kBatch) {
     bool all_done = true;
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) all_done = all_done && done[p];
+    for (int p = 0; p < PPT; ++p) all_done = all_done && T[p] < a.t_min;
     // also the barrier before the next batch overwrites the staged records
     if constexpr (NW == 1) {
       if (__all(all_done)) break;
@@ -68,16 +68,16 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_fwd(RasterArgs a) {
     for (int j = 0; j < jend; ++j) {
       const float4 g0 = st.g0[j];
       const float4 g1 = st.g1[j];
-      const int4 rc = st.rc[j];
+      const int4 rc = uniform_rect(st.rc[j]);
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
-        if (done[p] || !rect_hits_block(rc, bx[p], by[p])) continue;
+        if (!rect_hits_block(rc, bx[p], by[p])) continue;   // scalar test
         const float dx = pxf[p] - g0.x, dy = pyf[p] - g0.y;
         const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
         const bool in_rect =
             (unsigned)(px[p] - rc.x) <= (unsigned)rc.y && (unsigned)(py[p] - rc.z) <= (unsigned)rc.w;
         const float aval = fminf(a.alpha_max, g1.y * __expf(-power));
-        if (in_rect && power <= half_k2 && aval >= a.alpha_min) {
+        if (T[p] >= a.t_min && in_rect && power <= half_k2 && aval >= a.alpha_min) {
           const float wgt = aval * T[p];
 #pragma unroll
           for (int l = 0; l < NL; ++l) {
@@ -87,7 +87,6 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_fwd(RasterArgs a) {
           }
           T[p] *= 1.0f - aval;
           last[p] = start + j + 1;
-          if (T[p] < a.t_min) done[p] = true;
         }
       }
     }
@@ -113,7 +112,8 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
   __shared__ float s_grad[kBatch][G2];
   __shared__ uint32_t s_last[NW];
   const TileGeom t = tile_of(a);
-  const int lane = threadIdx.x & (kLanes - 1), wave = threadIdx.x / kLanes;
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kLanes));
   int px[PPT], py[PPT], bx[PPT], by[PPT];
   float pxf[PPT], pyf[PPT];
   bool inside[PPT];
@@ -152,12 +152,14 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
   }
   // one past the last pair any pixel of the tile used
   for (int off = 32; off > 0; off >>= 1) tile_last = max(tile_last, (uint32_t)__shfl_xor((int)tile_last, off, 64));
-  const uint32_t wave_last = tile_last;   // this wave's pixels used no pair at or past it
+  // this wave's pixels used no pair at or past it (equal in every lane after the reduction)
+  const uint32_t wave_last = (uint32_t)__builtin_amdgcn_readfirstlane((int)tile_last);
   if constexpr (NW > 1) {
     if (lane == 0) s_last[wave] = tile_last;
     __syncthreads();
 #pragma unroll
     for (int w = 0; w < NW; ++w) tile_last = max(tile_last, s_last[w]);
+    tile_last = (uint32_t)__builtin_amdgcn_readfirstlane((int)tile_last);
   }
   const uint2 rg = a.ranges[blockIdx.x];
   const float half_k2 = 0.5f * a.k_sigma * a.k_sigma;
@@ -174,14 +176,18 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
       const uint32_t pidx = top - 1 - j;
       const float4 g0 = st.g0[j];
       const float4 g1 = st.g1[j];
-      const int4 rc = st.rc[j];
-      float gr[G2P];
+      const int4 rc = uniform_rect(st.rc[j]);
+      // Branch-free per pixel: a pixel outside the support takes alpha = 0,
+      // which leaves its T and B exactly unchanged and adds exact zeros to
+      // the alpha- and colour-gradient terms.
+      float gr[G2P];   // read only when some pixel of the wave was supported
+      if constexpr (PPT > 1)
 #pragma unroll
-      for (int c = 0; c < G2P; ++c) gr[c] = 0.f;
+        for (int c = 0; c < G2P; ++c) gr[c] = 0.f;
       bool any = false;
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
-        if (!rect_hits_block(rc, bx[p], by[p])) continue;
+        if (!rect_hits_block(rc, bx[p], by[p])) continue;   // scalar test
         const float dx = pxf[p] - g0.x, dy = pyf[p] - g0.y;
         const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
         const bool in_rect =
@@ -190,33 +196,43 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
         const float oG = g1.y * Gv;
         const bool clamped = oG > a.alpha_max;
         const float aval = clamped ? a.alpha_max : oG;
-        if (pidx < mylast[p] && in_rect && power <= half_k2 && aval >= a.alpha_min) {
-          any = true;
-          T[p] = T[p] * __builtin_amdgcn_rcpf(1.0f - aval);
-          float dLda = 0.f;
-          const float aT = aval * T[p];
+        const bool sup = pidx < mylast[p] && in_rect && power <= half_k2 && aval >= a.alpha_min;
+        if (!__any(sup)) continue;
+        any = true;
+        const float ae = sup ? aval : 0.f;
+        const float Tb = T[p] * __builtin_amdgcn_rcpf(1.0f - ae);
+        const float aT = ae * Tb;
+        float dLda = 0.f;
 #pragma unroll
-          for (int l = 0; l < NL; ++l) {
-            const float2 v = st.v[l][j];
-            dLda += G[p][l].x * (v.x - Bacc[p][l].x) + G[p][l].y * (v.y - Bacc[p][l].y);
-            gr[6 + 2 * l] += aT * G[p][l].x;
-            gr[7 + 2 * l] += aT * G[p][l].y;
-            Bacc[p][l].x = aval * v.x + (1.0f - aval) * Bacc[p][l].x;
-            Bacc[p][l].y = aval * v.y + (1.0f - aval) * Bacc[p][l].y;
-          }
-          dLda *= T[p];
-          if (!clamped) {
-            gr[5] += Gv * dLda;
-            const float dpow = -aval * dLda;
-            gr[2] += 0.5f * dx * dx * dpow;
-            gr[3] += dx * dy * dpow;
-            gr[4] += 0.5f * dy * dy * dpow;
-            gr[0] -= (g0.z * dx + g0.w * dy) * dpow;
-            gr[1] -= (g0.w * dx + g1.x * dy) * dpow;
-          }
+        for (int l = 0; l < NL; ++l) {
+          const float2 v = st.v[l][j];
+          dLda += G[p][l].x * (v.x - Bacc[p][l].x) + G[p][l].y * (v.y - Bacc[p][l].y);
+          const float gx = aT * G[p][l].x, gy = aT * G[p][l].y;
+          gr[6 + 2 * l] = PPT == 1 ? gx : gr[6 + 2 * l] + gx;
+          gr[7 + 2 * l] = PPT == 1 ? gy : gr[7 + 2 * l] + gy;
+          Bacc[p][l].x = ae * v.x + (1.0f - ae) * Bacc[p][l].x;
+          Bacc[p][l].y = ae * v.y + (1.0f - ae) * Bacc[p][l].y;
         }
+        T[p] = Tb;
+        // clamped pixels pass no gradient to the opacity or the conic
+        const float dl = (sup && !clamped) ? dLda * Tb : 0.f;
+        const float dpow = -aval * dl;
+        const float g5 = Gv * dl;
+        const float g2 = 0.5f * dx * dx * dpow;
+        const float g3 = dx * dy * dpow;
+        const float g4 = 0.5f * dy * dy * dpow;
+        const float g0v = -(g0.z * dx + g0.w * dy) * dpow;
+        const float g1v = -(g0.w * dx + g1.x * dy) * dpow;
+        gr[0] = PPT == 1 ? g0v : gr[0] + g0v;
+        gr[1] = PPT == 1 ? g1v : gr[1] + g1v;
+        gr[2] = PPT == 1 ? g2 : gr[2] + g2;
+        gr[3] = PPT == 1 ? g3 : gr[3] + g3;
+        gr[4] = PPT == 1 ? g4 : gr[4] + g4;
+        gr[5] = PPT == 1 ? g5 : gr[5] + g5;
       }
-      if (__ballot(any) != 0ull) {
+#pragma unroll
+      for (int c = G2; c < G2P; ++c) gr[c] = 0.f;
+      if (any) {
         wave_sums_by_row<G2P>(gr);
         if ((lane & 15) == 15) {
           const int row = lane >> 4;

@@ -45,6 +45,13 @@ __device__ inline bool rect_hits_block(const int4& rc, int bx, int by) {
   return rc.x <= bx + 7 && bx <= rc.x + rc.y && rc.z <= by + 7 && by <= rc.z + rc.w;
 }
 
+// A rectangle read from LDS by every lane of a wave at one address, moved to
+// scalar registers so that tests on it compile to scalar branches.
+__device__ inline int4 uniform_rect(const int4& r) {
+  return make_int4(__builtin_amdgcn_readfirstlane(r.x), __builtin_amdgcn_readfirstlane(r.y),
+                   __builtin_amdgcn_readfirstlane(r.z), __builtin_amdgcn_readfirstlane(r.w));
+}
+
 template <int NL>
 struct Stage {
   float4 g0[kBatch];
