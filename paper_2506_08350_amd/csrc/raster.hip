@@ -64,14 +64,22 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_fwd(RasterArgs a) {
     const int cnt = (int)min(rg.y - start, (uint32_t)kBatch);
     stage_records<NL>(st, a, start, cnt, false);
     __syncthreads();
-    const int jend = __all(all_done) ? 0 : cnt;   // a finished wave only keeps the barriers
-    for (int j = 0; j < jend; ++j) {
+    uint64_t hits[PPT], todo = 0;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      hits[p] = block_hits(st.rc, 0, cnt, bx[p], by[p]);
+      todo |= hits[p];
+    }
+    if (__all(all_done)) todo = 0;   // a finished wave only keeps the barriers
+    while (todo) {
+      const int j = (int)__builtin_ctzll(todo);
+      todo &= todo - 1;
       const float4 g0 = st.g0[j];
       const float4 g1 = st.g1[j];
-      const int4 rc = uniform_rect(st.rc[j]);
+      const int4 rc = st.rc[j];
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
-        if (!rect_hits_block(rc, bx[p], by[p])) continue;   // scalar test
+        if (PPT > 1 && !((hits[p] >> j) & 1u)) continue;
         const float dx = pxf[p] - g0.x, dy = pyf[p] - g0.y;
         const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
         const bool in_rect =
@@ -172,11 +180,19 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
     __syncthreads();
     // pairs at or past wave_last touch none of this wave's pixels
     const int j0 = top > wave_last ? (int)min(top - wave_last, (uint32_t)cnt) : 0;
-    for (int j = j0; j < cnt; ++j) {
+    uint64_t hits[PPT], todo = 0;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      hits[p] = block_hits(st.rc, j0, cnt, bx[p], by[p]);
+      todo |= hits[p];
+    }
+    while (todo) {
+      const int j = (int)__builtin_ctzll(todo);
+      todo &= todo - 1;
       const uint32_t pidx = top - 1 - j;
       const float4 g0 = st.g0[j];
       const float4 g1 = st.g1[j];
-      const int4 rc = uniform_rect(st.rc[j]);
+      const int4 rc = st.rc[j];
       // Branch-free per pixel: a pixel outside the support takes alpha = 0,
       // which leaves its T and B exactly unchanged and adds exact zeros to
       // the alpha- and colour-gradient terms.
@@ -187,7 +203,7 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
       bool any = false;
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
-        if (!rect_hits_block(rc, bx[p], by[p])) continue;   // scalar test
+        if (PPT > 1 && !((hits[p] >> j) & 1u)) continue;
         const float dx = pxf[p] - g0.x, dy = pyf[p] - g0.y;
         const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
         const bool in_rect =

@@ -12,10 +12,9 @@ namespace chrf {
 // that do not depend on the pixel (the gradient reduction over the wave) are
 // shared by PPT pixels.  Records are staged in LDS in batches of kBatch pairs.
 constexpr int kLanes = 64;
-#ifndef CHRF_RASTER_BATCH
-#define CHRF_RASTER_BATCH 64
-#endif
-constexpr int kBatch = CHRF_RASTER_BATCH;
+// One staged pair per lane of a wave: a wave finds the pairs that reach its
+// block with one ballot per batch.
+constexpr int kBatch = 64;
 
 struct TileGeom {
   int view, tx, ty;
@@ -45,11 +44,14 @@ __device__ inline bool rect_hits_block(const int4& rc, int bx, int by) {
   return rc.x <= bx + 7 && bx <= rc.x + rc.y && rc.z <= by + 7 && by <= rc.z + rc.w;
 }
 
-// A rectangle read from LDS by every lane of a wave at one address, moved to
-// scalar registers so that tests on it compile to scalar branches.
-__device__ inline int4 uniform_rect(const int4& r) {
-  return make_int4(__builtin_amdgcn_readfirstlane(r.x), __builtin_amdgcn_readfirstlane(r.y),
-                   __builtin_amdgcn_readfirstlane(r.z), __builtin_amdgcn_readfirstlane(r.w));
+// Bit j: staged pair j, j_first <= j < cnt, has a support rectangle reaching
+// the 8x8 block at (bx, by).  Lane j tests pair j; the mask is wave-uniform,
+// so the pair walk visits only the set bits, in order, with scalar control.
+__device__ inline uint64_t block_hits(const int4* rc, int j_first, int cnt, int bx, int by) {
+  const int lane = threadIdx.x & 63;
+  bool h = false;
+  if (lane >= j_first && lane < cnt) h = rect_hits_block(rc[lane], bx, by);
+  return __ballot(h);
 }
 
 template <int NL>

@@ -74,7 +74,7 @@ __device__ inline void stage_records_l(StageL<NL>& st, const RasterArgs& a, uint
 
 // Pixel of this lane: wave w covers the w-th 8x8 block of the tile.
 __device__ inline void layer_pixel(const RasterArgs& a, const TileGeom& t, int& px, int& py, int& bx, int& by) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int bpr = a.tile_w >> 3;
   bx = t.tx * a.tile_w + (w % bpr) * 8;
   by = t.ty * a.tile_h + (w / bpr) * 8;
@@ -110,9 +110,18 @@ __global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_fwd(RasterArgs a) 
     stage_records_l<NL>(st, a, start, cnt, false);
     __syncthreads();
     if (__any(live != 0u)) {
-      for (int j = 0; j < cnt; ++j) {
+      // layers still live at some pixel of the wave; pairs of other layers are skipped
+      uint32_t wave_live = 0;
+#pragma unroll
+      for (int q = 0; q < NLAY; ++q)
+        if (__any((live >> q) & 1u)) wave_live |= 1u << q;
+      uint64_t todo = block_hits(st.s.rc, 0, cnt, bx, by);
+      const int lane = threadIdx.x & 63;
+      todo &= __ballot(lane < cnt && ((wave_live >> (st.lay[lane] & 7)) & 1u));
+      while (todo) {
+        const int j = (int)__builtin_ctzll(todo);
+        todo &= todo - 1;
         const int4 rc = st.s.rc[j];
-        if (!rect_hits_block(rc, bx, by)) continue;
         const int lay = __builtin_amdgcn_readfirstlane(st.lay[j]) & 7;
         if (!((live >> lay) & 1u)) continue;
         const float4 g0 = st.s.g0[j];
@@ -202,12 +211,14 @@ __global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_bwd(RasterArgs a) 
   if (inside) mylast = a.last[(size_t)t.view * plane + pix];
   uint32_t wave_last = mylast;
   for (int off = 32; off > 0; off >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, off, 64));
+  wave_last = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_last);
   if (lane == 0) s_last[threadIdx.x >> 6] = wave_last;
   for (int i = threadIdx.x; i < kBatch * G2; i += blockDim.x) (&s_grad[0][0])[i] = 0.f;
   __syncthreads();
   uint32_t tile_last = 0;
 #pragma unroll
   for (int w = 0; w < NWAVE; ++w) tile_last = max(tile_last, s_last[w]);
+  tile_last = (uint32_t)__builtin_amdgcn_readfirstlane((int)tile_last);
   const uint2 rg = a.ranges[blockIdx.x];
   const float half_k2 = 0.5f * a.k_sigma * a.k_sigma;
 
@@ -218,9 +229,11 @@ __global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_bwd(RasterArgs a) 
     if (top - cnt < wave_last) {   // this wave has work in the batch
       // pairs at or past wave_last touch none of this wave's pixels
       const int j0 = top > wave_last ? (int)min(top - wave_last, (uint32_t)cnt) : 0;
-      for (int j = j0; j < cnt; ++j) {
+      uint64_t todo = block_hits(st.s.rc, j0, cnt, bx, by);
+      while (todo) {
+        const int j = (int)__builtin_ctzll(todo);
+        todo &= todo - 1;
         const int4 rc = st.s.rc[j];
-        if (!rect_hits_block(rc, bx, by)) continue;
         const uint32_t pidx = top - 1 - j;
         const int packed = __builtin_amdgcn_readfirstlane(st.lay[j]);
         const int lay = packed & 7;
@@ -234,9 +247,6 @@ __global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_bwd(RasterArgs a) 
         if (!__any(useful)) continue;
         const float4 g0 = st.s.g0[j];
         const float4 g1 = st.s.g1[j];
-        float gr[G2P];
-#pragma unroll
-        for (int c = 0; c < G2P; ++c) gr[c] = 0.f;
         const float dx = pxf - g0.x, dy = pyf - g0.y;
         const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
         const bool in_rect = (unsigned)(px - rc.x) <= (unsigned)rc.y && (unsigned)(py - rc.z) <= (unsigned)rc.w;
@@ -244,60 +254,69 @@ __global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_bwd(RasterArgs a) 
         const float oG = g1.y * Gv;
         const bool clamped = oG > a.alpha_max;
         const float aval = clamped ? a.alpha_max : oG;
-        const bool sup = pidx < mylast && in_rect && power <= half_k2 && aval >= a.alpha_min;
-        if (sup) {
-          float dLda = 0.f;
+        const bool sup = useful && pidx < mylast && in_rect && power <= half_k2 && aval >= a.alpha_min;
+        if (!__any(sup)) continue;
+        // Branch-free per pixel: where layer q is not active the own layer takes
+        // alpha = 0 (its T and B stay exactly unchanged) and another layer's
+        // straight-through term is zero.
+        float gr[G2P];
+        float dLda = 0.f;
 #pragma unroll
-          for (int q = 0; q < NLAY; ++q) {
-            if (pidx >= stop[q]) continue;   // layer q had stopped before this pair
-            const bool own = q == lay;       // wave-uniform
-            if (!own && !((ste_live >> q) & 1u)) continue;   // zero straight-through weight
-            const float Tb = own ? T[q] * __builtin_amdgcn_rcpf(1.0f - aval) : T[q];
-            float sq = 0.f;
+        for (int q = 0; q < NLAY; ++q) {
+          const bool own = q == lay;   // wave-uniform
+          if (!own && !((ste_live >> q) & 1u)) {   // zero straight-through weight
+            gr[6 + 2 * NL + q] = 0.f;
+            continue;
+          }
+          const bool act = sup && pidx < stop[q];   // layer q had not stopped before this pair
+          float sq = 0.f;
+#pragma unroll
+          for (int l = 0; l < NL; ++l) {
+            const float2 v = st.s.v[l][j];
+            sq += G[q][l].x * (v.x - Bacc[q][l].x) + G[q][l].y * (v.y - Bacc[q][l].y);
+          }
+          if (own) {
+            const float ae = act ? aval : 0.f;
+            const float Tb = T[q] * __builtin_amdgcn_rcpf(1.0f - ae);
+            sq *= Tb;
+            gr[6 + 2 * NL + q] = ae * sq;
+            dLda = act ? sq : 0.f;
+            const float aT = ae * Tb;
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
               const float2 v = st.s.v[l][j];
-              sq += G[q][l].x * (v.x - Bacc[q][l].x) + G[q][l].y * (v.y - Bacc[q][l].y);
+              gr[6 + 2 * l] = aT * G[q][l].x;
+              gr[7 + 2 * l] = aT * G[q][l].y;
+              Bacc[q][l].x = ae * v.x + (1.0f - ae) * Bacc[q][l].x;
+              Bacc[q][l].y = ae * v.y + (1.0f - ae) * Bacc[q][l].y;
             }
-            sq *= Tb;
-            gr[6 + 2 * NL + q] = aval * sq;
-            if (own) {
-              dLda = sq;
-              const float aT = aval * Tb;
-#pragma unroll
-              for (int l = 0; l < NL; ++l) {
-                const float2 v = st.s.v[l][j];
-                gr[6 + 2 * l] = aT * G[q][l].x;
-                gr[7 + 2 * l] = aT * G[q][l].y;
-                Bacc[q][l].x = aval * v.x + (1.0f - aval) * Bacc[q][l].x;
-                Bacc[q][l].y = aval * v.y + (1.0f - aval) * Bacc[q][l].y;
-              }
-              T[q] = Tb;
-            }
-          }
-          if (!clamped) {
-            gr[5] = Gv * dLda;
-            const float dpow = -aval * dLda;
-            gr[2] = 0.5f * dx * dx * dpow;
-            gr[3] = dx * dy * dpow;
-            gr[4] = 0.5f * dy * dy * dpow;
-            gr[0] = -(g0.z * dx + g0.w * dy) * dpow;
-            gr[1] = -(g0.w * dx + g1.x * dy) * dpow;
+            T[q] = Tb;
+          } else {
+            gr[6 + 2 * NL + q] = act ? aval * (sq * T[q]) : 0.f;
           }
         }
-        if (__ballot(sup) != 0ull) {
-          wave_sums_by_row<G2P>(gr);
-          if ((lane & 15) == 15) {
-            const int row = lane >> 4;
+        // clamped pixels pass no gradient to the opacity or the conic
+        const float dl = clamped ? 0.f : dLda;
+        const float dpow = -aval * dl;
+        gr[5] = Gv * dl;
+        gr[2] = 0.5f * dx * dx * dpow;
+        gr[3] = dx * dy * dpow;
+        gr[4] = 0.5f * dy * dy * dpow;
+        gr[0] = -(g0.z * dx + g0.w * dy) * dpow;
+        gr[1] = -(g0.w * dx + g1.x * dy) * dpow;
 #pragma unroll
-            for (int k = 0; k < G2P / 4; ++k) {
-              const int c = k + row * (G2P / 4);
-              if (c < G2) {
-                if (NWAVE == 1)
-                  s_grad[j][c] = gr[k];
-                else
-                  atomicAdd(&s_grad[j][c], gr[k]);
-              }
+        for (int c = G2; c < G2P; ++c) gr[c] = 0.f;
+        wave_sums_by_row<G2P>(gr);
+        if ((lane & 15) == 15) {
+          const int row = lane >> 4;
+#pragma unroll
+          for (int k = 0; k < G2P / 4; ++k) {
+            const int c = k + row * (G2P / 4);
+            if (c < G2) {
+              if (NWAVE == 1)
+                s_grad[j][c] = gr[k];
+              else
+                atomicAdd(&s_grad[j][c], gr[k]);
             }
           }
         }
