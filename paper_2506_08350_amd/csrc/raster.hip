@@ -279,10 +279,11 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
 }
 
 // Waves per tile of the forward: up to kFwdWaves, one or more 8x8 blocks
-// each.  Two waves per 16x16 tile halve the serial walk of a wave and let
-// the CU overlap one wave's record loads with the other's compositing.
+// each.  One wave per 8x8 block of a 16x16 tile: each wave walks only the
+// pairs that reach its block, and the CU overlaps one wave's record loads
+// with the others' compositing.
 #ifndef CHRF_FWD_WAVES
-#define CHRF_FWD_WAVES 2
+#define CHRF_FWD_WAVES 4
 #endif
 constexpr int kFwdWaves = CHRF_FWD_WAVES;
 
@@ -292,11 +293,11 @@ static void launch_fwd_nl(const RasterArgs& a, int blocks, hipStream_t s) {
   k_raster_fwd<NL, BPT / NW, NW><<<blocks, kLanes * NW, 0, s>>>(a);
 }
 
-// Waves per tile of the backward: one 8x8 block per wave at 16x16 tiles
-// (the per-pair wave reduction is then per block, but four waves per tile
-// hide the record gathers and atomics better than one wave with four blocks).
+// Waves per tile of the backward: two waves of two 8x8 blocks each at 16x16
+// tiles, so one per-pair wave reduction serves two pixels per lane while two
+// waves still overlap record gathers and atomics.
 #ifndef CHRF_BWD_WAVES
-#define CHRF_BWD_WAVES 4
+#define CHRF_BWD_WAVES 2
 #endif
 constexpr int kBwdWaves = CHRF_BWD_WAVES;
 
