@@ -341,12 +341,41 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
   }
 }
 
+// The adjoint reads K input columns, one per plane.  With two columns per
+// workgroup and half-height inputs, plane k + 1 is copied from HBM straight
+// into an LDS buffer (global_load_lds, 16 bytes = one row of both columns
+// per lane) while plane k's transform runs; its stage-1 inputs are read from
+// that buffer.  The stage twiddles are read before the copy is started, so
+// that only the explicit wait before the next plane waits on it.
+// A plane's parameters moved to scalar registers where they are loaded, so
+// that the load completes there and not at a later wait.
+__device__ inline HParam uniform_hparam(const HParam& h) {
+  const auto u = [](float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); };
+  HParam r;
+  r.frac_rev = u(h.frac_rev);
+  r.z = u(h.z);
+  r.inv_lam = u(h.inv_lam);
+  r.inv_lam2 = u(h.inv_lam2);
+  r.kx_max = __builtin_amdgcn_readfirstlane(h.kx_max);
+  r.ky_max = __builtin_amdgcn_readfirstlane(h.ky_max);
+  const unsigned long long e = (unsigned long long)h.evan_bound;
+  r.evan_bound = (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(e >> 32)) << 32) |
+                             (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)e));
+  return r;
+}
+
+typedef __attribute__((address_space(1))) void gmem_void;
+typedef __attribute__((address_space(3))) void lds_void;
+
 template <int C, bool HALF>
 __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoint_t(
     const float2* __restrict__ z, float2* __restrict__ w1out, AsmGeom g, FftDesc fc) {
   using CT = ColT<C>;
+  constexpr bool kDma = HALF && C == 2;
+  constexpr int kLiveRows = kColN / 2;
   __shared__ cpx lds[lds_padded_size(kColN * C)];
   __shared__ cpx s_tw[CT::kLdsTw ? kColN : 1];
+  __shared__ cpx s_in[kDma ? kLiveRows * C : 1];   // [row][column]
   const cpx* twl = CT::kLdsTw ? stage_twiddles<CT::NT>(s_tw, fc.tw) : fc.tw;
   const int ngroups = g.pW / C;
   const int gid = col_remap(blockIdx.x, gridDim.x, CT::SPAN);
@@ -367,25 +396,58 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoi
 #pragma unroll
     for (int q = 0; q < 9; ++q) s_q[q][b] = transfer_q(hp0, cf, j + q * (kColN / 9), g);
   }
+  // wave w copies rows 64 i .. 64 i + 63 for i = w, w + NT / 64, ...
+  auto copy_plane = [&](int k) {
+    if constexpr (kDma) {
+      const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+      const float2* zk = z + ((size_t)bl * g.K + k) * g.H * g.pW + c0;
+      for (int i = w; i * 64 < kLiveRows; i += CT::NT / 64) {
+        const int row = i * 64 + lane;
+        if (row < kLiveRows)
+          __builtin_amdgcn_global_load_lds((const gmem_void*)(zk + (size_t)row * g.pW), (lds_void*)&s_in[i * 64 * C], 16,
+                                           0, 0);
+      }
+    }
+  };
+  // the copies of this wave are complete and every wave has passed here
+  auto copies_visible = [] {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    __syncthreads();
+  };
+  if constexpr (kDma) {
+    copy_plane(0);
+    copies_visible();
+  }
   for (int k = 0; k < g.K; ++k) {
     const float2* zk = z + ((size_t)bl * g.K + k) * g.H * g.pW + c0 + s;
     const int jj = opaque_v(j), kx = opaque_v(c0 + s);
+    const HParam hp = uniform_hparam(g.hp[lam * g.K + k]);
     cpx v1[1][16], v3[1][9];
     if (b < CT::Fwd::B1) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int n = jj + r * (kColN / 16);
-        v1[0][r] = (HALF ? r < 8 : n < g.H) ? ldc(zk + (size_t)n * g.pW) : cpx{0.f, 0.f};
+        if constexpr (kDma) {
+          v1[0][r] = r < 8 ? s_in[(r < 8 ? n : 0) * C + s] : cpx{0.f, 0.f};
+        } else {
+          v1[0][r] = (HALF ? r < 8 : n < g.H) ? ldc(zk + (size_t)n * g.pW) : cpx{0.f, 0.f};
+        }
       }
     }
-    CT::Fwd::template run<CT::kLdsTw && CT::kRegSpec>(v1, v3, lds, twl, opaque_v(b));   // C = 4 would spill with the table
-    const HParam hp = g.hp[lam * g.K + k];
+    // stage 1 has read its inputs once the hook runs: the buffer is free
+    auto start_next = [&] {
+      if (k + 1 < g.K) copy_plane(k + 1);
+    };
+    // C = 4 would spill with the table
+    CT::Fwd::template run_hooked<CT::kLdsTw && CT::kRegSpec, 1, kDma>(v1, v3, lds, twl, start_next, opaque_v(b));
     if (b < CT::Fwd::B3) {
       const bool col_pass = g.band_mode < 2 || abs(sbin(kx, g.pW)) <= hp.kx_max;
 #pragma unroll
       for (int q = 0; q < 9; ++q)
         acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_from_q(hp, col_pass, s_q[q][b], jj + q * (kColN / 9), g));
     }
+    if constexpr (kDma)
+      if (k + 1 < g.K) copies_visible();
   }
 #pragma unroll
   for (int q = 0; q < 9; ++q) acc[0][q] = acc[0][q] * g.norm;

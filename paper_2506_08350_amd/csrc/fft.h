@@ -20,6 +20,24 @@ struct cpx {
   float x, y;
 };
 
+// Workgroup barrier ordering LDS accesses only.  The stage barriers of the
+// transforms guard nothing but the LDS work buffer; unlike __syncthreads()
+// this one does not first wait for the wave's global loads and stores still
+// in flight (output stores, or copies into LDS for the next transform).
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+// The same for waves with copies into LDS (global_load_lds) in flight to a
+// buffer that the barrier does not guard: an LDS fence would also wait for
+// those copies, so the wave waits only for its own LDS operations (the
+// memory clobber keeps the compiler from moving accesses across).  The
+// caller waits for the copies itself before reading their buffer.
+__device__ inline void lds_barrier_copies_in_flight() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 __host__ __device__ inline cpx mk(float x, float y) { return cpx{x, y}; }
 __host__ __device__ inline cpx operator+(cpx a, cpx b) { return cpx{a.x + b.x, a.y + b.y}; }
 __host__ __device__ inline cpx operator-(cpx a, cpx b) { return cpx{a.x - b.x, a.y - b.y}; }
@@ -301,6 +319,14 @@ struct Fft3 {
   static constexpr int B1 = C * N / R1, B2 = C * N / R2, B3 = C * N / R3;
   static constexpr int M1 = (B1 + NT - 1) / NT, M2 = (B2 + NT - 1) / NT, M3 = (B3 + NT - 1) / NT;
 
+  template <bool COPIES>
+  __device__ static inline void stage_barrier() {
+    if constexpr (COPIES)
+      lds_barrier_copies_in_flight();
+    else
+      lds_barrier();
+  }
+
   __device__ static inline cpx twid(const cpx* __restrict__ tw, int m) {
     const cpx w = tw[m];
     return INV ? cpx{w.x, -w.y} : w;
@@ -318,13 +344,31 @@ struct Fft3 {
 #pragma unroll
       for (int r = 1; r < R; ++r, m += step) v[r] = INV ? cmulc(v[r], tw[m]) : cmul(v[r], tw[m]);
     } else {
-      const cpx w = twid(tw, step);
-      cpx wr = w;
+      apply_twiddle_powers(v, twid(tw, step));
+    }
+  }
+  // The value is pinned where it is used: an early-loaded twiddle would
+  // otherwise have all its powers formed early and kept live.
+  __device__ static inline cpx pinned(cpx w) {
+    asm volatile("" : "+v"(w.x), "+v"(w.y));
+    return w;
+  }
+  // Makes the early twiddle loads complete here, before the hook starts
+  // loads of its own: a later wait for them would also wait for those.
+  template <int A, int B>
+  __device__ static inline void settle_twiddles(cpx (&w2)[A], cpx (&w3)[B]) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        v[r] = cmul(v[r], wr);
-        wr = cmul(wr, w);
-      }
+    for (int i = 0; i < A; ++i) w2[i] = pinned(w2[i]);
+#pragma unroll
+    for (int i = 0; i < B; ++i) w3[i] = pinned(w3[i]);
+  }
+  template <int R>
+  __device__ static inline void apply_twiddle_powers(cpx (&v)[R], cpx w) {
+    cpx wr = w;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      v[r] = cmul(v[r], wr);
+      wr = cmul(wr, w);
     }
   }
 
@@ -333,6 +377,34 @@ struct Fft3 {
   template <bool TABLE = false>
   __device__ static inline void run(cpx (&v1)[M1][R1], cpx (&v3)[M3][R3], cpx* lds, const cpx* __restrict__ tw,
                                     int tid = threadIdx.x) {
+    run_hooked<TABLE, 1>(v1, v3, lds, tw, [] {}, tid);
+  }
+
+  // As run(), calling hook() once stage AT (1 or 2) has written its outputs
+  // to LDS, for callers that start the loads of their next transform there.
+  // EARLY_TW is for hooks that start copies into LDS: the stage-2 and
+  // stage-3 twiddles (one entry each) are read before stage 1 and settled
+  // before the hook, so that no vector-memory wait after it waits on the
+  // copies too (vector-memory loads complete in issue order), and the stage
+  // barriers after the hook do not wait for them either.
+  template <bool TABLE, int AT, bool EARLY_TW = false, class Hook>
+  __device__ static inline void run_hooked(cpx (&v1)[M1][R1], cpx (&v3)[M3][R3], cpx* lds,
+                                           const cpx* __restrict__ tw, Hook&& hook, int tid = threadIdx.x) {
+    static_assert(AT == 1 || AT == 2, "hook after stage 1 or 2");
+    static_assert(!(EARLY_TW && TABLE), "early twiddles are single table entries");
+    cpx w2[EARLY_TW ? M2 : 1], w3[EARLY_TW ? M3 : 1];
+    if constexpr (EARLY_TW) {
+#pragma unroll
+      for (int i = 0; i < M2; ++i) {
+        const int b = tid + i * NT;
+        w2[i] = (B2 % NT == 0 || b < B2) ? twid(tw, ((b / C) % R1) * (N / (R1 * R2))) : cpx{1.f, 0.f};
+      }
+#pragma unroll
+      for (int i = 0; i < M3; ++i) {
+        const int b = tid + i * NT;
+        w3[i] = (B3 % NT == 0 || b < B3) ? twid(tw, b / C) : cpx{1.f, 0.f};
+      }
+    }
     // stage 1 (Ns = 1): no twiddles; output q of butterfly j goes to j R1 + q
 #pragma unroll
     for (int i = 0; i < M1; ++i) {
@@ -351,7 +423,11 @@ struct Fft3 {
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
+    if constexpr (AT == 1) {
+      if constexpr (EARLY_TW) settle_twiddles(w2, w3);
+      hook();
+    }
     // stage 2 (Ns = R1)
     cpx v2[M2][R2];
 #pragma unroll
@@ -363,11 +439,14 @@ struct Fft3 {
 #pragma unroll
         for (int r = 0; r < R2; ++r)
           v2[i][r] = lds[strided_pad<(N / R2) * C>(p0, j * C + s, r)];
-        apply_twiddles<R2, TABLE>(v2[i], tw, k * (N / (R1 * R2)));
+        if constexpr (EARLY_TW)
+          apply_twiddle_powers(v2[i], pinned(w2[EARLY_TW ? i : 0]));
+        else
+          apply_twiddles<R2, TABLE>(v2[i], tw, k * (N / (R1 * R2)));
         Dft<R2, INV>::run(v2[i]);
       }
     }
-    __syncthreads();
+    stage_barrier<EARLY_TW>();
 #pragma unroll
     for (int i = 0; i < M2; ++i) {
       const int b = tid + i * NT;
@@ -379,7 +458,11 @@ struct Fft3 {
         for (int q = 0; q < R2; ++q) lds[strided_pad<R1 * C>(p0, base * C + s, q)] = v2[i][q];
       }
     }
-    __syncthreads();
+    stage_barrier<EARLY_TW>();
+    if constexpr (AT == 2) {
+      if constexpr (EARLY_TW) settle_twiddles(w2, w3);
+      hook();
+    }
     // stage 3 (Ns = R1 R2 = N / R3): j < Ns, so k = j and outputs land at j + q N/R3
 #pragma unroll
     for (int i = 0; i < M3; ++i) {
@@ -389,11 +472,14 @@ struct Fft3 {
         const int p0 = lds_pad(j * C + s);
 #pragma unroll
         for (int r = 0; r < R3; ++r) v3[i][r] = lds[strided_pad<(N / R3) * C>(p0, j * C + s, r)];
-        apply_twiddles<R3, TABLE>(v3[i], tw, j);
+        if constexpr (EARLY_TW)
+          apply_twiddle_powers(v3[i], pinned(w3[EARLY_TW ? i : 0]));
+        else
+          apply_twiddles<R3, TABLE>(v3[i], tw, j);
         Dft<R3, INV>::run(v3[i]);
       }
     }
-    __syncthreads();   // LDS is free again for the caller
+    stage_barrier<EARLY_TW>();   // LDS is free again for the caller
   }
 };
 
