@@ -348,10 +348,12 @@ def main(argv=None):
         torch.cuda.synchronize()
         fwd_ms = (time.perf_counter() - f0) * 1000.0 / args.steps
 
-    # The dominant kernel of the step is a raster kernel, bound by its vector
-    # ALU work: it is reported against the VALU issue peak (lane-operations
-    # issued per second, from its counted VALU instructions and the live
-    # launch time).  The dominant propagation kernel is reported against HBM.
+    # The dominant kernel of the step (the raster backward, or a column FFT
+    # pass) issues more vector-ALU lane-operations per HBM byte than the
+    # chip's ratio (78.6 T/s over 8 TB/s, about 10 per byte), so it is
+    # reported against the VALU issue peak (lane-operations issued per
+    # second, from its counted VALU instructions and the live launch time).
+    # The dominant propagation kernel is also reported against HBM.
     per_launch = {n: (c, tot / c) for n, (c, tot) in kt.items()}
     fused = args.loss == "mse"
     asm = {n: v for n, v in per_launch.items() if kernel_bytes(n, B, L, K, H, W, pH, pW, train, fused) is not None}
