@@ -37,6 +37,21 @@ __device__ inline int opaque_v(int v) {
   return v;
 }
 
+// Plane parameters are read-only during a launch: read through the constant
+// address space, a uniform index becomes a scalar load, which neither waits
+// on nor is waited on with the vector-memory traffic (output stores, copies).
+__device__ inline HParam load_hparam(const HParam* hp, int i) {
+  static_assert(sizeof(HParam) % 4 == 0, "read as 32-bit words");
+  typedef const __attribute__((address_space(4))) uint32_t* const_words;
+  const const_words src = (const_words)(hp + i);
+  uint32_t w[sizeof(HParam) / 4];
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(HParam) / 4); ++k) w[k] = src[k];
+  HParam r;
+  __builtin_memcpy(&r, w, sizeof r);
+  return r;
+}
+
 // Transfer function H_k at the bins of one column.  The column terms are
 // computed once; per element the band tests are integer compares, the
 // residual phase is formed in revolutions with the hardware square root and
@@ -312,13 +327,16 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
   }
   float qv[9];   // plane-independent transfer terms of this thread's 9 bins
   if (b < CT::Inv::B1) {
-    const HParam hp0 = g.hp[lam * g.K];
+    const HParam hp0 = load_hparam(g.hp, lam * g.K);
     const ColFreq cf = col_freq(hp0, c0 + s, g);
 #pragma unroll
     for (int q = 0; q < 9; ++q) qv[q] = transfer_q(hp0, cf, j + q * (kColN / 9), g);
   }
+  // inverse-transform twiddles, the same for every plane: read once, so that
+  // the plane loop issues no vector load that would wait on its stores
+  const typename CT::Inv::StageTw itw = CT::Inv::stage_twiddles_of(fc.tw, b);
   for (int k = 0; k < g.K; ++k) {
-    const HParam hp = g.hp[lam * g.K + k];
+    const HParam hp = load_hparam(g.hp, lam * g.K + k);
     const int jj = opaque_v(j), kx = opaque_v(c0 + s);
     cpx w1[1][9], w3[1][16];
     if (b < CT::Inv::B1) {
@@ -329,7 +347,10 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
         w1[0][q] = cmul(sv, transfer_from_q(hp, col_pass, qv[q], jj + q * (kColN / 9), g));
       }
     }
-    CT::Inv::template run<CT::kLdsTw>(w1, w3, lds, twl, opaque_v(b));
+    if constexpr (CT::kLdsTw)
+      CT::Inv::template run<CT::kLdsTw>(w1, w3, lds, twl, opaque_v(b));
+    else
+      CT::Inv::run_with_twiddles(w1, w3, lds, itw, opaque_v(b));
     if (b < CT::Inv::B3) {
       float2* yk = y + ((size_t)bl * g.K + k) * g.H * g.pW + kx;
 #pragma unroll
@@ -347,23 +368,6 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
 // per lane) while plane k's transform runs; its stage-1 inputs are read from
 // that buffer.  The stage twiddles are read before the copy is started, so
 // that only the explicit wait before the next plane waits on it.
-// A plane's parameters moved to scalar registers where they are loaded, so
-// that the load completes there and not at a later wait.
-__device__ inline HParam uniform_hparam(const HParam& h) {
-  const auto u = [](float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); };
-  HParam r;
-  r.frac_rev = u(h.frac_rev);
-  r.z = u(h.z);
-  r.inv_lam = u(h.inv_lam);
-  r.inv_lam2 = u(h.inv_lam2);
-  r.kx_max = __builtin_amdgcn_readfirstlane(h.kx_max);
-  r.ky_max = __builtin_amdgcn_readfirstlane(h.ky_max);
-  const unsigned long long e = (unsigned long long)h.evan_bound;
-  r.evan_bound = (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(e >> 32)) << 32) |
-                             (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)e));
-  return r;
-}
-
 typedef __attribute__((address_space(1))) void gmem_void;
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -391,7 +395,7 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoi
   // (each thread reads back only its own entries) to spare registers
   __shared__ float s_q[9][CT::NT];
   if (b < CT::Fwd::B3) {
-    const HParam hp0 = g.hp[lam * g.K];
+    const HParam hp0 = load_hparam(g.hp, lam * g.K);
     const ColFreq cf = col_freq(hp0, c0 + s, g);
 #pragma unroll
     for (int q = 0; q < 9; ++q) s_q[q][b] = transfer_q(hp0, cf, j + q * (kColN / 9), g);
@@ -421,7 +425,7 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoi
   for (int k = 0; k < g.K; ++k) {
     const float2* zk = z + ((size_t)bl * g.K + k) * g.H * g.pW + c0 + s;
     const int jj = opaque_v(j), kx = opaque_v(c0 + s);
-    const HParam hp = uniform_hparam(g.hp[lam * g.K + k]);
+    const HParam hp = load_hparam(g.hp, lam * g.K + k);
     cpx v1[1][16], v3[1][9];
     if (b < CT::Fwd::B1) {
 #pragma unroll

@@ -380,31 +380,56 @@ struct Fft3 {
     run_hooked<TABLE, 1>(v1, v3, lds, tw, [] {}, tid);
   }
 
+  // The stage-2 and stage-3 twiddles of this thread (one table entry each;
+  // their powers are formed where they are applied).
+  struct StageTw {
+    cpx w2[M2], w3[M3];
+  };
+  __device__ static inline StageTw stage_twiddles_of(const cpx* __restrict__ tw, int tid) {
+    StageTw t;
+#pragma unroll
+    for (int i = 0; i < M2; ++i) {
+      const int b = tid + i * NT;
+      t.w2[i] = (B2 % NT == 0 || b < B2) ? twid(tw, ((b / C) % R1) * (N / (R1 * R2))) : cpx{1.f, 0.f};
+    }
+#pragma unroll
+    for (int i = 0; i < M3; ++i) {
+      const int b = tid + i * NT;
+      t.w3[i] = (B3 % NT == 0 || b < B3) ? twid(tw, b / C) : cpx{1.f, 0.f};
+    }
+    return t;
+  }
+
   // As run(), calling hook() once stage AT (1 or 2) has written its outputs
   // to LDS, for callers that start the loads of their next transform there.
   // EARLY_TW is for hooks that start copies into LDS: the stage-2 and
-  // stage-3 twiddles (one entry each) are read before stage 1 and settled
-  // before the hook, so that no vector-memory wait after it waits on the
-  // copies too (vector-memory loads complete in issue order), and the stage
-  // barriers after the hook do not wait for them either.
+  // stage-3 twiddles are read before stage 1 and settled before the hook, so
+  // that no vector-memory wait after it waits on the copies too (vector-memory
+  // loads complete in issue order), and the stage barriers after the hook do
+  // not wait for them either.
   template <bool TABLE, int AT, bool EARLY_TW = false, class Hook>
   __device__ static inline void run_hooked(cpx (&v1)[M1][R1], cpx (&v3)[M3][R3], cpx* lds,
                                            const cpx* __restrict__ tw, Hook&& hook, int tid = threadIdx.x) {
-    static_assert(AT == 1 || AT == 2, "hook after stage 1 or 2");
     static_assert(!(EARLY_TW && TABLE), "early twiddles are single table entries");
-    cpx w2[EARLY_TW ? M2 : 1], w3[EARLY_TW ? M3 : 1];
-    if constexpr (EARLY_TW) {
-#pragma unroll
-      for (int i = 0; i < M2; ++i) {
-        const int b = tid + i * NT;
-        w2[i] = (B2 % NT == 0 || b < B2) ? twid(tw, ((b / C) % R1) * (N / (R1 * R2))) : cpx{1.f, 0.f};
-      }
-#pragma unroll
-      for (int i = 0; i < M3; ++i) {
-        const int b = tid + i * NT;
-        w3[i] = (B3 % NT == 0 || b < B3) ? twid(tw, b / C) : cpx{1.f, 0.f};
-      }
-    }
+    run_core<TABLE, AT, EARLY_TW ? 1 : 0>(v1, v3, lds, tw, hook, tid,
+                                            EARLY_TW ? stage_twiddles_of(tw, tid) : StageTw{});
+  }
+
+  // As run(), with the stage twiddles read beforehand (stage_twiddles_of):
+  // for transforms in a loop whose twiddles do not change, so that the loop
+  // issues no vector-memory load that would wait on its earlier stores.
+  __device__ static inline void run_with_twiddles(cpx (&v1)[M1][R1], cpx (&v3)[M3][R3], cpx* lds, const StageTw& t,
+                                                  int tid) {
+    run_core<false, 1, 2>(v1, v3, lds, nullptr, [] {}, tid, t);
+  }
+
+  // MODE 0: twiddles read in their stage; 1: read early, settled before the
+  // hook, copy-tolerant stage barriers after it; 2: supplied by the caller.
+  template <bool TABLE, int AT, int MODE, class Hook>
+  __device__ static inline void run_core(cpx (&v1)[M1][R1], cpx (&v3)[M3][R3], cpx* lds, const cpx* __restrict__ tw,
+                                         Hook&& hook, int tid, StageTw t) {
+    static_assert(AT == 1 || AT == 2, "hook after stage 1 or 2");
+    constexpr bool EARLY_TW = MODE == 1, GIVEN_TW = MODE >= 1;
     // stage 1 (Ns = 1): no twiddles; output q of butterfly j goes to j R1 + q
 #pragma unroll
     for (int i = 0; i < M1; ++i) {
@@ -425,7 +450,7 @@ struct Fft3 {
     }
     lds_barrier();
     if constexpr (AT == 1) {
-      if constexpr (EARLY_TW) settle_twiddles(w2, w3);
+      if constexpr (EARLY_TW) settle_twiddles(t.w2, t.w3);
       hook();
     }
     // stage 2 (Ns = R1)
@@ -439,8 +464,8 @@ struct Fft3 {
 #pragma unroll
         for (int r = 0; r < R2; ++r)
           v2[i][r] = lds[strided_pad<(N / R2) * C>(p0, j * C + s, r)];
-        if constexpr (EARLY_TW)
-          apply_twiddle_powers(v2[i], pinned(w2[EARLY_TW ? i : 0]));
+        if constexpr (GIVEN_TW)
+          apply_twiddle_powers(v2[i], pinned(t.w2[i]));
         else
           apply_twiddles<R2, TABLE>(v2[i], tw, k * (N / (R1 * R2)));
         Dft<R2, INV>::run(v2[i]);
@@ -460,7 +485,7 @@ struct Fft3 {
     }
     stage_barrier<EARLY_TW>();
     if constexpr (AT == 2) {
-      if constexpr (EARLY_TW) settle_twiddles(w2, w3);
+      if constexpr (EARLY_TW) settle_twiddles(t.w2, t.w3);
       hook();
     }
     // stage 3 (Ns = R1 R2 = N / R3): j < Ns, so k = j and outputs land at j + q N/R3
@@ -472,8 +497,8 @@ struct Fft3 {
         const int p0 = lds_pad(j * C + s);
 #pragma unroll
         for (int r = 0; r < R3; ++r) v3[i][r] = lds[strided_pad<(N / R3) * C>(p0, j * C + s, r)];
-        if constexpr (EARLY_TW)
-          apply_twiddle_powers(v3[i], pinned(w3[EARLY_TW ? i : 0]));
+        if constexpr (GIVEN_TW)
+          apply_twiddle_powers(v3[i], pinned(t.w3[i]));
         else
           apply_twiddles<R3, TABLE>(v3[i], tw, j);
         Dft<R3, INV>::run(v3[i]);
