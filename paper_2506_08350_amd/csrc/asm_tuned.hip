@@ -304,6 +304,7 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
   const int lam = bl % g.n_lambda;
   const int b = threadIdx.x;
   const int s = b % C, j = b / C;
+  float qv[9];   // plane-independent transfer terms of this thread's 9 bins
   {
     cpx v1[1][16], v3[1][9];
     if (b < CT::Fwd::B1) {
@@ -313,6 +314,13 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
         const bool live = HALF ? r < 8 : n < g.H;
         v1[0][r] = live ? ldc(x1 + ((size_t)bl * g.H + n) * g.pW + c0 + s) : cpx{0.f, 0.f};
       }
+    }
+    // formed while the column loads are in flight
+    if (b < CT::Inv::B1) {
+      const HParam hp0 = load_hparam(g.hp, lam * g.K);
+      const ColFreq cf = col_freq(hp0, c0 + s, g);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) qv[q] = transfer_q(hp0, cf, j + q * (kColN / 9), g);
     }
     CT::Fwd::template run<CT::kLdsTw>(v1, v3, lds, twl);
     if (b < CT::Fwd::B3) {
@@ -324,13 +332,6 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
           spec[b + q * CT::Fwd::B3] = v3[0][q] * g.norm;
       }
     }
-  }
-  float qv[9];   // plane-independent transfer terms of this thread's 9 bins
-  if (b < CT::Inv::B1) {
-    const HParam hp0 = load_hparam(g.hp, lam * g.K);
-    const ColFreq cf = col_freq(hp0, c0 + s, g);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) qv[q] = transfer_q(hp0, cf, j + q * (kColN / 9), g);
   }
   // inverse-transform twiddles, the same for every plane: read once, so that
   // the plane loop issues no vector load that would wait on its stores
@@ -394,12 +395,6 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoi
   // plane-independent transfer terms of this thread's 9 bins, kept in LDS
   // (each thread reads back only its own entries) to spare registers
   __shared__ float s_q[9][CT::NT];
-  if (b < CT::Fwd::B3) {
-    const HParam hp0 = load_hparam(g.hp, lam * g.K);
-    const ColFreq cf = col_freq(hp0, c0 + s, g);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) s_q[q][b] = transfer_q(hp0, cf, j + q * (kColN / 9), g);
-  }
   // wave w copies rows 64 i .. 64 i + 63 for i = w, w + NT / 64, ...
   auto copy_plane = [&](int k) {
     if constexpr (kDma) {
@@ -418,10 +413,14 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoi
     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     __syncthreads();
   };
-  if constexpr (kDma) {
-    copy_plane(0);
-    copies_visible();
+  if constexpr (kDma) copy_plane(0);
+  if (b < CT::Fwd::B3) {
+    const HParam hp0 = load_hparam(g.hp, lam * g.K);
+    const ColFreq cf = col_freq(hp0, c0 + s, g);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s_q[q][b] = transfer_q(hp0, cf, j + q * (kColN / 9), g);
   }
+  if constexpr (kDma) copies_visible();   // the terms above were formed while plane 0 arrived
   for (int k = 0; k < g.K; ++k) {
     const float2* zk = z + ((size_t)bl * g.K + k) * g.H * g.pW + c0 + s;
     const int jj = opaque_v(j), kx = opaque_v(c0 + s);
