@@ -222,12 +222,14 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
           const float2 v = st.v[l][j];
-          dLda += G[p][l].x * (v.x - Bacc[p][l].x) + G[p][l].y * (v.y - Bacc[p][l].y);
+          // v - B serves dL/da and the update B <- a v + (1 - a) B = B + a (v - B)
+          const float ex = v.x - Bacc[p][l].x, ey = v.y - Bacc[p][l].y;
+          dLda += G[p][l].x * ex + G[p][l].y * ey;
           const float gx = aT * G[p][l].x, gy = aT * G[p][l].y;
           gr[6 + 2 * l] = PPT == 1 ? gx : gr[6 + 2 * l] + gx;
           gr[7 + 2 * l] = PPT == 1 ? gy : gr[7 + 2 * l] + gy;
-          Bacc[p][l].x = ae * v.x + (1.0f - ae) * Bacc[p][l].x;
-          Bacc[p][l].y = ae * v.y + (1.0f - ae) * Bacc[p][l].y;
+          Bacc[p][l].x += ae * ex;
+          Bacc[p][l].y += ae * ey;
         }
         T[p] = Tb;
         // clamped pixels pass no gradient to the opacity or the conic

@@ -287,8 +287,9 @@ __global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_bwd(RasterArgs a) 
               const float2 v = st.s.v[l][j];
               gr[6 + 2 * l] = aT * G[q][l].x;
               gr[7 + 2 * l] = aT * G[q][l].y;
-              Bacc[q][l].x = ae * v.x + (1.0f - ae) * Bacc[q][l].x;
-              Bacc[q][l].y = ae * v.y + (1.0f - ae) * Bacc[q][l].y;
+              // B <- a v + (1 - a) B as B + a (v - B), reusing v - B of dL/da
+              Bacc[q][l].x += ae * (v.x - Bacc[q][l].x);
+              Bacc[q][l].y += ae * (v.y - Bacc[q][l].y);
             }
             T[q] = Tb;
           } else {
