@@ -158,11 +158,14 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* __restrict
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Stable scatter of one pass.  Each block ranks its 16 x 256 keys (wave
-// ballots per round, counts of earlier waves and rounds in LDS), places them
-// in LDS in block-local digit order, then writes them out in that order: the
-// keys of one digit leave the block as one contiguous run, so the stores are
-// coalesced instead of one scattered 4-byte store per key.
+// Stable scatter of one pass.  Each wave ranks a contiguous quarter of the
+// block's 16 x 256 keys, 64 at a time in order, against its own running
+// digit counts in LDS (wave ballots group equal digits; no workgroup barrier
+// while ranking), then the waves' counts give each wave's start within every
+// digit.  The keys are placed in LDS in block-local digit order and written
+// out in that order: the keys of one digit leave the block as one contiguous
+// run, so the stores are coalesced instead of one scattered 4-byte store per
+// key.
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restrict__ keys_in,
                                                                 const uint32_t* __restrict__ vals_in,
@@ -171,27 +174,28 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
                                                                 const uint64_t* n_dev, int shift,
                                                                 const uint32_t* __restrict__ offsets, int nblocks) {
   constexpr int NW = kSortThreads / 64;
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t wcnt[NW][256];
+  constexpr int kWaveKeys = kSortItems * 64;   // keys ranked by one wave
+  __shared__ uint32_t wcnt[NW][256];           // per wave: running digit counts, then its start in each digit
   __shared__ uint32_t goff[256];
   __shared__ uint32_t lstart[256];
   __shared__ uint32_t wsum[NW];
   __shared__ K skey[kSortTile];
   __shared__ uint32_t sval[kSortTile];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t n = live_count(n_max, n_dev);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   if (base >= n) return;   // uniform per block
-  run[tid] = 0;
-  for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
+#pragma unroll
+  for (int i = lane; i < 256; i += 64) wcnt[wave][i] = 0;   // read back only by this wave until the barrier
   goff[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
-  __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   K key[kSortItems];
   uint32_t val[kSortItems], dig[kSortItems], rank[kSortItems];
+  const int64_t wbase = base + (int64_t)wave * kWaveKeys;
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const int64_t idx = base + (int64_t)r * kSortThreads + tid;
+    const int64_t idx = wbase + r * 64 + lane;
     const bool valid = idx < n;
     key[r] = 0;
     val[r] = 0;
@@ -210,28 +214,28 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
       peers &= on ? m : ~m;
     }
     const uint32_t lower = __popcll(peers & lt_mask);
-    if (valid && lower == 0) wcnt[wave][d] = __popcll(peers);
-    __syncthreads();
-    uint32_t before = 0;
-    for (int w = 0; w < wave; ++w) before += wcnt[w][d];
-    rank[r] = valid ? run[d] + before + lower : ~0u;   // rank among the block's keys of digit d
-    __syncthreads();
-    uint32_t add = 0;
-    for (int w = 0; w < NW; ++w) {
-      add += wcnt[w][tid];
-      wcnt[w][tid] = 0;
-    }
-    run[tid] += add;
-    __syncthreads();
+    // every lane reads the count before the group's first lane updates it
+    // (one wave's LDS operations complete in program order)
+    const uint32_t before = wcnt[wave][d];
+    rank[r] = valid ? before + lower : ~0u;   // rank among this wave's keys of digit d so far
+    if (valid && lower == 0) wcnt[wave][d] = before + (uint32_t)__popcll(peers);
   }
-  // block-local start of every digit
+  __syncthreads();
+  // digit tid: each wave's start among the block's keys of that digit
+  uint32_t total = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const uint32_t c = wcnt[w][tid];
+    wcnt[w][tid] = total;
+    total += c;
+  }
   uint32_t tot;
-  lstart[tid] = block_exclusive_scan<uint32_t>(run[tid], wsum, &tot);
+  lstart[tid] = block_exclusive_scan<uint32_t>(total, wsum, &tot);   // block-local start of every digit
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     if (rank[r] != ~0u) {
-      const uint32_t p = lstart[dig[r]] + rank[r];
+      const uint32_t p = lstart[dig[r]] + wcnt[wave][dig[r]] + rank[r];
       skey[p] = key[r];
       sval[p] = val[r];
     }
