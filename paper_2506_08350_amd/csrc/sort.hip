@@ -589,21 +589,50 @@ hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-__global__ void k_tile_ranges(const uint32_t* __restrict__ key, const uint64_t* total, int64_t capacity,
-                              uint2* __restrict__ ranges) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Tile ranges from the sorted pair keys: [first, one past last) of every
+// tile present.  Each thread takes four consecutive keys with one 16-byte
+// load (plus the keys just before and after them), in a grid-stride loop.
+constexpr int kRangeKeys = 4;
+constexpr int kRangeMaxBlocks = 2048;
+
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ key, const uint64_t* total,
+                                                     int64_t capacity, uint2* __restrict__ ranges) {
   const uint64_t t = *total;
   const int64_t n = t < (uint64_t)capacity ? (int64_t)t : capacity;
-  if (i >= n) return;
-  const uint32_t k = key[i];
-  if (i == 0 || key[i - 1] != k) ranges[k].x = (uint32_t)i;
-  if (i == n - 1 || key[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * kRangeKeys;
+  for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeKeys; i0 < n; i0 += stride) {
+    uint32_t k[kRangeKeys];
+    if (i0 + kRangeKeys <= n) {
+      const uint4 v = *reinterpret_cast<const uint4*>(key + i0);
+      k[0] = v.x;
+      k[1] = v.y;
+      k[2] = v.z;
+      k[3] = v.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < kRangeKeys; ++e) k[e] = i0 + e < n ? key[i0 + e] : 0u;
+    }
+    const bool has_prev = i0 > 0, has_next = i0 + kRangeKeys < n;
+    const uint32_t prev = has_prev ? key[i0 - 1] : 0u;
+    const uint32_t next = has_next ? key[i0 + kRangeKeys] : 0u;
+#pragma unroll
+    for (int e = 0; e < kRangeKeys; ++e) {
+      const int64_t i = i0 + e;
+      if (i >= n) break;
+      const bool first = e == 0 ? !has_prev || prev != k[0] : k[e - 1] != k[e];
+      const bool last = i + 1 == n || (e + 1 < kRangeKeys ? k[e + 1] != k[e] : next != k[e]);
+      if (first) ranges[k[e]].x = (uint32_t)i;
+      if (last) ranges[k[e]].y = (uint32_t)(i + 1);
+    }
+  }
 }
 
 hipError_t launch_tile_ranges(const uint32_t* pair_key, const uint64_t* total, int64_t capacity, uint2* ranges,
                               hipStream_t s) {
   if (capacity <= 0) return hipSuccess;
-  k_tile_ranges<<<(unsigned)((capacity + 255) / 256), 256, 0, s>>>(pair_key, total, capacity, ranges);
+  const int64_t per_block = 256 * kRangeKeys;
+  const int64_t blocks = std::min<int64_t>((capacity + per_block - 1) / per_block, kRangeMaxBlocks);
+  k_tile_ranges<<<(unsigned)blocks, 256, 0, s>>>(pair_key, total, capacity, ranges);
   return hipGetLastError();
 }
 
