@@ -102,6 +102,39 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const TIn* __restric
   }
 }
 
+// Down-sweep that forms its block offset itself, the sum of the block sums
+// before it (a block reduction over at most kScanFuseBlocks values), instead
+// of a separate single-block scan of the block sums; the last block also
+// writes the total.
+constexpr int kScanFuseBlocks = 1024;
+
+template <typename TIn, typename TOut>
+__global__ __launch_bounds__(kScanThreads) void k_scan_down_fused(const TIn* __restrict__ in, TOut* __restrict__ out,
+                                                                  int64_t n, const TOut* __restrict__ block_sums,
+                                                                  TOut* total) {
+  __shared__ TOut lw[kScanThreads / 64];
+  TOut pre = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanThreads) pre += block_sums[b];
+  TOut off;
+  block_exclusive_scan<TOut>(pre, lw, &off);   // off: the sum over all threads
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  TIn v[kScanItems];
+  TOut s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = base + i < n ? in[base + i] : 0;
+    s += (TOut)v[i];
+  }
+  TOut tot;
+  TOut run = block_exclusive_scan<TOut>(s, lw, &tot) + off;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += (TOut)v[i];
+  }
+  if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
+}
+
 int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
 template <typename T>
@@ -117,8 +150,12 @@ static hipError_t scan_impl(const TIn* in, TOut* out, int64_t n, TOut* tmp, TOut
   }
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   k_scan_reduce<TIn, TOut><<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, tmp);
-  k_scan_top<TOut><<<1, 1024, 0, s>>>(tmp, nb, total);
-  k_scan_down<TIn, TOut><<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, tmp);
+  if (nb <= kScanFuseBlocks) {
+    k_scan_down_fused<TIn, TOut><<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, tmp, total);
+  } else {
+    k_scan_top<TOut><<<1, 1024, 0, s>>>(tmp, nb, total);
+    k_scan_down<TIn, TOut><<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, tmp);
+  }
   return hipGetLastError();
 }
 
