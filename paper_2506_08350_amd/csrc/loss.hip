@@ -24,6 +24,8 @@ constexpr int kLT = 32;                 // output tile edge
 constexpr int kLR = 5;                  // window radius
 constexpr int kLE = kLT + 2 * kLR;      // staged edge
 constexpr int kLThreads = 256;
+constexpr int kLB = 4;                  // outputs per thread along a pass (register blocking)
+static_assert(kLThreads == kLT * (kLT / kLB), "one vertical-pass block of kLB rows per thread");
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
 
@@ -65,55 +67,78 @@ __global__ __launch_bounds__(kLThreads) void k_loss_fwd(const float* __restrict_
     sy[r][c] = ld_or0(y, lg.H, lg.W, lg.chan, r0 + r, c0 + c);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kLE * kLT; i += kLThreads) {
-    const int r = i / kLT, c = i % kLT;
-    float a = 0.f, b = 0.f, aa = 0.f, bb = 0.f, ab = 0.f;
+  // horizontal pass: item (row r, 4-column group) reads 14 staged values of
+  // each image once for its 4 outputs of the five products
+  for (int i = threadIdx.x; i < kLE * (kLT / kLB); i += kLThreads) {
+    const int r = i / (kLT / kLB), cb = (i % (kLT / kLB)) * kLB;
+    float acc[kLB][5] = {};
 #pragma unroll
-    for (int k = 0; k <= 2 * kLR; ++k) {
-      const float u = sx[r][c + k], v = sy[r][c + k], w = lg.g[k];
-      a += w * u;
-      b += w * v;
-      aa += w * u * u;
-      bb += w * v * v;
-      ab += w * u * v;
+    for (int k = 0; k < kLB + 2 * kLR; ++k) {
+      const float u = sx[r][cb + k], v = sy[r][cb + k];
+      const float uu = u * u, vv = v * v, uv = u * v;
+#pragma unroll
+      for (int o = 0; o < kLB; ++o) {
+        const int tap = k - o;
+        if (tap < 0 || tap > 2 * kLR) continue;
+        const float w = lg.g[tap];
+        acc[o][0] += w * u;
+        acc[o][1] += w * v;
+        acc[o][2] += w * uu;
+        acc[o][3] += w * vv;
+        acc[o][4] += w * uv;
+      }
     }
-    hs[0][r][c] = a;
-    hs[1][r][c] = b;
-    hs[2][r][c] = aa;
-    hs[3][r][c] = bb;
-    hs[4][r][c] = ab;
+#pragma unroll
+    for (int o = 0; o < kLB; ++o)
+#pragma unroll
+      for (int q = 0; q < 5; ++q) hs[q][r][cb + o] = acc[o][q];
   }
   __syncthreads();
   const uint8_t* mk = masks ? masks + ((size_t)(img / lg.per_view) * lg.planes + img % lg.planes) * lg.H * lg.W
                             : nullptr;
   float s_sum = 0.f, r_sum = 0.f;
-  for (int i = threadIdx.x; i < kLT * kLT; i += kLThreads) {
-    const int r = i / kLT, c = i % kLT;
-    const int gr = ty * kLT + r, gc = tx * kLT + c;
-    if (gr >= lg.H || gc >= lg.W) continue;
-    float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  // vertical pass: thread (column c, row group) forms the window averages of
+  // kLB consecutive output rows from 14 staged rows
+  {
+    const int c = threadIdx.x % kLT, r0o = (threadIdx.x / kLT) * kLB;
+    float m[kLB][5] = {};
 #pragma unroll
-    for (int k = 0; k <= 2 * kLR; ++k) {
-      const float w = lg.g[k];
+    for (int k = 0; k < kLB + 2 * kLR; ++k) {
+      float h[5];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) m[q] += w * hs[q][r + k][c];
+      for (int q = 0; q < 5; ++q) h[q] = hs[q][r0o + k][c];
+#pragma unroll
+      for (int o = 0; o < kLB; ++o) {
+        const int tap = k - o;
+        if (tap < 0 || tap > 2 * kLR) continue;
+        const float w = lg.g[tap];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) m[o][q] += w * h[q];
+      }
     }
-    const float mx = m[0], my = m[1];
-    const float a1 = 2.f * mx * my + kC1;
-    const float a2 = 2.f * (m[4] - mx * my) + kC2;
-    const float b1 = mx * mx + my * my + kC1;
-    const float b2 = (m[2] - mx * mx) + (m[3] - my * my) + kC2;
-    const float inv = 1.0f / (b1 * b2);
-    const float S = a1 * a2 * inv;
-    const size_t o = (size_t)img * lg.H * lg.W + (size_t)gr * lg.W + gc;   // maps are dense per image
-    dmu[o] = (2.f * my * a2 - 2.f * my * a1) * inv - S * (2.f * mx / b1 - 2.f * mx / b2);
-    dexx[o] = -S / b2;
-    dexy[o] = 2.f * a1 * inv;
-    s_sum += S;
-    const float xv = sx[r + kLR][c + kLR], yv = sy[r + kLR][c + kLR];
-    const float d = xv - yv;
-    const float mval = mk ? (float)mk[(size_t)gr * lg.W + gc] : 0.f;
-    r_sum += lg.recon ? d * d * (1.f + mval + yv * yv) : d * d;
+#pragma unroll
+    for (int o = 0; o < kLB; ++o) {
+      const int r = r0o + o;
+      const int gr = ty * kLT + r, gc = tx * kLT + c;
+      if (gr >= lg.H || gc >= lg.W) continue;
+      const float mx = m[o][0], my = m[o][1];
+      const float a1 = 2.f * mx * my + kC1;
+      const float a2 = 2.f * (m[o][4] - mx * my) + kC2;
+      const float b1 = mx * mx + my * my + kC1;
+      const float b2 = (m[o][2] - mx * mx) + (m[o][3] - my * my) + kC2;
+      // one division: 1/b1 = b2 inv, 1/b2 = b1 inv
+      const float inv = 1.0f / (b1 * b2);
+      const float S = a1 * a2 * inv;
+      const size_t oi = (size_t)img * lg.H * lg.W + (size_t)gr * lg.W + gc;   // maps are dense per image
+      dmu[oi] = (2.f * my * a2 - 2.f * my * a1) * inv - S * 2.f * mx * (b2 - b1) * inv;
+      dexx[oi] = -S * b1 * inv;
+      dexy[oi] = 2.f * a1 * inv;
+      s_sum += S;
+      const float xv = sx[r + kLR][c + kLR], yv = sy[r + kLR][c + kLR];
+      const float d = xv - yv;
+      const float mval = mk ? (float)mk[(size_t)gr * lg.W + gc] : 0.f;
+      r_sum += lg.recon ? d * d * (1.f + mval + yv * yv) : d * d;
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     s_sum += __shfl_xor(s_sum, off, 64);
@@ -156,42 +181,58 @@ __global__ __launch_bounds__(kLThreads) void k_loss_bwd(const float* __restrict_
     sd[2][r][c] = ld_or0(dexy + mbase, lg.H, lg.W, 1, r0 + r, c0 + c);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kLE * kLT; i += kLThreads) {
-    const int r = i / kLT, c = i % kLT;
-    float a = 0.f, b = 0.f, e = 0.f;
+  for (int i = threadIdx.x; i < kLE * (kLT / kLB); i += kLThreads) {
+    const int r = i / (kLT / kLB), cb = (i % (kLT / kLB)) * kLB;
+    float acc[kLB][3] = {};
 #pragma unroll
-    for (int k = 0; k <= 2 * kLR; ++k) {
-      const float w = lg.g[k];
-      a += w * sd[0][r][c + k];
-      b += w * sd[1][r][c + k];
-      e += w * sd[2][r][c + k];
+    for (int k = 0; k < kLB + 2 * kLR; ++k) {
+      float h[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) h[q] = sd[q][r][cb + k];
+#pragma unroll
+      for (int o = 0; o < kLB; ++o) {
+        const int tap = k - o;
+        if (tap < 0 || tap > 2 * kLR) continue;
+        const float w = lg.g[tap];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[o][q] += w * h[q];
+      }
     }
-    hs[0][r][c] = a;
-    hs[1][r][c] = b;
-    hs[2][r][c] = e;
+#pragma unroll
+    for (int o = 0; o < kLB; ++o)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) hs[q][r][cb + o] = acc[o][q];
   }
   __syncthreads();
   const float scale = grad_scale ? *grad_scale : 1.0f;
   const uint8_t* mk = masks ? masks + ((size_t)(img / lg.per_view) * lg.planes + img % lg.planes) * lg.H * lg.W
                             : nullptr;
-  for (int i = threadIdx.x; i < kLT * kLT; i += kLThreads) {
-    const int r = i / kLT, c = i % kLT;
-    const int gr = ty * kLT + r, gc = tx * kLT + c;
-    if (gr >= lg.H || gc >= lg.W) continue;
-    float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+  const int c = threadIdx.x % kLT, r0o = (threadIdx.x / kLT) * kLB;
+  float f[kLB][3] = {};
 #pragma unroll
-    for (int k = 0; k <= 2 * kLR; ++k) {
-      const float w = lg.g[k];
-      f0 += w * hs[0][r + k][c];
-      f1 += w * hs[1][r + k][c];
-      f2 += w * hs[2][r + k][c];
+  for (int k = 0; k < kLB + 2 * kLR; ++k) {
+    float h[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) h[q] = hs[q][r0o + k][c];
+#pragma unroll
+    for (int o = 0; o < kLB; ++o) {
+      const int tap = k - o;
+      if (tap < 0 || tap > 2 * kLR) continue;
+      const float w = lg.g[tap];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) f[o][q] += w * h[q];
     }
-    const size_t o = base + ((size_t)gr * lg.W + gc) * lg.chan;
-    const float xv = I[o], yv = T[o];
+  }
+#pragma unroll
+  for (int o = 0; o < kLB; ++o) {
+    const int gr = ty * kLT + r0o + o, gc = tx * kLT + c;
+    if (gr >= lg.H || gc >= lg.W) continue;
+    const size_t oi = base + ((size_t)gr * lg.W + gc) * lg.chan;
+    const float xv = I[oi], yv = T[oi];
     const float mval = mk ? (float)mk[(size_t)gr * lg.W + gc] : 0.f;
-    const float g_ssim = ssim_coef * (f0 + 2.f * xv * f1 + yv * f2);
+    const float g_ssim = ssim_coef * (f[o][0] + 2.f * xv * f[o][1] + yv * f[o][2]);
     const float g_rec = recon_coef * (xv - yv) * (lg.recon ? 1.f + mval + yv * yv : 1.f);
-    dL_dI[o] = scale * (g_ssim + g_rec);
+    dL_dI[oi] = scale * (g_ssim + g_rec);
   }
 }
 
