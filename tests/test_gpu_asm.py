@@ -144,3 +144,35 @@ def test_wide_rows_propagation_and_fused_loss(W):
         describe_partials(r, to_device(make_gaussians(0, 1, 9)), api.pack_cameras([cam]), tgt, 2 * H)
     assert torch.allclose(part, rows, rtol=1e-5), (part[:4].tolist(), rows[:4].tolist())
     assert abs(float(out["loss"]) - float((tgt.double() ** 2).mean())) < 1e-5
+
+
+@pytest.mark.parametrize("views,zs", [
+    (1, (1e-3,)),                                                  # one plane: no copy in flight
+    (2, (0.4e-3, 0.9e-3, 1.3e-3, 1.7e-3, 2.2e-3, 2.6e-3, 3e-3)),   # seven planes, two views
+])
+def test_full_size_plane_counts_and_views(views, zs):
+    """At 1080 x 1920 with two columns per workgroup the adjoint copies each
+    plane's input into LDS while the previous plane's transform runs, and
+    the plane parameters are read by scalar loads: one plane, seven planes,
+    and two views (group indexing across views).  Sampled planes of the
+    propagation and the full adjoint of the last view against the oracle."""
+    announce(f"propagate 1080x1920, {views} views, {len(zs)} planes")
+    H, W = 1080, 1920
+    lam, K = 515e-9, len(zs)
+    opt = Optics((lam,), zs, 8e-6, 2, 2)
+    r = make_renderer([identity_camera(W, H)] * views, opt, 1, cols_per_block=2)
+    rng = np.random.default_rng(9)
+    U = rng.uniform(0, 1, (views, 1, H, W)) * np.exp(2j * np.pi * rng.uniform(0, 1, (views, 1, H, W)))
+    prop, _ = r.propagate(_to_gpu(U), want_intensity=False)
+    torch.cuda.synchronize()
+    for v, k in {(0, 0), (views - 1, K - 1)}:
+        ref = oracle.propagate(U[v, 0], lam, zs[k], 8e-6, 2, 2)
+        assert rel_l2(cplx(prop[v, 0, k]), ref) < TOL, (v, k)
+    del prop
+    G = rng.normal(size=(views, 1, K, H, W)).astype(np.float32) + 1j * rng.normal(size=(views, 1, K, H, W)).astype(
+        np.float32)
+    back = r.propagate_adjoint(torch.from_numpy(np.stack([G.real, G.imag], -1)).cuda())
+    torch.cuda.synchronize()
+    v = views - 1
+    ref = sum(oracle.propagate_adjoint(G[v, 0, k].astype(np.complex128), lam, zs[k], 8e-6, 2, 2) for k in range(K))
+    assert rel_l2(cplx(back[v, 0]), ref) < TOL
