@@ -7,6 +7,7 @@ wires chrf_backward into torch.autograd.
 from __future__ import annotations
 
 import ctypes as C
+import gc
 import math
 from dataclasses import dataclass
 
@@ -514,8 +515,17 @@ class CapturedTrainStep:
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.graph):
-            self.loss, self.grads, _ = renderer.train_step(params, cams, target, masks=masks)
+        # No cyclic garbage collection during the capture: a collected plan
+        # frees device memory, which a capture in progress does not allow.
+        gc.collect()
+        was_enabled = gc.isenabled()
+        gc.disable()
+        try:
+            with torch.cuda.graph(self.graph):
+                self.loss, self.grads, _ = renderer.train_step(params, cams, target, masks=masks)
+        finally:
+            if was_enabled:
+                gc.enable()
 
     def replay(self):
         self.graph.replay()
