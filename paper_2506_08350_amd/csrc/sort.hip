@@ -185,11 +185,42 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* __restrict
   const int64_t n = live_count(n_max, n_dev);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   if (base < n) {
-#pragma unroll 4
-    for (int i = 0; i < kSortItems; ++i) {
-      const int64_t idx = base + i * kSortThreads + threadIdx.x;
-      if (idx < n) atomicAdd(&cnt[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+    // each thread counts kSortItems consecutive keys and adds every run of
+    // equal digits with one atomic: sorted-by-depth pairs carry long runs in
+    // their high tile digits, which would otherwise pile atomics on one counter
+    const int64_t t0 = base + (int64_t)threadIdx.x * kSortItems;
+    K k[kSortItems];
+    if constexpr (sizeof(K) == 4) {
+      if (t0 + kSortItems <= n) {
+#pragma unroll
+        for (int i = 0; i < kSortItems; i += 4) {
+          const uint4 v = *reinterpret_cast<const uint4*>(keys + t0 + i);
+          k[i] = v.x;
+          k[i + 1] = v.y;
+          k[i + 2] = v.z;
+          k[i + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) k[i] = t0 + i < n ? keys[t0 + i] : K(0);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kSortItems; ++i) k[i] = t0 + i < n ? keys[t0 + i] : K(0);
     }
+    uint32_t run_d = 0, run_c = 0;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+      if (t0 + i >= n) break;
+      const uint32_t d = (uint32_t)(k[i] >> shift) & 255u;
+      if (run_c != 0 && d != run_d) {
+        atomicAdd(&cnt[run_d], run_c);
+        run_c = 0;
+      }
+      run_d = d;
+      ++run_c;
+    }
+    if (run_c != 0) atomicAdd(&cnt[run_d], run_c);
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
