@@ -168,8 +168,10 @@ __global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_fwd(RasterArgs a) 
   a.last[(size_t)t.view * plane + pix] = walk_end;
 }
 
+// At least four waves per SIMD (a 128-VGPR budget): the per-layer state of
+// four layers alone needs 143 registers unconstrained, three waves per SIMD.
 template <int NL, int NLAY, int NWAVE>
-__global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_bwd(RasterArgs a) {
+__global__ __launch_bounds__(64 * NWAVE, 4) void k_raster_layers_bwd(RasterArgs a) {
   constexpr int G2 = 6 + 2 * NL + NLAY;
   constexpr int G2P = (G2 + 3) & ~3;
   __shared__ StageL<NL> st;
