@@ -82,8 +82,10 @@ __device__ inline void layer_pixel(const RasterArgs& a, const TileGeom& t, int& 
   py = by + (lane >> 3);
 }
 
+// Eight waves per SIMD (a 64-VGPR budget, met without spills): the walk is
+// latency-bound, so more resident waves hide more of it.
 template <int NL, int NLAY, int NWAVE>
-__global__ __launch_bounds__(64 * NWAVE) void k_raster_layers_fwd(RasterArgs a) {
+__global__ __launch_bounds__(64 * NWAVE, 8) void k_raster_layers_fwd(RasterArgs a) {
   __shared__ StageL<NL> st;
   const TileGeom t = tile_of(a);
   int px, py, bx, by;
