@@ -26,8 +26,9 @@ u_k = ASM(P; -Z_k), I_k = |u_k|^2.  ASM is ``asm.propagate`` (pad, transfer
 function, crop to the layer grid).
 
 Backward.  Per layer the reverse-order replay of raster.py with that layer's
-T, accumulated field B_l and loss gradient G_l.  With w = rho_{n,l} and T_l
-the transmittance of layer l in front of n,
+T (taken, as in raster.py, from a forward replay that keeps the transmittance
+in front of every Gaussian), accumulated field B_l and loss gradient G_l.
+With w = rho_{n,l} and T_l the transmittance of layer l in front of n,
 
     dL/drho_{n,l} = a_n T_l sum_lambda Re(conj(G_l) (v_n - B_l))
 
@@ -108,6 +109,26 @@ def render_layers(proj, opacity, footprint, weights, width, height, thr=DEFAULT,
     return LayerRaster(U, T, stop, order)
 
 
+def layer_transmittance_in_front(proj, opacity, footprint, weights, res: LayerRaster, thr=DEFAULT, window=None):
+    """Per layer, the transmittance in front of every Gaussian over its support
+    rectangle, by replaying each layer's front-to-back product up to the
+    position where the layer stopped: {order position: [layers, rows, cols]}."""
+    w_all = np.asarray(weights, np.float64)
+    nl = w_all.shape[1]
+    T = np.ones_like(res.T_final)
+    out = {}
+    for pos, g in enumerate(res.order):
+        sp = _support(g, proj, opacity, footprint["rect"], thr, window)
+        if sp is None:
+            continue
+        sl, _, _, _, _, a, _, sup = sp
+        out[pos] = np.stack([T[l][sl] for l in range(nl)])
+        for l in range(nl):
+            live = sup & (pos <= res.stop[l][sl])
+            T[l][sl] = np.where(live, T[l][sl] * (1.0 - w_all[g, l] * a), T[l][sl])
+    return out
+
+
 def render_layers_backward(proj, opacity, footprint, weights, res: LayerRaster, G_layers, thr=DEFAULT,
                            window=None):
     """Reverse replay of every layer.  G_layers [layers, wavelengths, H, W]
@@ -121,8 +142,8 @@ def render_layers_backward(proj, opacity, footprint, weights, res: LayerRaster, 
     d_op = np.zeros(N)
     d_v = np.zeros((N, lam), np.complex128)
     d_rho = np.zeros((N, nl))
-    T = res.T_final.copy()
-    Bacc = np.zeros((nl, lam) + T.shape[1:], np.complex128)
+    T_front = layer_transmittance_in_front(proj, opacity, footprint, w_all, res, thr, window)
+    Bacc = np.zeros((nl, lam) + res.T_final.shape[1:], np.complex128)
     for pos in range(len(res.order) - 1, -1, -1):
         g = res.order[pos]
         sp = _support(g, proj, opacity, footprint["rect"], thr, window)
@@ -136,7 +157,7 @@ def render_layers_backward(proj, opacity, footprint, weights, res: LayerRaster, 
             if not live.any():
                 continue
             w = w_all[g, l]
-            Tb = np.where(live, T[l][sl] / (1.0 - w * a), T[l][sl])
+            Tb = np.where(live, T_front[pos][l], 0.0)
             Gs = G_layers[(l, slice(None)) + sl]
             Bs = Bacc[(l, slice(None)) + sl]
             s = np.where(live, Tb * np.sum((np.conj(Gs) * (v - Bs)).real, axis=0), 0.0)
@@ -144,7 +165,6 @@ def render_layers_backward(proj, opacity, footprint, weights, res: LayerRaster, 
             dLda += w * s
             d_v[g] += np.sum(np.where(live[None], w * a * Tb * Gs, 0.0), axis=(1, 2))
             Bacc[(l, slice(None)) + sl] = np.where(live[None], w * a * v + (1.0 - w * a) * Bs, Bs)
-            T[l][sl] = Tb
         free = sup & ~clamped
         d_op[g] += np.sum(np.where(free, G * dLda, 0.0))
         dpow = np.where(free, -a * dLda, 0.0)

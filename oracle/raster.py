@@ -19,8 +19,10 @@ Gaussians in the global sorted order gives every pixel the same sequence as a
 per-pixel loop.
 
 Backward (Supplementary D backward pass and Sec. 4.2): reverse order from each
-pixel's last contributor; the transmittance before g is recovered as
-T_after / (1 - a_g), and with B the field accumulated behind g,
+pixel's last contributor.  T_g, the transmittance in front of g, is taken from
+a forward replay that keeps it for every included (pixel, Gaussian) pair (the
+GPU recovers it by dividing by 1 - a_g instead; the oracle does not mirror
+that), and with B the field accumulated behind g,
 
     dL/da_g = T_g * sum_l Re(conj(G_l) (v_{g,l} - B_l)),
     B_l    <- a_g v_{g,l} + (1 - a_g) B_l,
@@ -102,6 +104,25 @@ def render_field(proj, opacity, footprint, width, height, thr, window=None) -> R
     return RasterResult(U, T, last, order, ncon)
 
 
+def transmittance_in_front(proj, opacity, footprint, res: RasterResult, thr, window=None):
+    """T in front of every included (pixel, Gaussian) pair, by replaying the
+    front-to-back product: {order position: T over that Gaussian's support
+    rectangle (clipped to ``window``), meaningful where it was included}."""
+    T = np.ones_like(res.T_final)
+    out = {}
+    for pos, g in enumerate(res.order):
+        sp = _support(g, proj, opacity, footprint["rect"], thr, window)
+        if sp is None:
+            continue
+        sl, _, _, _, _, a, _, sup = sp
+        inc = sup & (pos <= res.last[sl])
+        if not inc.any():
+            continue
+        out[pos] = T[sl].copy()
+        T[sl] = np.where(inc, T[sl] * (1.0 - a), T[sl])
+    return out
+
+
 def render_field_backward(proj, opacity, footprint, res: RasterResult, G_U, thr, window=None):
     """Per-Gaussian 2D gradients for one view (over ``window`` only, if given).
 
@@ -113,26 +134,27 @@ def render_field_backward(proj, opacity, footprint, res: RasterResult, G_U, thr,
     d_conic = np.zeros((N, 3))
     d_op = np.zeros(N)
     d_v = np.zeros((N, L), np.complex128)
-    T = res.T_final.copy()
     Bacc = np.zeros_like(G_U)
     rect = footprint["rect"]
+    T_front = transmittance_in_front(proj, opacity, footprint, res, thr, window)
     for pos in range(len(res.order) - 1, -1, -1):
         g = res.order[pos]
         sp = _support(g, proj, opacity, rect, thr, window)
         if sp is None:
             continue
         sl, dx, dy, power, G, a, clamped, sup = sp
+        # included: supported and not behind the pixel's last contributor
+        # (the Gaussian that crossed T_min is itself included)
         inc = sup & (pos <= res.last[sl])
         if not inc.any():
             continue
-        Tg = np.where(inc, T[sl] / (1.0 - a), T[sl])
+        Tg = np.where(inc, T_front[pos], 0.0)
         Gs = G_U[(slice(None),) + sl]
         Bs = Bacc[(slice(None),) + sl]
         v = proj.v[g][:, None, None]
         dLda = np.where(inc, Tg * np.sum((np.conj(Gs) * (v - Bs)).real, axis=0), 0.0)
         d_v[g] += np.sum(np.where(inc[None], a * Tg * Gs, 0.0), axis=(1, 2))
         Bacc[(slice(None),) + sl] = np.where(inc[None], a * v + (1.0 - a) * Bs, Bs)
-        T[sl] = Tg
         free = inc & ~clamped
         d_op[g] += np.sum(np.where(free, G * dLda, 0.0))
         dpow = np.where(free, -a * dLda, 0.0)

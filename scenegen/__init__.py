@@ -95,14 +95,18 @@ class Workload:
 
 
 def make_gaussians(n, n_lambda, seed, *, x_range=(-0.5, 0.5), y_range=(-0.5, 0.5),
-                   z_range=(1.0, 3.0), log_scale_mean=-4.0, log_scale_std=0.5) -> Scene:
+                   z_range=(1.0, 3.0), log_scale_mean=-4.0, log_scale_std=0.5, opacity_logit_mean=0.0,
+                   opacity_logit_std=1.0) -> Scene:
+    """opacity = sigmoid(N(opacity_logit_mean, opacity_logit_std)); a large mean
+    draws the near-opaque Gaussians of the learned fields (Supplementary F),
+    whose alpha clamps at alpha_max and whose stacks end pixel walks early."""
     rng = np.random.default_rng(seed)
     means = np.stack([
         rng.uniform(*x_range, n), rng.uniform(*y_range, n), rng.uniform(*z_range, n)
     ], axis=1)
     log_scales = rng.normal(log_scale_mean, log_scale_std, (n, 3))
     quats = rng.normal(0.0, 1.0, (n, 4))          # uniform rotation once normalised
-    opacity = 1.0 / (1.0 + np.exp(-rng.normal(0.0, 1.0, n)))
+    opacity = 1.0 / (1.0 + np.exp(-rng.normal(opacity_logit_mean, opacity_logit_std, n)))
     amp = rng.uniform(0.0, 1.0, (n, n_lambda))
     phase = rng.uniform(0.0, 2.0 * math.pi, (n, n_lambda))
     f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)

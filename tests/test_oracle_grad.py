@@ -16,6 +16,7 @@ import torch
 import oracle
 from oracle import binning
 from scenegen import Optics, Scene, identity_camera, make_gaussians, make_targets, yaw_cameras
+from tests import dense_reference as dense
 
 
 
@@ -76,60 +77,16 @@ def test_gradient_matches_central_differences():
 
 
 def _torch_dense_loss(params, sc, cams, opt, tg, thr):
-    """Independent dense formulation: every pixel against every Gaussian."""
-    means, log_scales, quats, opacity, amp, phase = params
+    """Independent dense formulation: every pixel against every Gaussian,
+    with the early stop of Algorithm 2 as a fixed mask."""
     total = 0.0
     n_el = 0
     for b, cam in enumerate(cams):
-        fp = binning.fp32_footprint(sc.means, sc.log_scales, sc.quats, cam, k_sigma=thr.k_sigma)
-        vis = torch.as_tensor(fp["visible"])
-        order = np.lexsort((np.arange(sc.n), fp["key"].astype(np.int64)))
-        q = quats / torch.linalg.norm(quats, dim=1, keepdim=True)
-        w, x, y, z = q.unbind(1)
-        R = torch.stack([
-            torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
-            torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
-            torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1),
-        ], 1)
-        S = torch.diag_embed(torch.exp(log_scales))
-        RS = R @ S
-        Sigma = RS @ RS.transpose(1, 2)
-        Wc = torch.as_tensor(np.asarray(cam.R, np.float64))
-        tcam = means @ Wc.T + torch.as_tensor(np.asarray(cam.t, np.float64))
-        fx, fy = float(np.float32(cam.fx)), float(np.float32(cam.fy))
-        cx, cy = float(np.float32(cam.cx)), float(np.float32(cam.cy))
-        tx, ty, tz = tcam.unbind(1)
-        zero = torch.zeros_like(tz)
-        J = torch.stack([torch.stack([fx / tz, zero, -fx * tx / tz ** 2], -1),
-                         torch.stack([zero, fy / tz, -fy * ty / tz ** 2], -1)], 1)
-        JW = J @ Wc
-        cov = JW @ Sigma @ JW.transpose(1, 2)
-        conic = torch.linalg.inv(cov)
-        mu = torch.stack([fx * tx / tz + cx, fy * ty / tz + cy], -1)
-        H, Wd = cam.height, cam.width
-        py, px = torch.meshgrid(torch.arange(H) + 0.5, torch.arange(Wd) + 0.5, indexing="ij")
-        pix = torch.stack([px.reshape(-1), py.reshape(-1)], -1)
-        d = pix[:, None, :] - mu[None]
-        power = 0.5 * torch.einsum("pgi,gij,pgj->pg", d, conic, d)
-        rect = torch.as_tensor(fp["rect"])
-        inrect = ((pix[:, None, 0] >= rect[None, :, 0] + 0.5) & (pix[:, None, 0] <= rect[None, :, 1] + 0.5)
-                  & (pix[:, None, 1] >= rect[None, :, 2] + 0.5) & (pix[:, None, 1] <= rect[None, :, 3] + 0.5))
-        oG = opacity[None] * torch.exp(-power)
-        a = torch.where(oG > thr.alpha_max, torch.full_like(oG, thr.alpha_max), oG)
-        sup = inrect & vis[None] & (power <= 0.5 * thr.k_sigma ** 2) & (a >= thr.alpha_min)
-        a = torch.where(sup, a, torch.zeros_like(a))
-        a = a[:, order]
-        T = torch.cumprod(torch.cat([torch.ones_like(a[:, :1]), 1 - a[:, :-1]], 1), 1)
-        v = torch.polar(amp, phase)[order]                      # [G, L]
-        U = torch.einsum("pg,gl->lp", (a * T).to(v.dtype), v).reshape(-1, H, Wd)
+        a, v, _, H, Wd = dense.dense_alpha(params, sc, cam, thr)
+        U = dense.composite(a, v, thr.t_min, H, Wd)
         for li, lam in enumerate(opt.wavelengths):
-            P = torch.zeros((2 * H, 2 * Wd), dtype=U.dtype)
-            P[:H, :Wd] = U[li]
-            fy_ = torch.fft.fftfreq(2 * H, d=opt.pitch)[:, None]
-            fx_ = torch.fft.fftfreq(2 * Wd, d=opt.pitch)[None, :]
             for ki, zz in enumerate(opt.distances):
-                Hz = torch.as_tensor(oracle.transfer_function(2 * H, 2 * Wd, opt.pitch, lam, zz, opt.band_limit))
-                u = torch.fft.ifft2(Hz * torch.fft.fft2(P))[:H, :Wd]
+                u = dense.asm(U[li], lam, zz, opt.pitch, opt.band_limit)
                 I = u.real ** 2 + u.imag ** 2
                 total = total + torch.sum((I - torch.as_tensor(tg[b, li, ki], dtype=torch.float64)) ** 2)
                 n_el += I.numel()
@@ -183,3 +140,70 @@ def test_amplitude_and_phase_formulas_single_gaussian():
     dphi = np.sum(aT * c * (-math.sin(ph) * G[0].real + math.cos(ph) * G[0].imag))
     assert abs(g["amp"][0, 0] - dc) < 1e-12 * max(1, abs(dc))
     assert abs(g["phase"][0, 0] - dphi) < 1e-12 * max(1, abs(dphi))
+
+
+def _saturated_problem(seed=31):
+    """Dense near-opaque Gaussians: most pixel walks end early (T < T_min)
+    and a fifth of the Gaussians clamp at alpha_max somewhere."""
+    sc = make_gaussians(80, 2, seed, x_range=(-0.25, 0.25), y_range=(-0.25, 0.25), log_scale_mean=-1.8,
+                        log_scale_std=0.3, opacity_logit_mean=3.5, opacity_logit_std=1.5)
+    sc = Scene(*(a.astype(np.float64) for a in sc.arrays()))
+    cams = yaw_cameras((0.0, 8.0), (0.0, 0.0, 2.0), 40, 32, f=64)
+    opt = Optics((639e-9, 473e-9), (0.5e-3, 1.5e-3), 8e-6, 2, 2)
+    tg = make_targets((2, 2, 2, 32, 40), seed + 1)
+    return sc, cams, opt, tg
+
+
+def test_gradient_with_early_termination_and_clamp_matches_dense_autograd():
+    """Default thresholds on a saturated scene: the backward replay from each
+    pixel's last contributor (Sec. 4.2), the crossing Gaussian included
+    (Algorithm 2's stop after T < T_min), and the zero gradient of clamped
+    alphas, against the dense formulation whose stop mask comes from its own
+    cumulative product."""
+    sc, cams, opt, tg = _saturated_problem()
+    thr = oracle.DEFAULT
+    st = oracle.forward(sc, cams, opt, thr, targets=tg)
+    params = [torch.tensor(a, requires_grad=True) for a in sc.arrays()]
+    for v, cam in zip(st["views"], cams):
+        assert np.mean(v["res"].T_final < thr.t_min) >= 0.5
+        with torch.no_grad():
+            a, _, _, _, _ = dense.dense_alpha(params, sc, cam, thr)
+        assert dense.stop_fraction(a, thr.t_min) >= 0.5
+        assert float((a >= thr.alpha_max).any(0).double().mean()) >= 0.1   # clamped Gaussians
+    grads = oracle.backward(st)
+    loss = _torch_dense_loss(params, sc, cams, opt, tg, thr)
+    assert abs(loss.item() - st["loss"]) < 1e-12 * abs(st["loss"])
+    loss.backward()
+    for name, p in zip(("means", "log_scales", "quats", "opacity", "amp", "phase"), params):
+        ref = p.grad.numpy()
+        err = np.linalg.norm(grads[name] - ref) / np.linalg.norm(ref)
+        assert err < 1e-9, (name, err)
+
+
+def test_dense_pin_detects_a_dropped_crossing_gaussian():
+    """The pin above is sensitive to the cut: a replay that stops one
+    contributor early at every terminated pixel (the crossing Gaussian
+    dropped) is far outside its tolerance."""
+    sc, cams, opt, tg = _saturated_problem()
+    thr = oracle.DEFAULT
+    st = oracle.forward(sc, cams, opt, thr, targets=tg)
+    ref = oracle.backward(st)
+    for v in st["views"]:
+        res = v["res"]
+        done = res.T_final < thr.t_min
+        last = res.last.copy()
+        for r, c in zip(*np.nonzero(done)):
+            # the previous included position of this pixel
+            prev = [pos for pos in range(last[r, c]) if _includes(v, sc, thr, pos, r, c)]
+            last[r, c] = prev[-1] if prev else -1
+        v["res"] = oracle.RasterResult(res.U, res.T_final, last, res.order, res.n_contrib)
+    bad = oracle.backward(st)
+    worst = max(np.linalg.norm(bad[k] - ref[k]) / np.linalg.norm(ref[k]) for k in ref)
+    assert worst > 1e-4
+
+
+def _includes(view, sc, thr, pos, r, c):
+    from oracle import raster
+    g = view["res"].order[pos]
+    sp = raster._support(g, view["proj"], sc.opacity, view["fp"]["rect"], thr, (r, r + 1, c, c + 1))
+    return sp is not None and bool(sp[-1].any())

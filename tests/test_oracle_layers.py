@@ -202,3 +202,60 @@ def test_hard_assignment_and_straight_through_weights():
     st = layers.forward_layers(sc, lg, cams[:1], opt, oracle.DEFAULT, targets=tg[:1])
     g = layers.backward_layers(st)
     assert np.allclose(g["logits"], g["rho"] * layers.ste_softmax(lg))
+
+
+def test_layer_gradients_with_termination_match_dense_autograd():
+    """Default thresholds, three layers of dense near-opaque Gaussians (about
+    half the pixels end each layer's walk early; some alphas clamp): the
+    oracle's per-layer reverse replay against a dense torch formulation of
+    Eqs. 13-16 whose per-layer stop masks come from its own cumulative
+    products, differentiated by autograd w.r.t. the Gaussian parameters and
+    the assignment weights rho at the one-hot point."""
+    import torch
+
+    from tests import dense_reference as dense
+
+    old = torch.get_default_dtype()
+    torch.set_default_dtype(torch.float64)
+    try:
+        sc = make_gaussians(160, 2, 35, x_range=(-0.25, 0.25), y_range=(-0.25, 0.25), log_scale_mean=-1.8,
+                            log_scale_std=0.3, opacity_logit_mean=3.5, opacity_logit_std=1.5)
+        sc = Scene(*(a.astype(np.float64) for a in sc.arrays()))
+        cams = yaw_cameras((0.0, 9.0), (0.0, 0.0, 2.0), 32, 28, f=48)
+        opt = Optics((639e-9, 473e-9), (0.6e-3, 1.1e-3, 1.6e-3), 8e-6, 2, 2)
+        logits = np.random.default_rng(35).normal(size=(sc.n, 3))
+        tg = make_targets((2, 2, 3, 28, 32), 37)
+        thr = oracle.DEFAULT
+        st = layers.forward_layers(sc, logits, cams, opt, thr, targets=tg)
+        for v in st["views"]:
+            stopped = np.any(v["res"].stop != layers.NEVER, axis=0)
+            assert np.mean(stopped) >= 0.5
+        g = layers.backward_layers(st)
+
+        params = [torch.tensor(a, requires_grad=True) for a in sc.arrays()]
+        w = torch.tensor(st["weights"], requires_grad=True)
+        total, n_el, clamped = 0.0, 0, 0.0
+        for b, cam in enumerate(cams):
+            a, v, order, H, W = dense.dense_alpha(params, sc, cam, thr)
+            clamped = max(clamped, float((a >= thr.alpha_max).any(0).double().mean()))
+            wl = w[order]
+            U = [dense.composite(a * wl[:, l][None], v, thr.t_min, H, W) for l in range(3)]
+            for li, lam in enumerate(opt.wavelengths):
+                P = sum(dense.asm(U[l][li], lam, z, opt.pitch, opt.band_limit) for l, z in enumerate(opt.distances))
+                for k, z in enumerate(opt.distances):
+                    u = dense.asm(P, lam, -z, opt.pitch, opt.band_limit)
+                    I = u.real ** 2 + u.imag ** 2
+                    total = total + torch.sum((I - torch.as_tensor(tg[b, li, k])) ** 2)
+                    n_el += I.numel()
+        assert clamped >= 0.1
+        loss = total / n_el
+        assert abs(loss.item() - st["loss"]) < 1e-12 * st["loss"]
+        loss.backward()
+        for name, p in zip(("means", "log_scales", "quats", "opacity", "amp", "phase"), params):
+            ref = p.grad.numpy()
+            err = np.linalg.norm(g[name] - ref) / np.linalg.norm(ref)
+            assert err < 1e-9, (name, err)
+        err = np.linalg.norm(g["rho"] - w.grad.numpy()) / np.linalg.norm(w.grad.numpy())
+        assert err < 1e-9, ("rho", err)
+    finally:
+        torch.set_default_dtype(old)
