@@ -107,7 +107,10 @@ typedef struct chrf_grads {
  *                      0 selects 128 * n_views * max_gaussians, capped at 2^28
  *   pad_factor         1 or 2: the propagation grid is pad_factor times the
  *                      field in each dimension (zero padding, top-left)
- *   band_limit         1: cut f^2 > 1/lambda^2 (Eq. 7); 2: also the sampling
+ *   band_limit         0: none: every bin is kept, a bin with f^2 > 1/lambda^2
+ *                      taking the decaying continuation of Eq. 7,
+ *                      exp(-2 pi |z| sqrt(f^2 - 1/lambda^2));
+ *                      1: cut f^2 > 1/lambda^2 (Eq. 7); 2: also the sampling
  *                      band limit |f_x| <= 1/(lambda sqrt((2 df_x z)^2 + 1)),
  *                      likewise in y, with df = 1/(padded size * pitch)
  *   pitch              pixel pitch in metres (Delta x of Sec. 3)
@@ -116,7 +119,10 @@ typedef struct chrf_grads {
  *   k_sigma            support half-width in standard deviations (3)
  *   alpha_min, alpha_max, t_min   compositing thresholds (1/255, 0.99, 1e-4):
  *                      a Gaussian contributes where a >= alpha_min; a is
- *                      clamped at alpha_max; a pixel stops after T < t_min
+ *                      clamped at alpha_max, which must be below 1 (the
+ *                      backward recovers the transmittance in front of a
+ *                      Gaussian by dividing by 1 - a, Sec. 4.2); a pixel
+ *                      stops after T < t_min
  *   tile_w, tile_h     raster tile, multiples of 8 with tile_w*tile_h in {64,128,256}
  *                      (0, 0 selects 16 x 16, the tile of Sec. 4.2)
  *   cols_per_block     columns per workgroup in the column FFT passes
@@ -194,6 +200,9 @@ const char* chrf_version(void);
 /* Validate desc and build a plan (host object + small device tables).
  * Errors: CHRF_EINVAL, CHRF_EUNSUPPORTED (size/radix/LDS limits), CHRF_EHIP, CHRF_ENOMEM. */
 chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_plan** out);
+/* Destroy a plan.  It frees no device memory itself (its small tables are
+ * released by the next chrf_plan_create or by chrf_destroy), so it may be
+ * called while another stream is being captured into a HIP graph. */
 void chrf_plan_destroy(chrf_plan* plan);
 /* Bytes of device workspace the caller must allocate (256-byte aligned start). */
 size_t chrf_plan_workspace_bytes(const chrf_plan* plan);

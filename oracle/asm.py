@@ -46,12 +46,20 @@ def band_mask(pH, pW, pitch, lam, z, mode):
 
 
 def transfer_function(pH, pW, pitch, lam, z, mode=2):
+    """Modes 1 and 2 cut the bins beyond 1/lambda (Eq. 7).  Mode 0 cuts
+    nothing: those bins keep the continuation of Eq. 7 that decays away from
+    the source plane, exp(-2 pi |z| sqrt(f^2 - 1/lambda^2)) (reading: the
+    paper always band-limits; the decaying branch is taken for either sign of
+    z so that backward propagation stays bounded)."""
     fy = frequencies(pH, pitch)[:, None]
     fx = frequencies(pW, pitch)[None, :]
     arg = 1.0 / (lam * lam) - fx * fx - fy * fy
     mask = band_mask(pH, pW, pitch, lam, z, mode) & (arg >= 0.0)
     phase = 2.0 * np.pi * z * np.sqrt(np.where(arg >= 0.0, arg, 0.0))
-    return np.where(mask, np.exp(1j * phase), 0.0)
+    H = np.where(mask, np.exp(1j * phase), 0.0)
+    if mode == 0:
+        H = np.where(arg < 0.0, np.exp(-2.0 * np.pi * abs(z) * np.sqrt(np.where(arg < 0.0, -arg, 0.0))), H)
+    return H
 
 
 def _pad(U, pad):

@@ -34,7 +34,10 @@ class Thresholds:
 
 DEFAULT = Thresholds()
 # Differentiable everywhere that matters: used by the finite-difference pins.
-SMOOTH = Thresholds(k_sigma=8.0, alpha_min=0.0, alpha_max=1.0, t_min=0.0)
+# alpha_max is the largest single-precision value below 1 (the backward
+# recovers T by dividing by 1 - alpha, so the GPU plans require alpha_max < 1);
+# no opacity of these scenes reaches it, so nothing clamps.
+SMOOTH = Thresholds(k_sigma=8.0, alpha_min=0.0, alpha_max=1.0 - 2.0 ** -24, t_min=0.0)
 
 
 def mse_loss(I, target):

@@ -7,7 +7,6 @@ wires chrf_backward into torch.autograd.
 from __future__ import annotations
 
 import ctypes as C
-import gc
 import math
 from dataclasses import dataclass
 
@@ -142,6 +141,10 @@ class Renderer:
         nbytes = int(self.lib.chrf_plan_workspace_bytes(self.plan))
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{device}")
         self.device = torch.device(f"cuda:{device}")
+        # Counts the calls that rewrite the state a backward reads from the
+        # workspace (forward, propagate, phase-only step); the autograd path
+        # checks it so that a backward never runs against a later forward.
+        self.generation = 0
 
     def __del__(self):
         if getattr(self, "plan", None) is not None and self.plan.value:
@@ -213,6 +216,7 @@ class Renderer:
         _check_tensor(target, "target", (B, L, K, H, W))
         _check_tensor(masks, "masks", (B, K, H, W), torch.uint8)
         g = self._gauss(params)
+        self.generation += 1
         check(self.lib.chrf_forward(self.plan, C.byref(g), _ptr(cams), _ptr(self.workspace), _ptr(field),
                                     _ptr(prop), _ptr(inten), _ptr(target), _ptr(masks), _ptr(loss), _stream()))
         self._saved = (target, masks, prop, inten)   # read again by a backward of the "paper" loss
@@ -249,6 +253,7 @@ class Renderer:
         _check_tensor(field, "field", (B, L, H, W, 2))
         prop = torch.empty((B, L, K, H, W, 2), dtype=torch.float32, device=self.device) if want_prop else None
         inten = torch.empty((B, L, K, H, W), dtype=torch.float32, device=self.device) if want_intensity else None
+        self.generation += 1
         check(self.lib.chrf_propagate(self.plan, _ptr(field), _ptr(self.workspace), _ptr(prop), _ptr(inten),
                                       _stream()))
         return prop, inten
@@ -260,6 +265,7 @@ class Renderer:
         _check_tensor(phi, "phi", (self.B, self.L, self.H, self.W))
         loss = torch.empty((), dtype=torch.float32, device=self.device)
         dphi = torch.empty_like(phi)
+        self.generation += 1
         check(self.lib.chrf_phase_only_step(self.plan, _ptr(targets), _ptr(phi), _ptr(self.workspace), _ptr(loss),
                                             _ptr(dphi), _stream()))
         return loss, dphi
@@ -427,6 +433,8 @@ class Trainer:
         self.headroom = pair_headroom
         self.gen = torch.Generator(device=self.p["means"].device).manual_seed(seed)
         self.step_count = 0
+        self.overflows = 0
+        self._status_pending = None
         self._reset_stats()
         self._ensure_capacity()
 
@@ -452,11 +460,40 @@ class Trainer:
         if st != 0:
             self.r = self.r.resized(max_pairs=int(need * self.headroom) + 4096)
 
+    def _check_status(self):
+        """Reads the pair-list status the previous step copied to host memory
+        (its copy has long completed, so this does not stall the stream).  A
+        step whose pairs overflowed had incomplete gradients: the renderer is
+        replaced by one with room for the pairs it needed."""
+        if self._status_pending is None:
+            return
+        host, done = self._status_pending
+        self._status_pending = None
+        done.synchronize()
+        total = (int(host[0]) & 0xFFFFFFFF) | ((int(host[1]) & 0xFFFFFFFF) << 32)
+        if int(host[3]) != 0:
+            raise RuntimeError("radix sort: a look-back wait gave up; the step's pair lists were not valid")
+        if int(host[2]) != 0:
+            self.overflows += 1
+            self.r = self.r.resized(max_pairs=int(total * self.headroom) + 4096)
+
+    def _queue_status(self):
+        """Copies the status words of the step just enqueued to pinned host
+        memory, to be read at the next step."""
+        host = torch.empty(4, dtype=torch.int32, pin_memory=True)
+        status = self.r.region(_lib.REGION_STATUS, torch.int32)[:4]
+        host.copy_(status, non_blocking=True)
+        done = torch.cuda.Event()
+        done.record(torch.cuda.current_stream())
+        self._status_pending = (host, done)
+
     def step(self):
         """One training step; returns the loss (device scalar) before the update."""
+        self._check_status()
         self.step_count += 1
         rp = self.render_params()
         loss, grads, _ = self.r.train_step(rp, self.cams, self.target, masks=self.masks)
+        self._queue_status()
         o = rp["opacity"]
         grads["opacity"] = (grads["opacity"] * o * (1.0 - o)).contiguous()
         self.r.densify_stats(self.n, self.accum, self.count)
@@ -515,17 +552,8 @@ class CapturedTrainStep:
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
-        # No cyclic garbage collection during the capture: a collected plan
-        # frees device memory, which a capture in progress does not allow.
-        gc.collect()
-        was_enabled = gc.isenabled()
-        gc.disable()
-        try:
-            with torch.cuda.graph(self.graph):
-                self.loss, self.grads, _ = renderer.train_step(params, cams, target, masks=masks)
-        finally:
-            if was_enabled:
-                gc.enable()
+        with torch.cuda.graph(self.graph):
+            self.loss, self.grads, _ = renderer.train_step(params, cams, target, masks=masks)
 
     def replay(self):
         self.graph.replay()
@@ -546,6 +574,7 @@ class HologramFunction(torch.autograd.Function):
         params = {k: v.detach().contiguous() for k, v in params.items()}
         out = renderer.forward(params, cams, want_field=False, want_prop=True, want_intensity=True)
         ctx.renderer = renderer
+        ctx.generation = renderer.generation
         ctx.cams = cams
         ctx.params = params
         ctx.save_for_backward(out["prop"])
@@ -554,7 +583,17 @@ class HologramFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, dI):
         (prop,) = ctx.saved_tensors
-        grads = ctx.renderer.backward(ctx.params, ctx.cams, dL_dI=dI.contiguous(), prop=prop)
+        r = ctx.renderer
+        if r.generation != ctx.generation:
+            raise RuntimeError("render_intensity: the renderer ran another forward after this one; its workspace "
+                               "(pair lists, transmittance) no longer belongs to this graph.  Use one renderer per "
+                               "outstanding autograd forward.")
+        st, need = r.read_status()
+        if st == _lib.CHRF_ECAPACITY:
+            raise _lib.ChrfError(st, f"pair list overflow in the forward ({need} pairs needed, capacity "
+                                     f"{r.desc.max_pairs}); the gradient would be incomplete")
+        check(st)
+        grads = r.backward(ctx.params, ctx.cams, dL_dI=dI.contiguous(), prop=prop)
         g_logits = grads.get(LAYER_LOGITS)
         return (None, None) + tuple(grads[k] for k in PARAM_NAMES) + (g_logits,)
 

@@ -34,14 +34,19 @@ __device__ inline void st(float2* p, cpx v) { *p = make_float2(v.x, v.y); }
 
 __device__ inline int signed_bin(int k, int n) { return 2 * k < n ? k : k - n; }
 
-// H_k(fx, fy) / (pH pW) at bins (kx, ky); zero outside the band.
+// H_k(fx, fy) / (pH pW) at bins (kx, ky); zero outside the band (band modes
+// 1 and 2).  Band mode 0 cuts nothing: a bin beyond 1 / lambda keeps the
+// decaying continuation exp(-2 pi |z| sqrt(f^2 - 1/lambda^2)) of Eq. 7.
 __device__ inline cpx transfer(const HParam& hp, int kx, int ky, const AsmGeom& g) {
   const int sx = signed_bin(kx, g.pW), sy = signed_bin(ky, g.pH);
   if (g.band_mode >= 2 && (abs(sx) > hp.kx_max || abs(sy) > hp.ky_max)) return cpx{0.f, 0.f};
   const long long lhs = (long long)sx * sx * g.pH * g.pH + (long long)sy * sy * g.pW * g.pW;
-  if (lhs > hp.evan_bound) return cpx{0.f, 0.f};
   const float fx = (float)sx * g.ax, fy = (float)sy * g.ay;
   const float f2 = fx * fx + fy * fy;
+  if (lhs > hp.evan_bound) {
+    if (g.band_mode != 0) return cpx{0.f, 0.f};
+    return cpx{expf(-hp.decay * sqrtf(fmaxf(f2 - hp.inv_lam2, 0.0f))) * g.norm, 0.f};
+  }
   const float root = sqrtf(fmaxf(hp.inv_lam2 - f2, 0.0f));
   float rev = hp.frac_rev - hp.z * f2 / (hp.inv_lam + root);
   rev -= rintf(rev);
@@ -329,7 +334,7 @@ size_t col_lds_bytes(int pH, int C) { return 2 * sizeof(cpx) * (size_t)pH * C; }
 
 hipError_t launch_cols_forward(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, int C,
                                hipStream_t s) {
-  if (tuned_cols(g)) return launch_cols_forward_t(x1, y, g, fc, C == 2 ? 2 : 4, s);
+  if (tuned_cols(g)) return launch_cols_forward_t(x1, y, g, fc, C, s);
   const int ngroups = g.pW / C;
   const unsigned blocks = (unsigned)(g.n_bl * ngroups);
   const int span = C * 8 >= 128 ? 1 : 128 / (C * 8);
@@ -341,7 +346,7 @@ hipError_t launch_cols_forward(const float2* x1, float2* y, const AsmGeom& g, co
 
 hipError_t launch_cols_adjoint(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, int C,
                                hipStream_t s) {
-  if (tuned_cols(g)) return launch_cols_adjoint_t(z, w1, g, fc, C == 2 ? 2 : 4, s);
+  if (tuned_cols(g)) return launch_cols_adjoint_t(z, w1, g, fc, C, s);
   const int ngroups = g.pW / C;
   const unsigned blocks = (unsigned)(g.n_bl * ngroups);
   const int span = C * 8 >= 128 ? 1 : 128 / (C * 8);

@@ -469,7 +469,9 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoi
 using Row3840 = RowT<3840, 256, 16, 16, 15>;
 
 bool tuned_rows(const AsmGeom& g) { return g.pW == 3840; }
-bool tuned_cols(const AsmGeom& g) { return g.pH == kColN && g.pW % 128 == 0; }
+// (band mode 0 with evanescent bins present needs the decaying continuation,
+// which only the generic passes form)
+bool tuned_cols(const AsmGeom& g) { return g.pH == kColN && g.pW % 128 == 0 && !(g.band_mode == 0 && g.evanescent); }
 
 static bool rows_half(const AsmGeom& g) { return 2 * g.W == g.pW; }
 static bool cols_half(const AsmGeom& g) { return 2 * g.H == g.pH; }

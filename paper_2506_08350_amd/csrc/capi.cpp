@@ -54,6 +54,14 @@ struct chrf_ctx {
   int device = 0;
   int lds_per_block = 65536;
   std::map<int, cpx*> twiddles;
+  // Device tables and events of destroyed plans.  Freeing device memory is not
+  // allowed while any stream of the process is being captured into a graph,
+  // and a plan may be destroyed at such a time (a caller dropping a renderer
+  // while it captures another one), so plans hand their resources here; they
+  // are released by the next chrf_plan_create (which allocates, so it is not
+  // called during a capture either) or by chrf_destroy.
+  std::vector<void*> retired_mem;
+  std::vector<hipEvent_t> retired_events;
   std::mutex mu;
 };
 
@@ -66,6 +74,7 @@ struct chrf_plan {
   int64_t cap = 0;
   int cols_per_block = 0;
   int g2 = 0;
+  bool evanescent = false;
   bool layered = false;
   int loss_kind = 0;
   // loss_kind 1: buffers of the last forward that the backward reads again
@@ -171,6 +180,7 @@ AsmGeom geom(const chrf_plan* p) {
   g.n_lambda = p->L;
   g.K = p->K;
   g.band_mode = p->d.band_limit;
+  g.evanescent = p->evanescent ? 1 : 0;
   g.ax = (float)(1.0 / (p->pW * p->d.pitch));
   g.ay = (float)(1.0 / (p->pH * p->d.pitch));
   g.norm = (float)(1.0 / ((double)p->pH * (double)p->pW));
@@ -212,8 +222,17 @@ chrf_status chrf_create(int device, chrf_ctx** out) {
   return CHRF_OK;
 }
 
+static void release_retired(chrf_ctx* ctx) {
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  for (void* m : ctx->retired_mem) hipFree(m);
+  for (hipEvent_t e : ctx->retired_events) hipEventDestroy(e);
+  ctx->retired_mem.clear();
+  ctx->retired_events.clear();
+}
+
 void chrf_destroy(chrf_ctx* ctx) {
   if (!ctx) return;
+  release_retired(ctx);
   for (auto& kv : ctx->twiddles) hipFree(kv.second);
   delete ctx;
 }
@@ -230,14 +249,16 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   if (d.max_gaussians < 0 || (int64_t)d.max_gaussians * d.n_views >= ((int64_t)1 << 31))
     return fail(CHRF_EINVAL, "plan: n_views * max_gaussians must be below 2^31");
   if (d.pad_factor != 1 && d.pad_factor != 2) return fail(CHRF_EINVAL, "plan: pad_factor must be 1 or 2");
-  if (d.band_limit != 1 && d.band_limit != 2) return fail(CHRF_EINVAL, "plan: band_limit must be 1 or 2");
+  if (d.band_limit < 0 || d.band_limit > 2) return fail(CHRF_EINVAL, "plan: band_limit must be 0, 1 or 2");
   if (!(d.pitch > 0)) return fail(CHRF_EINVAL, "plan: pitch must be positive");
   for (int l = 0; l < d.n_lambda; ++l)
     if (!(d.wavelengths[l] > 0)) return fail(CHRF_EINVAL, "plan: wavelengths must be positive");
   for (int k = 0; k < d.n_planes; ++k)
     if (!std::isfinite(d.distances[k])) return fail(CHRF_EINVAL, "plan: distances must be finite");
-  if (!(d.k_sigma > 0) || !(d.alpha_max > 0 && d.alpha_max <= 1) || !(d.alpha_min >= 0) || !(d.t_min >= 0))
-    return fail(CHRF_EINVAL, "plan: thresholds out of range");
+  // alpha_max < 1: the backward recovers T in front of a pair by dividing by 1 - alpha
+  if (!(d.k_sigma > 0) || !(d.alpha_max > 0 && d.alpha_max < 1) || !(d.alpha_min >= 0) || !(d.t_min >= 0))
+    return fail(CHRF_EINVAL, "plan: thresholds out of range (k_sigma > 0, 0 < alpha_max < 1, alpha_min >= 0, "
+                             "t_min >= 0)");
   if (d.layered != 0 && d.layered != 1) return fail(CHRF_EINVAL, "plan: layered must be 0 or 1");
   if (d.loss_kind != 0 && d.loss_kind != 1) return fail(CHRF_EINVAL, "plan: loss_kind must be 0 or 1");
   if (!(d.ssim_weight >= 0) || !std::isfinite(d.ssim_weight)) return fail(CHRF_EINVAL, "plan: ssim_weight must be >= 0");
@@ -247,6 +268,7 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   if (tw <= 0 || th <= 0 || tw % 8 || th % 8 || (tw * th != 64 && tw * th != 128 && tw * th != 256))
     return fail(CHRF_EINVAL, "plan: tile_w, tile_h must be multiples of 8 with tile_w * tile_h in {64, 128, 256}");
 
+  release_retired(ctx);
   chrf_plan* p = new (std::nothrow) chrf_plan();
   if (!p) return fail(CHRF_ENOMEM, "plan: out of host memory");
   p->ctx = ctx;
@@ -334,6 +356,11 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
       const double e = (double)p->pW * p->pH * d.pitch / lam;
       const double bound = std::floor(e * e);
       h.evan_bound = bound > 9e18 ? (long long)9e18 : (long long)bound;
+      h.decay = (float)(2.0 * M_PI * std::fabs(z));
+      // the corner bin (pW/2, pH/2) has the largest |f|
+      const double hx = (double)(p->pW / 2), hy = (double)(p->pH / 2);
+      if (hx * hx * p->pH * (double)p->pH + hy * hy * p->pW * (double)p->pW > (double)h.evan_bound)
+        p->evanescent = true;
     }
   {
     hipError_t e = hipMalloc(&p->hp_dev, sizeof(HParam) * hp.size());
@@ -398,14 +425,19 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   return CHRF_OK;
 }
 
+// Frees nothing on the device itself (see chrf_ctx::retired_mem), so a plan
+// may be destroyed while another stream is being captured.
 void chrf_plan_destroy(chrf_plan* p) {
   if (!p) return;
-  if (p->hp_dev) hipFree(p->hp_dev);
-  for (auto& r : p->trec) {
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+  {
+    std::lock_guard<std::mutex> lock(p->ctx->mu);
+    if (p->hp_dev) p->ctx->retired_mem.push_back(p->hp_dev);
+    for (auto& r : p->trec) {
+      p->ctx->retired_events.push_back(r.a);
+      p->ctx->retired_events.push_back(r.b);
+    }
+    for (auto e : p->ev_pool) p->ctx->retired_events.push_back(e);
   }
-  for (auto e : p->ev_pool) hipEventDestroy(e);
   delete p;
 }
 

@@ -66,13 +66,16 @@ struct HParam {
   float inv_lam2;    // 1 / lambda^2
   int kx_max, ky_max;          // sampling band limit in bins (mode 2), else large
   long long evan_bound;        // kx^2 pH^2 + ky^2 pW^2 <= bound  <=> f^2 <= 1/lambda^2
+  float decay;                 // 2 pi |z|: band mode 0 keeps evanescent bins as exp(-decay sqrt(f^2 - 1/lambda^2))
+  float pad_;
 };
 
 struct AsmGeom {
   int H, W, pH, pW;
   int n_bl;         // views * wavelengths
   int n_lambda, K;
-  int band_mode;
+  int band_mode;    // 0 none (evanescent bins decay), 1 Eq. 7, 2 Eq. 7 + sampling limit
+  int evanescent;   // some bin of the padded grid lies beyond 1 / lambda for some wavelength
   float ax, ay;     // 1 / (pW pitch), 1 / (pH pitch)
   float norm;       // 1 / (pH pW)
   const HParam* hp; // [n_lambda][K]

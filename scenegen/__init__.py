@@ -241,8 +241,26 @@ def _c3_layers():
     return w
 
 
+def _c3_fd(second=False):
+    """The finite-difference subset of the 1080p training workload: its first
+    50 Gaussians rendered at 64 x 64 with fx = fy = 64, same wavelengths,
+    planes and pitch; the second case redraws the log-scales N(-2.5, 0.3)
+    for footprints of several pixels.  Targets U[0, 1)."""
+    full = make_gaussians(100_000, 3, 1002)
+    scene = full.subset(np.arange(50))
+    if second:
+        rng = np.random.default_rng(1002 + 40_000)
+        scene.log_scales = rng.normal(-2.5, 0.3, (50, 3)).astype(np.float32)
+    cam = identity_camera(64, 64, f=64)
+    opt = Optics((639e-9, 515e-9, 473e-9), (0.5e-3, 1.0e-3, 1.5e-3, 2.0e-3), 8e-6, 2, 2)
+    name = "c3_fd_subset_64_wide" if second else "c3_fd_subset_64"
+    w = Workload(name, scene, [cam], opt, backward=True)
+    w.targets = make_targets((1, 3, 4, 64, 64), 1002 + 50_000 + int(second))
+    return w
+
+
 WORKLOADS = {"c1": _c1, "c2": lambda: _c2(False), "c3": lambda: _c2(True), "c4": _c4, "c5": _c5,
-             "c3_layers": _c3_layers}
+             "c3_layers": _c3_layers, "c3_fd": _c3_fd, "c3_fd_wide": lambda: _c3_fd(True)}
 
 
 def make_workload(key: str) -> Workload:

@@ -32,26 +32,3 @@ def rel_l2(a, b):
 
 def announce(msg):
     print(f"[gpu] {msg}", flush=True)
-
-
-def describe_partials(r, params, cams, target, n_rows):
-    """Extra facts for a failed comparison of the fused per-row loss sums:
-    NaN counts of the inputs and outputs, and the sums again from a cloned
-    target and from a constant target of ones."""
-    from paper_2506_08350_amd import _lib
-    import torch
-
-    def rows_of(t):
-        out = r.forward(params, cams, want_field=False, want_intensity=True, target=t)
-        torch.cuda.synchronize()
-        part = r.region(_lib.REGION_LOSS_PARTIAL, torch.float32)[:n_rows].double()
-        I = out["intensity"]
-        return (int(torch.isnan(part).sum()), part[:2].tolist(), int(torch.isnan(I).sum()), float(out["loss"]))
-
-    facts = {
-        "target_nan": int(torch.isnan(target).sum()),
-        "clone": rows_of(target.clone()),
-        "ones": rows_of(torch.ones_like(target)),
-    }
-    print(f"[gpu] partial sums: {facts}", flush=True)
-    return facts

@@ -118,7 +118,7 @@ def test_wide_rows_propagation_and_fused_loss(W):
     the squared targets."""
     from paper_2506_08350_amd import _lib, api
     from scenegen import make_gaussians
-    from tests.gpu_helpers import describe_partials, to_device
+    from tests.gpu_helpers import to_device
 
     announce(f"wide rows W={W}")
     H = 6
@@ -140,8 +140,6 @@ def test_wide_rows_propagation_and_fused_loss(W):
     assert float(out["intensity"].abs().max()) == 0.0
     part = r.region(_lib.REGION_LOSS_PARTIAL, torch.float32)[:2 * H].double()
     rows = (tgt.double() ** 2).sum(-1).reshape(-1)
-    if not torch.allclose(part, rows, rtol=1e-5):
-        describe_partials(r, to_device(make_gaussians(0, 1, 9)), api.pack_cameras([cam]), tgt, 2 * H)
     assert torch.allclose(part, rows, rtol=1e-5), (part[:4].tolist(), rows[:4].tolist())
     assert abs(float(out["loss"]) - float((tgt.double() ** 2).mean())) < 1e-5
 

@@ -101,3 +101,107 @@ def test_autotune_caches_a_runnable_choice(tmp_path):
     loss, _, _ = r.train_step(params, cam_t, target)
     st = oracle.forward(sc, cams, opt, targets=tg)
     assert abs(float(loss) - st["loss"]) < 1e-4 * st["loss"]
+
+
+def test_renderer_dropped_during_another_capture():
+    """A renderer freed while another one's training step is being captured
+    (for example by the cyclic garbage collector) does not break the capture:
+    destroying a plan frees no device memory."""
+    import gc
+
+    announce("plan destroyed during a capture")
+    sc, cams, opt, tg = _problem(views=(0.0,))
+    params = to_device(sc)
+    cam_t = api.pack_cameras(cams)
+    target = torch.from_numpy(tg).cuda()
+    r = make_renderer(cams, opt, sc.n)
+    victim = make_renderer(cams, opt, sc.n)
+    cycle = {"renderer": victim}
+    cycle["self"] = cycle          # only the cyclic collector can free it
+    del victim
+    loss0, g0, _ = r.train_step(params, cam_t, target)
+    loss0 = float(loss0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        r.train_step(params, cam_t, target)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        loss, grads, _ = r.train_step(params, cam_t, target)
+        del cycle
+        assert gc.collect() > 0   # the victim's plan is destroyed inside the capture
+    for _ in range(2):
+        graph.replay()
+        torch.cuda.synchronize()
+        assert float(loss) == loss0
+
+
+def test_plan_rejects_alpha_max_of_one():
+    opt = Optics((515e-9,), (1e-3,), 8e-6, 2, 2)
+    with pytest.raises(api._lib.ChrfError):
+        make_renderer([identity_camera(32, 32)], opt, 4, thr=oracle.Thresholds(alpha_max=1.0))
+
+
+def test_autograd_backward_after_another_forward_raises():
+    """One renderer serves one outstanding autograd forward: a backward after
+    the renderer ran another forward would read that forward's workspace."""
+    announce("autograd generation check")
+    sc, cams, opt, tg = _problem(views=(0.0,))
+    r = make_renderer(cams, opt, sc.n)
+    cam_t = api.pack_cameras(cams)
+    leaves = {k: v.clone().requires_grad_(True) for k, v in to_device(sc).items()}
+    I = api.render_intensity(r, cam_t, *(leaves[k] for k in api.PARAM_NAMES))
+    r.forward(to_device(sc), cam_t, want_field=True)
+    with pytest.raises(RuntimeError, match="another forward"):
+        I.sum().backward()
+
+
+def test_trainer_grows_the_pair_list_after_an_overflow():
+    """A training step whose pairs overflow the list is detected from the
+    status words (read one step later without stalling) and the renderer is
+    replaced by one with room for them."""
+    announce("trainer overflow detection")
+    sc, cams, opt, tg = _problem(views=(0.0,))
+    r = make_renderer(cams, opt, sc.n, max_pairs=1 << 16)
+    tr = api.Trainer(r, to_device(sc), api.pack_cameras(cams), torch.from_numpy(tg).cuda(), total_steps=10,
+                     densify_every=1000)
+    need = tr.r.read_status()[1]
+    tr.r = tr.r.resized(max_pairs=need // 2)    # too small from now on
+    tr.step()
+    tr.step()
+    torch.cuda.synchronize()
+    assert tr.overflows == 1
+    assert tr.r.desc.max_pairs > need
+    tr.step()
+    torch.cuda.synchronize()
+    assert tr.r.read_status()[0] == 0
+
+
+@pytest.mark.parametrize("H,W,pitch", [(24, 40, 0.3e-6), (1080, 1920, 8e-6)])
+def test_band_mode_none(H, W, pitch):
+    """band_limit 0 keeps every bin.  At 0.3 um pitch part of the padded grid
+    lies beyond 1/lambda and those bins decay (generic passes) — against the
+    oracle; at the 1080p workload's 8 um pitch no bin does, and the tuned
+    passes give exactly the band-limited result."""
+    announce(f"band mode 0 at {H}x{W}")
+    zs = (0.6e-6, -0.9e-6) if pitch < 1e-6 else (0.5e-3, 2e-3)
+    rng = np.random.default_rng(4)
+    U = rng.normal(size=(1, 1, H, W)) + 1j * rng.normal(size=(1, 1, H, W))
+    Ug = torch.from_numpy(np.stack([U.real, U.imag], -1).astype(np.float32)).cuda()
+    outs = []
+    for mode in (0, 1):
+        opt = Optics((515e-9,), zs, pitch, 2, mode)
+        r = make_renderer([identity_camera(W, H)], opt, 1)
+        prop, _ = r.propagate(Ug, want_intensity=False)
+        torch.cuda.synchronize()
+        outs.append(prop)
+        if mode == 0 and pitch < 1e-6:
+            from tests.gpu_helpers import cplx
+            for k, z in enumerate(zs):
+                ref = oracle.propagate(U[0, 0], 515e-9, z, pitch, 2, 0)
+                assert rel_l2(cplx(prop[0, 0, k]), ref) < 1e-4, k
+                assert rel_l2(ref, oracle.propagate(U[0, 0], 515e-9, z, pitch, 2, 1)) > 1e-3
+    if pitch > 1e-6:
+        assert torch.equal(outs[0], outs[1])

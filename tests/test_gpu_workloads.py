@@ -19,7 +19,7 @@ import oracle
 from oracle import binning, projection, raster
 from paper_2506_08350_amd import _lib, api
 from scenegen import make_workload
-from tests.gpu_helpers import announce, cplx, describe_partials, rel_l2
+from tests.gpu_helpers import announce, cplx, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -170,8 +170,6 @@ def test_four_views_2160p_2m_16_planes():
     rows = ((I - target) ** 2).sum(dim=-1).double().reshape(-1)
     part = r.region(_lib.REGION_LOSS_PARTIAL, torch.float32)[:rows.numel()].double()
     bad = torch.nonzero(~torch.isclose(part, rows, rtol=1e-4, atol=1e-3)).reshape(-1)
-    if bad.numel():
-        describe_partials(r, params, cam_t, target, rows.numel())
     assert bad.numel() == 0, (bad.numel(), bad[:8].tolist(), part[bad[:4]].tolist(), rows[bad[:4]].tolist())
     ref_loss = float(rows.sum()) / I.numel()
     loss_before = float(out["loss"])

@@ -42,7 +42,11 @@ def _brute_asm(U, lam, z, pitch, pad, mode):
                 ok &= abs(fy) <= 1 / (lam * math.sqrt((2 * dfy * z) ** 2 + 1))
             if not ok:
                 continue
-            h = np.exp(2j * np.pi * z * np.sqrt(1 / lam ** 2 - fx * fx - fy * fy))
+            arg = 1 / lam ** 2 - fx * fx - fy * fy
+            if arg >= 0:
+                h = np.exp(2j * np.pi * z * np.sqrt(arg))
+            else:   # mode 0 only: the decaying evanescent continuation
+                h = np.exp(-2 * np.pi * abs(z) * np.sqrt(-arg))
             X = np.sum(P * np.exp(-2j * np.pi * (ky * n[:, None] / pH + kx * m[None, :] / pW)))
             r = np.arange(H)[:, None]
             c = np.arange(W)[None, :]
@@ -55,6 +59,8 @@ def _brute_asm(U, lam, z, pitch, pad, mode):
     ((3, 5), 2, 1, PITCH, 2e-3),       # radix 3 and 5 on the padded 6 x 10 grid
     ((9, 15), 1, 2, PITCH, -1.5e-3),   # odd sizes, negative distance
     ((6, 5), 2, 2, 0.3e-6, 4e-6),      # evanescent and sampling masks both active
+    ((6, 5), 2, 0, 0.3e-6, 4e-6),      # no band limit: evanescent bins decay
+    ((5, 6), 1, 0, 0.3e-6, -3e-6),     # ... for either sign of z
 ])
 def test_matches_brute_force_dft(shape, pad, mode, pitch, z):
     rng = np.random.default_rng(7)
@@ -156,6 +162,27 @@ def test_evanescent_and_sampling_masks_remove_plane_waves():
         u2 = asm.propagate(U, LAM, z, pitch, pad=1, mode=2)
         assert np.max(np.abs(u1)) > 0.99                      # mode 1 keeps it
         assert (np.max(np.abs(u2)) > 0.99) == alive
+
+
+def test_evanescent_plane_wave_decays_without_band_limit():
+    """Band mode 0: a plane wave on a bin beyond 1/lambda is kept and scaled by
+    exp(-2 pi |z| sqrt(f^2 - 1/lambda^2)); one inside the band gets the phase
+    of Eq. 7 exactly as with the band limit."""
+    H = W = 32
+    pitch = 0.2e-6
+    c = np.arange(W)[None, :]
+    k_evan = int(math.ceil(W * pitch / LAM * 1.02))
+    f = k_evan / (W * pitch)
+    for z in (3e-7, -3e-7):
+        U = np.exp(2j * np.pi * k_evan * c / W) * np.ones((H, 1))
+        u = asm.propagate(U, LAM, z, pitch, pad=1, mode=0)
+        expect = math.exp(-2 * math.pi * abs(z) * math.sqrt(f * f - 1 / LAM ** 2))
+        assert 1e-3 < expect < 0.9
+        assert np.allclose(u, expect * U, rtol=0, atol=1e-12)
+    k_prop = int(math.floor(W * pitch / LAM * 0.9))
+    U = np.exp(2j * np.pi * k_prop * c / W) * np.ones((H, 1))
+    assert np.allclose(asm.propagate(U, LAM, 3e-7, pitch, 1, 0), asm.propagate(U, LAM, 3e-7, pitch, 1, 1),
+                       rtol=0, atol=1e-13)
 
 
 def test_adjoint_identity():
