@@ -147,6 +147,16 @@ typedef struct chrf_grads {
  *                      padding; one SSIM per view, wavelength and plane)
  *   ssim_weight        lambda_1 of the SSIM term (0.005 in the paper)
  *   phase_only         1: reserve the workspace of chrf_phase_only_step
+ *   deterministic      1: gradients reproducible bit for bit from run to run
+ *                      (single-plane plans): instead of adding per-pair
+ *                      gradient sums to the per-(view, Gaussian) rows with
+ *                      float atomics, the backward stores one row per
+ *                      (tile, Gaussian) pair and a second kernel sums each
+ *                      Gaussian's rows in the fixed order of its tiles (the
+ *                      per-view rows are then summed over views in view
+ *                      order, as always).  Costs workspace of about
+ *                      4 (2 + per-Gaussian row length) bytes per pair and
+ *                      two extra passes over it.
  */
 typedef struct chrf_plan_desc {
   int32_t height, width;
@@ -165,7 +175,8 @@ typedef struct chrf_plan_desc {
   int32_t loss_kind;
   float ssim_weight;
   int32_t phase_only;
-  int32_t reserved[3];
+  int32_t deterministic;
+  int32_t reserved[2];
 } chrf_plan_desc;
 
 /* Named regions of the workspace, for inspection by tests and tools. */

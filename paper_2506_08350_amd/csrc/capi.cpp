@@ -40,6 +40,7 @@ enum Reg {
   R_LAYER_OF, R_LFIELD, R_LTFINAL, R_LSTOP, R_LGRAD,   // layered plans only
   R_UPROP, R_INTEN, R_DMU, R_DEXX, R_DEXY, R_DLDI, R_LOSS2,   // loss_kind 1 only
   R_PO_P, R_PO_V, R_PO_GV, R_PO_D, R_PO_GP, R_PO_PART,       // phase_only plans only
+  R_DET_RID, R_DET_INV, R_DET_GRAD,                          // deterministic plans only
   R_NUM
 };
 
@@ -74,6 +75,7 @@ struct chrf_plan {
   int64_t cap = 0;
   int cols_per_block = 0;
   int g2 = 0;
+  bool deterministic = false;
   bool evanescent = false;
   bool layered = false;
   int loss_kind = 0;
@@ -263,6 +265,9 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   if (d.loss_kind != 0 && d.loss_kind != 1) return fail(CHRF_EINVAL, "plan: loss_kind must be 0 or 1");
   if (!(d.ssim_weight >= 0) || !std::isfinite(d.ssim_weight)) return fail(CHRF_EINVAL, "plan: ssim_weight must be >= 0");
   if (d.layered && d.n_planes > kMaxLayers) return fail(CHRF_EUNSUPPORTED, "plan: a layered plan takes 1..4 layers");
+  if (d.deterministic != 0 && d.deterministic != 1) return fail(CHRF_EINVAL, "plan: deterministic must be 0 or 1");
+  if (d.deterministic && d.layered)
+    return fail(CHRF_EUNSUPPORTED, "plan: deterministic gradients are available for single-plane plans only");
   int tw = d.tile_w, th = d.tile_h;
   if (tw == 0 && th == 0) tw = th = 16;
   if (tw <= 0 || th <= 0 || tw % 8 || th % 8 || (tw * th != 64 && tw * th != 128 && tw * th != 256))
@@ -287,6 +292,7 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   p->tiles_y = (d.height + th - 1) / th;
   p->n_tiles = p->tiles_x * p->tiles_y;
   p->layered = d.layered != 0;
+  p->deterministic = d.deterministic != 0;
   p->loss_kind = d.loss_kind;
   // per-(view, Gaussian) gradient row: 6 + 2 n_lambda values (+ n_layers), padded
   // to 16 floats (one 64-byte row) or the next multiple of 4
@@ -414,6 +420,8 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   sz[R_PO_V] = sz[R_PO_GV] = sizeof(float2) * fpix * p->K;
   sz[R_PO_D] = sizeof(float) * fpix * p->K * 6;             // 3 SSIM derivative maps x (re, im)
   sz[R_PO_PART] = po ? sizeof(float) * (size_t)loss_partial_elems(2 * p->B * p->L * p->K, p->H, p->W) : 0;
+  sz[R_DET_RID] = sz[R_DET_INV] = p->deterministic ? sizeof(uint32_t) * cap : 0;
+  sz[R_DET_GRAD] = p->deterministic ? sizeof(float) * cap * p->g2 : 0;
   size_t o = 0;
   for (int r = 0; r < R_NUM; ++r) {
     p->off[r] = o;
@@ -547,7 +555,8 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
   RUN("emit_pairs", launch_emit_pairs(gval, at<uint64_t>(plan, ws, R_OFFSETS), at<uint32_t>(plan, ws, R_CNT_SORTED),
                                       at<int4>(plan, ws, R_RECT), BN, Nst, plan->d.tile_w, plan->d.tile_h,
                                       plan->tiles_x, plan->n_tiles, at<uint32_t>(plan, ws, R_PKEY),
-                                      at<uint32_t>(plan, ws, R_PVAL), plan->cap, total, status + 2, s));
+                                      at<uint32_t>(plan, ws, R_PVAL), plan->cap, total, status + 2,
+                                      plan->deterministic ? at<uint32_t>(plan, ws, R_DET_RID) : nullptr, s));
   bool palt = false;
   RUN("sort_pairs", radix_sort_u32(at<uint32_t>(plan, ws, R_PKEY), at<uint32_t>(plan, ws, R_PKEY_ALT),
                                    at<uint32_t>(plan, ws, R_PVAL), at<uint32_t>(plan, ws, R_PVAL_ALT), plan->cap,
@@ -556,6 +565,9 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
   const uint32_t* pkey = at<uint32_t>(plan, ws, palt ? R_PKEY_ALT : R_PKEY);
   const uint32_t* pval = at<uint32_t>(plan, ws, palt ? R_PVAL_ALT : R_PVAL);
   RUN("tile_ranges", launch_tile_ranges(pkey, total, plan->cap, ranges, s));
+  if (plan->deterministic)
+    RUN("det_gather", launch_det_gather(const_cast<uint32_t*>(pval), at<uint32_t>(plan, ws, R_DET_RID),
+                                        at<uint32_t>(plan, ws, R_DET_INV), total, plan->cap, s));
 
   RasterArgs ra{};
   ra.rec_g0 = at<float4>(plan, ws, R_G0);
@@ -712,6 +724,11 @@ chrf_status chrf_backward(chrf_plan* plan, const chrf_gaussians* g, const chrf_c
   ra.grad_scale = grad_scale;
   ra.grad2d = grad2d;
   ra.g2stride = plan->g2;
+  float* pair_grad = plan->deterministic ? at<float>(plan, ws, R_DET_GRAD) : nullptr;
+  if (pair_grad) {
+    RUN("pair_grad_clear", launch_fill_f32(pair_grad, 0.f, plan->cap * plan->g2, s));
+    ra.pair_grad = pair_grad;
+  }
   if (plan->layered) {
     ra.layer_of = at<uint8_t>(plan, ws, R_LAYER_OF);
     ra.n_layers = plan->K;
@@ -721,6 +738,11 @@ chrf_status chrf_backward(chrf_plan* plan, const chrf_gaussians* g, const chrf_c
   } else {
     RUN("raster_backward", launch_raster_backward(ra, s));
   }
+  if (pair_grad)
+    RUN("det_reduce", launch_det_reduce(at<uint32_t>(plan, ws, plan->gsort_alt ? R_GVAL_ALT : R_GVAL),
+                                        at<uint64_t>(plan, ws, R_OFFSETS), at<uint32_t>(plan, ws, R_CNT_SORTED),
+                                        at<uint32_t>(plan, ws, R_DET_INV), pair_grad, (int64_t)plan->B * Nst,
+                                        plan->g2, plan->cap, grad2d, s));
   RUN("project_backward",
       launch_project_backward(g->means, g->log_scales, g->quats, g->amp, g->phase, reinterpret_cast<const Cam*>(cams),
                               g->n, Nst, plan->B, plan->L, at<uint32_t>(plan, ws, R_GCOUNT), grad2d, plan->g2,

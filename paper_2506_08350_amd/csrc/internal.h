@@ -111,7 +111,14 @@ hipError_t launch_gather_counts(const uint32_t* sorted_val, const uint32_t* coun
 hipError_t launch_emit_pairs(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* cnt_sorted,
                              const int4* rect, int64_t n, int n_stride, int tile_w, int tile_h, int tiles_x,
                              int n_tiles, uint32_t* pair_key, uint32_t* pair_val, int64_t capacity,
-                             const uint64_t* total, uint32_t* status, hipStream_t s);
+                             const uint64_t* total, uint32_t* status, uint32_t* det_rid, hipStream_t s);
+// deterministic gradient mode: slot bookkeeping after the pair sort, and the
+// fixed-order reduction of per-pair gradient rows into per-(view, Gaussian) rows
+hipError_t launch_det_gather(uint32_t* pair_val, const uint32_t* det_rid, uint32_t* inv, const uint64_t* total,
+                             int64_t capacity, hipStream_t s);
+hipError_t launch_det_reduce(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* cnt_sorted,
+                             const uint32_t* inv, const float* pair_grad, int64_t n, int g2, int64_t capacity,
+                             float* grad2d, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t* pair_key, const uint64_t* total, int64_t capacity, uint2* ranges,
                               hipStream_t s);
@@ -134,6 +141,7 @@ struct RasterArgs {
   const float* grad_scale;  // device scalar or null
   float* grad2d;            // [B * n_stride][g2stride]
   int g2stride;
+  float* pair_grad;         // deterministic mode: [pairs][g2stride] per-pair rows (plain stores), else null
   // multi-layer mode: field, grad_field [B][L][n_layers][H][W], t_final [B][n_layers][H][W]
   const uint8_t* layer_of;  // [n_stride] hard layer of each Gaussian
   int n_layers;

@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
             if (c < G2) {
               if constexpr (NW == 1)
                 s_grad[j][c] = gr[k];
-              else
+              else   // at most two waves: 0 + x + y rounds the same in either order
                 atomicAdd(&s_grad[j][c], gr[k]);
             }
           }
@@ -273,7 +273,12 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
     for (int t = threadIdx.x; t < cnt * G2; t += kLanes * NW) {
       const int i = t / G2, c = t - i * G2;
       const float sum = s_grad[i][c];
-      if (sum != 0.f) unsafeAtomicAdd(a.grad2d + (size_t)st.rid[i] * a.g2stride + c, sum);
+      if (sum != 0.f) {
+        if (a.pair_grad)   // deterministic mode: the row of pair top - 1 - i, summed later in a fixed order
+          a.pair_grad[(size_t)(top - 1 - i) * a.g2stride + c] = sum;
+        else
+          unsafeAtomicAdd(a.grad2d + (size_t)st.rid[i] * a.g2stride + c, sum);
+      }
       s_grad[i][c] = 0.f;
     }
     top -= cnt;
@@ -306,6 +311,7 @@ constexpr int kBwdWaves = CHRF_BWD_WAVES;
 template <int NL, int BPT>
 static void launch_bwd_nl(const RasterArgs& a, int blocks, hipStream_t s) {
   constexpr int NW = BPT < kBwdWaves ? BPT : kBwdWaves;
+  static_assert(NW <= 2, "the per-pair LDS sums are reproducible for at most two waves");
   k_raster_bwd<NL, BPT / NW, NW><<<blocks, kLanes * NW, 0, s>>>(a);
 }
 

@@ -21,6 +21,8 @@
 // earlier waves and earlier rounds held in LDS.  Counts that are only known on
 // the device (the number of pairs) are read by every block, so the launch
 // grid can be sized by capacity and the sequence needs no host round trip.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace chrf {
@@ -600,7 +602,8 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
                                                     const int4* __restrict__ rect, int64_t n, int n_stride,
                                                     int tile_w, int tile_h, int tiles_x, int n_tiles,
                                                     uint32_t* __restrict__ pair_key, uint32_t* __restrict__ pair_val,
-                                                    int64_t capacity, const uint64_t* total, uint32_t* status) {
+                                                    int64_t capacity, const uint64_t* total, uint32_t* status,
+                                                    uint32_t* __restrict__ det_rid) {
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kEmitTeam;
   const int lane = threadIdx.x % kEmitTeam;
   if (i == 0 && lane == 0 && *total > (uint64_t)capacity) status[0] = 1u;
@@ -622,19 +625,81 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
     const int dy = local / wt;
     const int dx = local - dy * wt;
     pair_key[base + local] = k0 + (uint32_t)(dy * tiles_x + dx);
-    pair_val[base + local] = rid;
+    if (det_rid) {
+      // deterministic mode: the sort carries the emission slot, the record id waits aside
+      pair_val[base + local] = (uint32_t)(base + local);
+      det_rid[base + local] = rid;
+    } else {
+      pair_val[base + local] = rid;
+    }
   }
 }
 
 hipError_t launch_emit_pairs(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* cnt_sorted,
                              const int4* rect, int64_t n, int n_stride, int tile_w, int tile_h, int tiles_x,
                              int n_tiles, uint32_t* pair_key, uint32_t* pair_val, int64_t capacity,
-                             const uint64_t* total, uint32_t* status, hipStream_t s) {
+                             const uint64_t* total, uint32_t* status, uint32_t* det_rid, hipStream_t s) {
   if (n <= 0 || capacity <= 0) return hipSuccess;
   const int64_t threads = n * kEmitTeam;
   k_emit_pairs<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(sorted_val, offsets, cnt_sorted, rect, n,
                                                                   n_stride, tile_w, tile_h, tiles_x, n_tiles,
-                                                                  pair_key, pair_val, capacity, total, status);
+                                                                  pair_key, pair_val, capacity, total, status,
+                                                                  det_rid);
+  return hipGetLastError();
+}
+
+// Deterministic mode, after the pair sort: the sorted values are emission
+// slots u.  Record where each slot went (inv[u] = sorted position) and
+// replace the slot by its record id, so the raster reads the usual list.
+__global__ __launch_bounds__(256) void k_det_gather(uint32_t* __restrict__ pair_val,
+                                                    const uint32_t* __restrict__ det_rid, uint32_t* __restrict__ inv,
+                                                    const uint64_t* total, int64_t capacity) {
+  const uint64_t live = min(*total, (uint64_t)capacity);
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < live; j += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t u = pair_val[j];
+    inv[u] = (uint32_t)j;
+    pair_val[j] = det_rid[u];
+  }
+}
+
+hipError_t launch_det_gather(uint32_t* pair_val, const uint32_t* det_rid, uint32_t* inv, const uint64_t* total,
+                             int64_t capacity, hipStream_t s) {
+  if (capacity <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((capacity + 255) / 256, 4096);
+  k_det_gather<<<(unsigned)blocks, 256, 0, s>>>(pair_val, det_rid, inv, total, capacity);
+  return hipGetLastError();
+}
+
+// Deterministic mode, after the raster backward wrote one gradient row per
+// sorted pair: each (view, Gaussian) row of grad2d is the sum of its pairs'
+// rows taken in emission order (the order of its tiles), with plain stores.
+__global__ __launch_bounds__(256) void k_det_reduce(const uint32_t* __restrict__ sorted_val,
+                                                    const uint64_t* __restrict__ offsets,
+                                                    const uint32_t* __restrict__ cnt_sorted,
+                                                    const uint32_t* __restrict__ inv,
+                                                    const float* __restrict__ pair_grad, int64_t n, int g2,
+                                                    int64_t capacity, float* __restrict__ grad2d) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / g2;
+  const int c = (int)(t - i * g2);
+  if (i >= n) return;
+  const uint32_t cnt = cnt_sorted[i];
+  if (cnt == 0) return;
+  const uint64_t base = offsets[i];
+  if (base >= (uint64_t)capacity) return;
+  const uint64_t end = min(base + cnt, (uint64_t)capacity);
+  float sum = 0.f;
+  for (uint64_t u = base; u < end; ++u) sum += pair_grad[(size_t)inv[u] * g2 + c];
+  grad2d[(size_t)sorted_val[i] * g2 + c] = sum;
+}
+
+hipError_t launch_det_reduce(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* cnt_sorted,
+                             const uint32_t* inv, const float* pair_grad, int64_t n, int g2, int64_t capacity,
+                             float* grad2d, hipStream_t s) {
+  if (n <= 0 || capacity <= 0) return hipSuccess;
+  const int64_t threads = n * g2;
+  k_det_reduce<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(sorted_val, offsets, cnt_sorted, inv, pair_grad, n,
+                                                                  g2, capacity, grad2d);
   return hipGetLastError();
 }
 

@@ -205,3 +205,40 @@ def test_band_mode_none(H, W, pitch):
                 assert rel_l2(ref, oracle.propagate(U[0, 0], 515e-9, z, pitch, 2, 1)) > 1e-3
     if pitch > 1e-6:
         assert torch.equal(outs[0], outs[1])
+
+
+def test_deterministic_gradients_are_reproducible():
+    """deterministic=1: the same gradients bit for bit on every run, eager and
+    replayed from a graph, within 1e-5 of the atomic mode and 1e-3 of the
+    oracle (the gradient bar)."""
+    announce("deterministic gradients")
+    sc, cams, opt, tg = _problem(n=600)
+    params = to_device(sc)
+    cam_t = api.pack_cameras(cams)
+    target = torch.from_numpy(tg).cuda()
+    rd = make_renderer(cams, opt, sc.n, deterministic=True)
+    runs = []
+    for _ in range(3):
+        loss, g, _ = rd.train_step(params, cam_t, target)
+        runs.append({k: v.clone() for k, v in g.items()})
+    step = api.CapturedTrainStep(rd, params, cam_t, target)
+    for _ in range(2):
+        _, g = step.replay()
+        runs.append({k: v.clone() for k, v in g.items()})
+    torch.cuda.synchronize()
+    for run in runs[1:]:
+        for k in api.PARAM_NAMES:
+            assert torch.equal(run[k], runs[0][k]), k
+    ra = make_renderer(cams, opt, sc.n)
+    _, ga, _ = ra.train_step(params, cam_t, target)
+    st = oracle.forward(sc, cams, opt, targets=tg)
+    ref = oracle.backward(st)
+    for k in api.PARAM_NAMES:
+        assert rel_l2(runs[0][k].cpu().numpy(), ga[k].cpu().numpy()) < 1e-5, k
+        assert rel_l2(runs[0][k].cpu().numpy(), ref[k]) < 1e-3, k
+
+
+def test_deterministic_layered_plan_is_refused():
+    opt = Optics((515e-9,), (1e-3, 2e-3), 8e-6, 2, 2)
+    with pytest.raises(api._lib.ChrfError):
+        make_renderer([identity_camera(32, 32)], opt, 4, tile=None, layered=True, deterministic=True)
