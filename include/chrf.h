@@ -385,6 +385,26 @@ chrf_status chrf_densify(const chrf_densify_desc* desc, void* scratch, int64_t c
                          void* hip_stream);
 
 /*
+ * chrf_densify for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, outputs and errors as chrf_densify, without the scratch
+ * argument: the scratch comes from a device array that the library holds
+ * per GPU (CHRF_NOALLOC_MAX_GAUSSIANS inputs' worth, about 48 MiB, resident
+ * from the first use on that GPU until the process ends).  The call itself
+ * allocates nothing; chrf_create resolves the array of its device, otherwise
+ * the first call on a device does.  The device is that of hip_stream (the
+ * current device for the null stream).
+ *   CHRF_EINVAL  desc->n > CHRF_NOALLOC_MAX_GAUSSIANS, or as chrf_densify.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (on different streams, or from several threads) race and must be
+ * ordered by the caller.  Nothing in the array has to start at zero.
+ */
+#define CHRF_NOALLOC_MAX_GAUSSIANS 4194304
+chrf_status chrf_densify_noalloc(const chrf_densify_desc* desc, int64_t capacity, int32_t* src, int32_t* kind,
+                                 float* means_out, float* log_scales_out, float* phase_out, int64_t* n_out,
+                                 void* hip_stream);
+
+/*
  * Carries a per-Gaussian array [n][row] through a densification: output row j
  * < min(*n_out, capacity) is in[src[j]], or zero when zero_new != 0 and
  * kind[j] != 0 (fresh optimiser state for new Gaussians).  out has

@@ -39,6 +39,7 @@ EXPORTED = [
     "chrf_backward", "chrf_propagate", "chrf_propagate_adjoint", "chrf_read_status",
     "chrf_timing_enable", "chrf_timing_report", "chrf_phase_only_step", "chrf_adam_step",
     "chrf_adan_step", "chrf_densify_stats", "chrf_densify_workspace_bytes", "chrf_densify", "chrf_gather_rows",
+    "chrf_densify_noalloc",
 ]
 
 
@@ -121,6 +122,7 @@ def load(path: str | None = None):
         "chrf_densify_workspace_bytes": (sz, [i64]),
         "chrf_densify": (i32, [C.POINTER(DensifyDesc), vp, i64, vp, vp, vp, vp, vp, vp, vp]),
         "chrf_gather_rows": (i32, [vp, i64, vp, vp, vp, i64, i32, vp, vp]),
+        "chrf_densify_noalloc": (i32, [C.POINTER(DensifyDesc), i64, vp, vp, vp, vp, vp, vp, vp]),
         "chrf_timing_enable": (i32, [vp, C.c_int]),
         "chrf_timing_report": (i32, [vp, C.c_char_p, sz]),
     }

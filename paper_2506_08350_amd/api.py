@@ -345,12 +345,14 @@ class DensifyConfig:
 
 
 def densify(params: dict, opacity: torch.Tensor, accum: torch.Tensor, count: torch.Tensor, xi: torch.Tensor,
-            zeta: torch.Tensor, cfg: DensifyConfig = DensifyConfig(), capacity=None):
+            zeta: torch.Tensor, cfg: DensifyConfig = DensifyConfig(), capacity=None, noalloc: bool = False):
     """Runs the library's densification.  params holds at least means,
     log_scales, quats and phase (float32 device tensors of n rows); opacity is
     the activated opacity used by the pruning test.  Returns (n_out, src, kind,
     means, log_scales, phase) with the new arrays cut to n_out rows; xi
-    [n, 2, 3] and zeta [n, 2, n_lambda] are standard normal draws."""
+    [n, 2, 3] and zeta [n, 2, n_lambda] are standard normal draws.  noalloc:
+    call the library's allocation-free variant (its scratch is a device array
+    the library holds) instead of passing a scratch buffer."""
     lib = _lib.load()
     n = int(params["means"].shape[0])
     n_lam = int(params["phase"].shape[1])
@@ -369,15 +371,20 @@ def densify(params: dict, opacity: torch.Tensor, accum: torch.Tensor, count: tor
     d.min_opacity = cfg.min_opacity
     d.phase_sigma = cfg.phase_sigma
     d.shrink = cfg.shrink
-    scratch = torch.empty(int(lib.chrf_densify_workspace_bytes(n)), dtype=torch.uint8, device=dev)
+    scratch = None if noalloc else torch.empty(int(lib.chrf_densify_workspace_bytes(n)), dtype=torch.uint8,
+                                               device=dev)
     src = torch.empty(cap, dtype=torch.int32, device=dev)
     kind = torch.empty(cap, dtype=torch.int32, device=dev)
     means = torch.empty((cap, 3), dtype=torch.float32, device=dev)
     log_scales = torch.empty((cap, 3), dtype=torch.float32, device=dev)
     phase = torch.empty((cap, n_lam), dtype=torch.float32, device=dev)
     n_out = torch.empty((), dtype=torch.int64, device=dev)
-    check(lib.chrf_densify(C.byref(d), _ptr(scratch), cap, _ptr(src), _ptr(kind), _ptr(means), _ptr(log_scales),
-                           _ptr(phase), _ptr(n_out), _stream()))
+    if noalloc:
+        check(lib.chrf_densify_noalloc(C.byref(d), cap, _ptr(src), _ptr(kind), _ptr(means), _ptr(log_scales),
+                                       _ptr(phase), _ptr(n_out), _stream()))
+    else:
+        check(lib.chrf_densify(C.byref(d), _ptr(scratch), cap, _ptr(src), _ptr(kind), _ptr(means),
+                               _ptr(log_scales), _ptr(phase), _ptr(n_out), _stream()))
     m = int(n_out)   # synchronises
     if m > cap:
         raise RuntimeError(f"densify: {m} outputs exceed the capacity {cap}")

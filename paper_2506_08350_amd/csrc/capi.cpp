@@ -192,6 +192,46 @@ AsmGeom geom(const chrf_plan* p) {
 
 }  // namespace
 
+// ------------------------------------------------------------ no-alloc ---
+// chrf_densify_noalloc takes its scratch from this array instead of a caller
+// buffer.  Every GPU the library runs on holds its own copy until the process
+// ends; host code must never pass the array's name to a kernel (on the host it
+// is only a stand-in for the symbol): it uses the per-device address that
+// hipGetSymbolAddress returns.
+constexpr int64_t kNoallocMaxN = CHRF_NOALLOC_MAX_GAUSSIANS;
+constexpr size_t kNoallocBytes = ((sizeof(uint32_t) * kNoallocMaxN + 255) & ~size_t(255)) +
+                                 ((sizeof(uint64_t) * kNoallocMaxN + 255) & ~size_t(255)) +
+                                 ((sizeof(uint64_t) * ((kNoallocMaxN + kScanTile - 1) / kScanTile + 1 + 16) + 255) &
+                                  ~size_t(255));
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+std::mutex g_noalloc_mu;
+std::map<int, void*> g_noalloc_ptr;   // device -> address of that device's copy of `scratch`
+
+// Address of `device`'s copy of the array, resolved once per device with that
+// device current (the caller's current device is restored).
+chrf_status noalloc_scratch(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  auto it = g_noalloc_ptr.find(device);
+  if (it != g_noalloc_ptr.end()) {
+    *out = it->second;
+    return CHRF_OK;
+  }
+  int prev = 0;
+  HIP_TRY(hipGetDevice(&prev));
+  HIP_TRY(hipSetDevice(device));
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  HIP_TRY(hipSetDevice(prev));
+  if (e != hipSuccess || !ptr)
+    return fail(CHRF_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_noalloc_ptr[device] = ptr;
+  *out = ptr;
+  return CHRF_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* chrf_last_error(void) { return g_err.c_str(); }
@@ -219,6 +259,14 @@ chrf_status chrf_create(int device, chrf_ctx** out) {
     } else {
       c->lds_per_block -= 1024;
     }
+  }
+  // resolve this device's copy of the allocation-free entry point's scratch
+  // array now, outside any capture the caller may start later
+  void* scratch_ptr = nullptr;
+  const chrf_status st = noalloc_scratch(device, &scratch_ptr);
+  if (st != CHRF_OK) {
+    delete c;
+    return st;
   }
   *out = c;
   return CHRF_OK;
@@ -899,6 +947,24 @@ chrf_status chrf_densify(const chrf_densify_desc* d, void* scratch, int64_t capa
                          reinterpret_cast<uint64_t*>(base + ds.tmp), reinterpret_cast<uint64_t*>(n_out),
                          (hipStream_t)hip_stream));
   return CHRF_OK;
+}
+
+chrf_status chrf_densify_noalloc(const chrf_densify_desc* d, int64_t capacity, int32_t* src, int32_t* kind,
+                                 float* means_out, float* log_scales_out, float* phase_out, int64_t* n_out,
+                                 void* hip_stream) {
+  if (!d) return fail(CHRF_EINVAL, "chrf_densify_noalloc: NULL argument");
+  if (d->n > kNoallocMaxN)
+    return fail(CHRF_EINVAL, "chrf_densify_noalloc: n = " + std::to_string(d->n) + " exceeds the maximum " +
+                                 std::to_string(kNoallocMaxN) + " of the library's scratch array");
+  int device = 0;
+  if (hip_stream)
+    HIP_TRY(hipStreamGetDevice((hipStream_t)hip_stream, &device));
+  else
+    HIP_TRY(hipGetDevice(&device));
+  void* ptr = nullptr;
+  const chrf_status st = noalloc_scratch(device, &ptr);
+  if (st != CHRF_OK) return st;
+  return chrf_densify(d, ptr, capacity, src, kind, means_out, log_scales_out, phase_out, n_out, hip_stream);
 }
 
 chrf_status chrf_gather_rows(const float* in, int64_t row, const int32_t* src, const int32_t* kind,
