@@ -580,6 +580,7 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
   pa.tiles_x = plan->tiles_x;
   pa.tiles_y = plan->tiles_y;
   pa.k_sigma = plan->d.k_sigma;
+  pa.alpha_min = plan->d.alpha_min;
   pa.rec_g0 = at<float4>(plan, ws, R_G0);
   pa.rec_g1 = at<float4>(plan, ws, R_G1);
   pa.rec_rect = at<int4>(plan, ws, R_RECT);

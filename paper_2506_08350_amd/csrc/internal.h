@@ -41,6 +41,7 @@ struct ProjArgs {
   int width, height;
   int tile_w, tile_h, tiles_x, tiles_y;
   float k_sigma;
+  float alpha_min;      // support threshold on a (bounds the support ellipse stored in rec_g1.z)
   float4* rec_g0;
   float4* rec_g1;
   int4* rec_rect;

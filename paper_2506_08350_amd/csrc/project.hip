@@ -110,8 +110,15 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
     const int tx0 = c0 / a.tile_w, tx1 = c1 / a.tile_w, ty0 = r0 / a.tile_h, ty1 = r1 / a.tile_h;
     cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
     const float A_ = syy / det, B_ = -sxy / det, C_ = sxx / det;
+    // Largest power at which the Gaussian can still support a pixel:
+    // power <= k^2 / 2, and o exp(-power) >= alpha_min (alpha_min < alpha_max)
+    // means power <= ln(o / alpha_min).  The raster kernels use it only to
+    // skip 8x8 blocks that the ellipse cannot reach.
+    const float op = a.opacity[g];
+    const float half_k2 = 0.5f * a.k_sigma * a.k_sigma;
+    const float pmax = a.alpha_min > 0.0f ? fminf(half_k2, logf(op / a.alpha_min)) : half_k2;
     a.rec_g0[rid] = make_float4(mux, muy, A_, B_);
-    a.rec_g1[rid] = make_float4(C_, a.opacity[g], 0.0f, 0.0f);
+    a.rec_g1[rid] = make_float4(C_, op, pmax, 0.0f);
     a.rec_rect[rid] = make_int4(c0, c1 - c0, r0, r1 - r0);
   }
   a.count[rid] = cnt;

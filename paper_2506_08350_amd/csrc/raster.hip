@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_fwd(RasterArgs a) {
     uint64_t hits[PPT], todo = 0;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-      hits[p] = block_hits(st.rc, 0, cnt, bx[p], by[p]);
+      hits[p] = block_hits(st.g0, st.g1, st.rc, 0, cnt, bx[p], by[p]);
       todo |= hits[p];
     }
     if (__all(all_done)) todo = 0;   // a finished wave only keeps the barriers
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
     uint64_t hits[PPT], todo = 0;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-      hits[p] = block_hits(st.rc, j0, cnt, bx[p], by[p]);
+      hits[p] = block_hits(st.g0, st.g1, st.rc, j0, cnt, bx[p], by[p]);
       todo |= hits[p];
     }
     while (todo) {

@@ -37,20 +37,47 @@ __device__ inline void block_of(const RasterArgs& a, const TileGeom& t, int p, i
   by = t.ty * a.tile_h + (p / bpr) * 8;
 }
 
-// Does the support rectangle rc = (c0, c1 - c0, r0, r1 - r0) reach the 8x8
-// block at (bx, by)?  Uniform over the wave, so a miss skips the block's
-// pixel work for every lane.
-__device__ inline bool rect_hits_block(const int4& rc, int bx, int by) {
-  return rc.x <= bx + 7 && bx <= rc.x + rc.y && rc.z <= by + 7 && by <= rc.z + rc.w;
+// Can the Gaussian support any pixel of the 8x8 block at (bx, by)?  A pixel
+// is supported only inside the support rectangle rc = (c0, c1 - c0, r0,
+// r1 - r0) and where power = d^T conic d / 2 <= pmax (g1.z, set by the
+// projection; d = pixel centre - mu).  The test takes the minimum of the
+// quadratic form over the box of pixel centres that lie in both the block
+// and the rectangle: zero if mu is inside the box, else the smaller of its
+// minima along the box edges that face mu (the minimiser of a positive
+// definite form over a box that excludes its centre lies on such an edge).
+// The margin covers the rounding of the per-pixel power and of this bound,
+// so no block holding a supported pixel is ever skipped; a skipped block
+// would have taken alpha = 0 at every pixel.
+__device__ inline bool support_hits_block(const float4& g0, const float4& g1, const int4& rc, int bx, int by) {
+  const int xlo = max(bx, rc.x), xhi = min(bx + 7, rc.x + rc.y);
+  const int ylo = max(by, rc.z), yhi = min(by + 7, rc.z + rc.w);
+  if (xlo > xhi || ylo > yhi) return false;
+  const float x0 = ((float)xlo + 0.5f) - g0.x, x1 = ((float)xhi + 0.5f) - g0.x;
+  const float y0 = ((float)ylo + 0.5f) - g0.y, y1 = ((float)yhi + 0.5f) - g0.y;
+  const float A = g0.z, B = g0.w, C = g1.x;
+  const bool xin = x0 <= 0.f && x1 >= 0.f, yin = y0 <= 0.f && y1 >= 0.f;
+  // minimum along the vertical edge facing mu: x = xe, y = -B xe / C clamped
+  const float xe = x0 > 0.f ? x0 : x1;
+  const float ys = fminf(fmaxf(-B * xe * __builtin_amdgcn_rcpf(C), y0), y1);
+  const float qx = 0.5f * (A * xe * xe + C * ys * ys) + B * xe * ys;
+  // and along the horizontal edge facing mu
+  const float ye = y0 > 0.f ? y0 : y1;
+  const float xs = fminf(fmaxf(-B * ye * __builtin_amdgcn_rcpf(A), x0), x1);
+  const float qy = 0.5f * (A * xs * xs + C * ye * ye) + B * xs * ye;
+  const float lb = xin ? (yin ? 0.f : qy) : (yin ? qx : fminf(qx, qy));
+  const float xm = fmaxf(-x0, x1), ym = fmaxf(-y0, y1);   // largest |dx|, |dy| over the box
+  const float mag = 0.5f * (A * xm * xm + C * ym * ym) + fabsf(B) * xm * ym;
+  return !(lb > g1.z + 1e-4f + 4e-6f * mag);   // NaN: not skipped
 }
 
-// Bit j: staged pair j, j_first <= j < cnt, has a support rectangle reaching
-// the 8x8 block at (bx, by).  Lane j tests pair j; the mask is wave-uniform,
-// so the pair walk visits only the set bits, in order, with scalar control.
-__device__ inline uint64_t block_hits(const int4* rc, int j_first, int cnt, int bx, int by) {
+// Bit j: staged pair j, j_first <= j < cnt, can support a pixel of the 8x8
+// block at (bx, by).  Lane j tests pair j; the mask is wave-uniform, so the
+// pair walk visits only the set bits, in order, with scalar control.
+__device__ inline uint64_t block_hits(const float4* g0, const float4* g1, const int4* rc, int j_first, int cnt,
+                                      int bx, int by) {
   const int lane = threadIdx.x & 63;
   bool h = false;
-  if (lane >= j_first && lane < cnt) h = rect_hits_block(rc[lane], bx, by);
+  if (lane >= j_first && lane < cnt) h = support_hits_block(g0[lane], g1[lane], rc[lane], bx, by);
   return __ballot(h);
 }
 

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(64 * NWAVE, 8) void k_raster_layers_fwd(RasterArgs 
 #pragma unroll
       for (int q = 0; q < NLAY; ++q)
         if (__any((live >> q) & 1u)) wave_live |= 1u << q;
-      uint64_t todo = block_hits(st.s.rc, 0, cnt, bx, by);
+      uint64_t todo = block_hits(st.s.g0, st.s.g1, st.s.rc, 0, cnt, bx, by);
       const int lane = threadIdx.x & 63;
       todo &= __ballot(lane < cnt && ((wave_live >> (st.lay[lane] & 7)) & 1u));
       while (todo) {
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(64 * NWAVE, 4) void k_raster_layers_bwd(RasterArgs 
     if (top - cnt < wave_last) {   // this wave has work in the batch
       // pairs at or past wave_last touch none of this wave's pixels
       const int j0 = top > wave_last ? (int)min(top - wave_last, (uint32_t)cnt) : 0;
-      uint64_t todo = block_hits(st.s.rc, j0, cnt, bx, by);
+      uint64_t todo = block_hits(st.s.g0, st.s.g1, st.s.rc, j0, cnt, bx, by);
       while (todo) {
         const int j = (int)__builtin_ctzll(todo);
         todo &= todo - 1;
