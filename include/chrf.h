@@ -157,6 +157,15 @@ typedef struct chrf_grads {
  *                      order, as always).  Costs workspace of about
  *                      4 (2 + per-Gaussian row length) bytes per pair and
  *                      two extra passes over it.
+ *   fft_rows_plan      radix schedule of the row transforms when the padded
+ *                      width is 3840 (0: 16*16*15, 1: 16*15*16, 2: 15*16*16);
+ *                      must be 0 for other widths
+ *   fft_cols_plan      radix schedule of the column transforms when the
+ *                      padded height is 2160 and cols_per_block is 2 (0:
+ *                      16*15*9, 1: 16*9*15, 2: 15*16*9, 3: 12*12*15, forward
+ *                      stage order); must be 0 otherwise.  Schedules change
+ *                      rounding only (CHRF_EUNSUPPORTED for a value out of
+ *                      range); the autotuner picks them.
  */
 typedef struct chrf_plan_desc {
   int32_t height, width;
@@ -176,7 +185,7 @@ typedef struct chrf_plan_desc {
   float ssim_weight;
   int32_t phase_only;
   int32_t deterministic;
-  int32_t reserved[2];
+  int32_t fft_rows_plan, fft_cols_plan;
 } chrf_plan_desc;
 
 /* Named regions of the workspace, for inspection by tests and tools. */

@@ -66,7 +66,8 @@ class PlanDesc(C.Structure):
                 ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
                 ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("cols_per_block", C.c_int32),
                 ("layered", C.c_int32), ("loss_kind", C.c_int32), ("ssim_weight", C.c_float),
-                ("phase_only", C.c_int32), ("deterministic", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("phase_only", C.c_int32), ("deterministic", C.c_int32), ("fft_rows_plan", C.c_int32),
+                ("fft_cols_plan", C.c_int32)]
 
 
 class DensifyDesc(C.Structure):

@@ -90,19 +90,21 @@ class Renderer:
     def __init__(self, height, width, optics: Optics, n_views=1, max_gaussians=1, n_lambda=None,
                  max_pairs=0, k_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
                  tile=None, cols_per_block=0, layered=False, loss="mse", ssim_weight=0.005, phase_only=False,
-                 deterministic=False, device=0):
+                 deterministic=False, fft_plans=(0, 0), device=0):
         """layered=True: multi-layer hologram with one layer per entry of
         optics.distances (the layer-to-hologram distances Z_l); the Gaussians
         then carry "logits" [N, layers] and the forward's "field" is the
         recorded hologram P.  loss: "mse" (Eq. 17) or "paper" (the masked
         three-term reconstruction loss plus ssim_weight * (1 - SSIM)).
         deterministic=True: gradients reproducible bit for bit (per-pair rows
-        summed in a fixed order instead of float atomics; single-plane only)."""
+        summed in a fixed order instead of float atomics; single-plane only).
+        fft_plans: (row, column) radix schedules of the tuned transforms
+        (chrf_plan_desc.fft_rows_plan / fft_cols_plan; 0 = default)."""
         self._config = dict(height=height, width=width, optics=optics, n_views=n_views, max_gaussians=max_gaussians,
                             n_lambda=n_lambda, max_pairs=max_pairs, k_sigma=k_sigma, alpha_min=alpha_min,
                             alpha_max=alpha_max, t_min=t_min, tile=tile, cols_per_block=cols_per_block,
                             layered=layered, loss=loss, ssim_weight=ssim_weight, phase_only=phase_only,
-                            deterministic=deterministic, device=device)
+                            deterministic=deterministic, fft_plans=tuple(fft_plans), device=device)
         self.ctx = context(device)
         self.lib = self.ctx.lib
         d = _lib.PlanDesc()
@@ -132,6 +134,7 @@ class Renderer:
         d.ssim_weight = float(ssim_weight)
         d.phase_only = 1 if phase_only else 0
         d.deterministic = 1 if deterministic else 0
+        d.fft_rows_plan, d.fft_cols_plan = int(fft_plans[0]), int(fft_plans[1])
         self.loss = loss
         self.desc = d
         h = C.c_void_p()

@@ -1,11 +1,15 @@
 """Autotuner for the launch configuration of one workload shape.
 
-Candidates are (raster tile shape, columns per workgroup of the column FFT
-pass).  Each candidate builds a plan, runs the fused training step a few
-times and is timed with HIP events on the launch stream (median of the
-timed repetitions); the fastest is kept.  Results persist in a JSON cache
-keyed by the device architecture and the workload shape, so a later process
-reuses them without timing again.
+The searched configuration is the raster tile shape, the columns per
+workgroup of the column FFT pass and, where the padded grid has tuned
+transforms (width 3840, height 2160), the radix schedules of the row and of
+the column transforms.  Each candidate builds a plan, runs the fused training
+step a few times and is timed with HIP events on the launch stream (median of
+the timed repetitions).  The search is coordinate-wise: the tile with the
+default transforms first, then the columns per workgroup, then the row
+schedule, then the column schedule, each keeping the best of the earlier
+steps.  Results persist in a JSON cache keyed by the device architecture and
+the workload shape, so a later process reuses them without timing again.
 """
 from __future__ import annotations
 
@@ -20,7 +24,9 @@ from . import api
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "chrf_autotune.json")
 
 TILES = ((16, 16), (16, 8), (8, 16), (32, 8), (8, 8))
-COLS = (4, 2, 1)
+COLS = (2, 4, 1)
+ROW_PLANS = (0, 1, 2)       # 3840: 16*16*15, 16*15*16, 15*16*16
+COL_PLANS = (0, 1, 2, 3)    # 2160: 16*15*9, 16*9*15, 15*16*9, 12*12*15 (two columns per workgroup)
 
 
 def shape_key(height, width, n_lambda, n_planes, n_views, n_gaussians, pad):
@@ -45,10 +51,11 @@ def _store(path, data):
     os.replace(tmp, path)
 
 
-def time_config(height, width, optics, params, cams, target, tile, cols, max_pairs, reps=5, warmup=2, **plan_kw):
-    """Median milliseconds of one fused training step for one configuration."""
+def time_config(height, width, optics, params, cams, target, max_pairs, reps=5, warmup=2, **plan_kw):
+    """Median milliseconds of one fused training step for one configuration
+    (plan_kw: Renderer keyword arguments, e.g. tile, cols_per_block, fft_plans)."""
     r = api.Renderer(height, width, optics, n_views=cams.shape[0], max_gaussians=params["means"].shape[0],
-                     max_pairs=max_pairs, tile=tile, cols_per_block=cols, **plan_kw)
+                     max_pairs=max_pairs, **plan_kw)
     for _ in range(warmup):
         r.train_step(params, cams, target)
     st, need = r.read_status()
@@ -64,33 +71,71 @@ def time_config(height, width, optics, params, cams, target, tile, cols, max_pai
         b.record(stream)
         b.synchronize()
         times.append(a.elapsed_time(b))
+    del r
     return statistics.median(times)
 
 
+def _jsonable(cfg):
+    return {k: list(v) if isinstance(v, tuple) else v for k, v in cfg.items()}
+
+
+def _from_json(d):
+    return {"tile": tuple(d["tile"]), "cols_per_block": int(d["cols_per_block"]),
+            "fft_plans": tuple(d.get("fft_plans", (0, 0)))}
+
+
 def autotune(height, width, optics, params, cams, target, max_pairs, cache=DEFAULT_CACHE, tiles=TILES, cols=COLS,
-             force=False, **plan_kw):
-    """Best (tile, cols_per_block) for this shape; cached across processes."""
+             row_plans=ROW_PLANS, col_plans=COL_PLANS, force=False, **plan_kw):
+    """Best configuration for this shape, as Renderer keyword arguments
+    {tile, cols_per_block, fft_plans}, and the cache entry with every timed
+    candidate; cached across processes unless cache is None."""
     key = shape_key(height, width, len(optics.wavelengths), len(optics.distances), cams.shape[0],
                     params["means"].shape[0], optics.pad)
     data = _load(cache) if cache else {}
     if not force and key in data:
-        d = data[key]
-        return tuple(d["tile"]), int(d["cols_per_block"]), d
+        return _from_json(data[key]), data[key]
     results = []
-    for t in tiles:
-        for c in cols:
-            try:
-                ms = time_config(height, width, optics, params, cams, target, t, c, max_pairs, **plan_kw)
-            except Exception as exc:   # unsupported candidate for this shape
-                results.append({"tile": list(t), "cols_per_block": c, "error": str(exc)})
-                continue
-            results.append({"tile": list(t), "cols_per_block": c, "ms": ms})
+
+    def trial(cfg):
+        for r in results:
+            if r["config"] == _jsonable(cfg):
+                return r.get("ms")
+        try:
+            ms = time_config(height, width, optics, params, cams, target, max_pairs, **cfg, **plan_kw)
+        except Exception as exc:   # a candidate this shape or build does not support
+            results.append({"config": _jsonable(cfg), "error": str(exc)})
+            return None
+        results.append({"config": _jsonable(cfg), "ms": ms})
+        return ms
+
+    best = {"tile": tuple(tiles[0]), "cols_per_block": cols[0], "fft_plans": (0, 0)}
+
+    def with_value(axis, v):
+        cfg = dict(best)
+        if axis == "row_plan":
+            cfg["fft_plans"] = (v, best["fft_plans"][1])
+        elif axis == "col_plan":
+            cfg["fft_plans"] = (best["fft_plans"][0], v)
+        else:
+            cfg[axis] = v
+        return cfg
+
+    for axis, values in (("tile", [tuple(t) for t in tiles]), ("cols_per_block", list(cols)),
+                         ("row_plan", list(row_plans)), ("col_plan", list(col_plans))):
+        scored = []
+        for v in values:
+            cfg = with_value(axis, v)
+            ms = trial(cfg)
+            if ms is not None:
+                scored.append((ms, cfg))
+        if scored:
+            best = min(scored, key=lambda t: t[0])[1]
     ok = [r for r in results if "ms" in r]
     if not ok:
         raise RuntimeError("no candidate configuration ran")
-    best = min(ok, key=lambda r: r["ms"])
-    entry = {"tile": best["tile"], "cols_per_block": best["cols_per_block"], "ms": best["ms"], "candidates": results}
+    best_ms = min(r["ms"] for r in ok if r["config"] == _jsonable(best))
+    entry = dict(_jsonable(best), ms=best_ms, candidates=results)
     if cache:
         data[key] = entry
         _store(cache, data)
-    return tuple(best["tile"]), int(best["cols_per_block"]), entry
+    return best, entry

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_rows_forward_t(const float2* __restrict
 #pragma unroll
     for (int r = 0; r < RT::R1; ++r) {
       const int e = j + r * RT::S1;
-      const bool live = HALF ? r < RT::R1 / 2 : e < g.W;
+      const bool live = (HALF && RT::R1 % 2 == 0) ? r < RT::R1 / 2 : e < g.W;
       v1[0][r] = live ? ldc(src + e) : cpx{0.f, 0.f};
     }
   }
@@ -152,13 +152,13 @@ __global__ __launch_bounds__(256) void k_rows_inverse_t(float2* __restrict__ y, 
     for (int r = 0; r < RT::R1; ++r) v1[0][r] = ldc(yrow + j + r * RT::S1);
   }
   RT::Inv::run(v1, v3, lds, fr.tw);
-  // v3[0][q] = u at column j + q * 256
+  // v3[0][q] = u at column j + q * S3 (threads j >= S3 hold no outputs)
   const size_t ob = row * (size_t)g.W;
   float lsum = 0.f;
 #pragma unroll
   for (int q = 0; q < RT::R3; ++q) {
     const int e = j + q * RT::S3;
-    if (!(HALF && q * RT::S3 >= RT::N / 2) && e < g.W) {
+    if (j < RT::S3 && !(HALF && q * RT::S3 >= RT::N / 2) && e < g.W) {
       const cpx u = v3[0][q];
       if (prop_out) stc(prop_out + ob + e, u);
       const float I = u.x * u.x + u.y * u.y;
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(256) void k_rows_adjoint_in_t(const float2* __restr
     for (int r = 0; r < RT::R1; ++r) {
       const int e = j + r * RT::S1;
       cpx G{0.f, 0.f};
-      if (HALF ? r < RT::R1 / 2 : e < g.W) {
+      if ((HALF && RT::R1 % 2 == 0) ? r < RT::R1 / 2 : e < g.W) {
         if (dL_dI) G = ldc(prop + ob + e) * (2.0f * dL_dI[ob + e]);
         if (dL_dprop) G = G + ldc(dL_dprop + ob + e);
       }
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void k_rows_adjoint_out_t(const float2* __rest
 #pragma unroll
   for (int q = 0; q < RT::R3; ++q) {
     const int e = j + q * RT::S3;
-    if (!(HALF && q * RT::S3 >= RT::N / 2) && e < g.W) {
+    if (j < RT::S3 && !(HALF && q * RT::S3 >= RT::N / 2) && e < g.W) {   // threads j >= S3 hold no outputs
       cpx v = v3[0][q];
       if (dL_dfield) v = v + ldc(dL_dfield + ob + e);
       stc(grad_field + ob + e, v);
@@ -256,17 +256,25 @@ __global__ __launch_bounds__(256) void k_rows_adjoint_out_t(const float2* __rest
 //          workgroups share a CU.
 constexpr int kColN = 2160;
 
-template <int C>
+// R1 R2 R3: radices of the forward column transform in stage order; the
+// inverse runs them in reverse order, so that each thread's R3 forward
+// outputs are the inputs of its inverse butterfly.
+template <int C_, int R1_ = 16, int R2_ = 15, int R3_ = 9>
 struct ColT {
+  static constexpr int C = C_, R1 = R1_, R2 = R2_, R3 = R3_;
   static constexpr int NT = 256 * C;
-  using Fwd = Fft3<kColN, C, NT, 16, 15, 9, false>;
-  using Inv = Fft3<kColN, C, NT, 9, 15, 16, true>;
+  static constexpr int S1 = kColN / R1, S3 = kColN / R3;
+  using Fwd = Fft3<kColN, C, NT, R1, R2, R3, false>;
+  using Inv = Fft3<kColN, C, NT, R3, R2, R1, true>;
   static_assert(Fwd::M1 == 1 && Fwd::M3 == 1 && Inv::M1 == 1 && Inv::M3 == 1, "one butterfly per thread");
   static_assert(Fwd::B3 == Inv::B1, "forward outputs feed the inverse inputs");
   static constexpr int SPAN = 128 / (8 * C);   // column groups per 128-byte line
   static constexpr bool kRegSpec = C <= 2;      // spectrum in registers, twiddles from memory
   static constexpr bool kLdsTw = !kRegSpec;     // twiddle table in LDS, read per power
   static constexpr int kMinBlocks = C == 1 ? 4 : (C == 2 ? 2 : 1);
+  // half-height field: input (and kept output) r of a first-stage butterfly
+  // is a field row iff r < R1 / 2 when R1 is even; otherwise decided per row
+  static constexpr bool kEvenSplit = R1 % 2 == 0;
 };
 
 __device__ inline int col_remap(int id, int nblocks, int span) {
@@ -288,15 +296,16 @@ __device__ inline const cpx* stage_twiddles(cpx* s_tw, const cpx* __restrict__ t
   return s_tw;
 }
 
-template <int C, bool HALF>
-__global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forward_t(
-    const float2* __restrict__ x1, float2* __restrict__ y, AsmGeom g, FftDesc fc) {
-  using CT = ColT<C>;
+template <class CT, bool HALF>
+__global__ __launch_bounds__(CT::NT, CT::kMinBlocks) void k_cols_forward_t(const float2* __restrict__ x1,
+                                                                          float2* __restrict__ y, AsmGeom g,
+                                                                          FftDesc fc) {
+  constexpr int C = CT::C, R1 = CT::R1, R3 = CT::R3;
   __shared__ cpx lds[lds_padded_size(kColN * C)];
   __shared__ cpx spec[CT::kRegSpec ? 1 : kColN * C];
   __shared__ cpx s_tw[CT::kLdsTw ? kColN : 1];
   const cpx* twl = CT::kLdsTw ? stage_twiddles<CT::NT>(s_tw, fc.tw) : fc.tw;
-  cpx sreg[CT::kRegSpec ? 9 : 1];
+  cpx sreg[CT::kRegSpec ? R3 : 1];
   const int ngroups = g.pW / C;
   const int gid = col_remap(blockIdx.x, gridDim.x, CT::SPAN);
   const int bl = gid / ngroups;
@@ -304,14 +313,14 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
   const int lam = bl % g.n_lambda;
   const int b = threadIdx.x;
   const int s = b % C, j = b / C;
-  float qv[9];   // plane-independent transfer terms of this thread's 9 bins
+  float qv[R3];   // plane-independent transfer terms of this thread's R3 bins
   {
-    cpx v1[1][16], v3[1][9];
+    cpx v1[1][R1], v3[1][R3];
     if (b < CT::Fwd::B1) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int n = j + r * (kColN / 16);
-        const bool live = HALF ? r < 8 : n < g.H;
+      for (int r = 0; r < R1; ++r) {
+        const int n = j + r * CT::S1;
+        const bool live = (HALF && CT::kEvenSplit) ? r < R1 / 2 : n < g.H;
         v1[0][r] = live ? ldc(x1 + ((size_t)bl * g.H + n) * g.pW + c0 + s) : cpx{0.f, 0.f};
       }
     }
@@ -320,12 +329,12 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
       const HParam hp0 = load_hparam(g.hp, lam * g.K);
       const ColFreq cf = col_freq(hp0, c0 + s, g);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) qv[q] = transfer_q(hp0, cf, j + q * (kColN / 9), g);
+      for (int q = 0; q < R3; ++q) qv[q] = transfer_q(hp0, cf, j + q * CT::S3, g);
     }
     CT::Fwd::template run<CT::kLdsTw>(v1, v3, lds, twl);
     if (b < CT::Fwd::B3) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
+      for (int q = 0; q < R3; ++q) {
         if constexpr (CT::kRegSpec)
           sreg[q] = v3[0][q] * g.norm;
         else
@@ -339,13 +348,13 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
   for (int k = 0; k < g.K; ++k) {
     const HParam hp = load_hparam(g.hp, lam * g.K + k);
     const int jj = opaque_v(j), kx = opaque_v(c0 + s);
-    cpx w1[1][9], w3[1][16];
+    cpx w1[1][R3], w3[1][R1];
     if (b < CT::Inv::B1) {
       const bool col_pass = g.band_mode < 2 || abs(sbin(kx, g.pW)) <= hp.kx_max;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
+      for (int q = 0; q < R3; ++q) {
         const cpx sv = CT::kRegSpec ? sreg[CT::kRegSpec ? q : 0] : spec[b + q * CT::Inv::B1];
-        w1[0][q] = cmul(sv, transfer_from_q(hp, col_pass, qv[q], jj + q * (kColN / 9), g));
+        w1[0][q] = cmul(sv, transfer_from_q(hp, col_pass, qv[q], jj + q * CT::S3, g));
       }
     }
     if constexpr (CT::kLdsTw)
@@ -355,9 +364,9 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
     if (b < CT::Inv::B3) {
       float2* yk = y + ((size_t)bl * g.K + k) * g.H * g.pW + kx;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int n = jj + q * (kColN / 16);
-        if (HALF ? q < 8 : n < g.H) stc(yk + (size_t)n * g.pW, w3[0][q]);
+      for (int q = 0; q < R1; ++q) {
+        const int n = jj + q * CT::S1;
+        if ((HALF && CT::kEvenSplit) ? q < R1 / 2 : n < g.H) stc(yk + (size_t)n * g.pW, w3[0][q]);
       }
     }
   }
@@ -372,10 +381,11 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_forwa
 typedef __attribute__((address_space(1))) void gmem_void;
 typedef __attribute__((address_space(3))) void lds_void;
 
-template <int C, bool HALF>
-__global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoint_t(
-    const float2* __restrict__ z, float2* __restrict__ w1out, AsmGeom g, FftDesc fc) {
-  using CT = ColT<C>;
+template <class CT, bool HALF>
+__global__ __launch_bounds__(CT::NT, CT::kMinBlocks) void k_cols_adjoint_t(const float2* __restrict__ z,
+                                                                          float2* __restrict__ w1out, AsmGeom g,
+                                                                          FftDesc fc) {
+  constexpr int C = CT::C, R1 = CT::R1, R3 = CT::R3;
   constexpr bool kDma = HALF && C == 2;
   constexpr int kLiveRows = kColN / 2;
   __shared__ cpx lds[lds_padded_size(kColN * C)];
@@ -389,12 +399,12 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoi
   const int lam = bl % g.n_lambda;
   const int b = threadIdx.x;
   const int s = b % C, j = b / C;
-  cpx acc[1][9];
+  cpx acc[1][R3];
 #pragma unroll
-  for (int q = 0; q < 9; ++q) acc[0][q] = cpx{0.f, 0.f};
-  // plane-independent transfer terms of this thread's 9 bins, kept in LDS
+  for (int q = 0; q < R3; ++q) acc[0][q] = cpx{0.f, 0.f};
+  // plane-independent transfer terms of this thread's R3 bins, kept in LDS
   // (each thread reads back only its own entries) to spare registers
-  __shared__ float s_q[9][CT::NT];
+  __shared__ float s_q[R3][CT::NT];
   // wave w copies rows 64 i .. 64 i + 63 for i = w, w + NT / 64, ...
   auto copy_plane = [&](int k) {
     if constexpr (kDma) {
@@ -418,22 +428,24 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoi
     const HParam hp0 = load_hparam(g.hp, lam * g.K);
     const ColFreq cf = col_freq(hp0, c0 + s, g);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) s_q[q][b] = transfer_q(hp0, cf, j + q * (kColN / 9), g);
+    for (int q = 0; q < R3; ++q) s_q[q][b] = transfer_q(hp0, cf, j + q * CT::S3, g);
   }
   if constexpr (kDma) copies_visible();   // the terms above were formed while plane 0 arrived
   for (int k = 0; k < g.K; ++k) {
     const float2* zk = z + ((size_t)bl * g.K + k) * g.H * g.pW + c0 + s;
     const int jj = opaque_v(j), kx = opaque_v(c0 + s);
     const HParam hp = load_hparam(g.hp, lam * g.K + k);
-    cpx v1[1][16], v3[1][9];
+    cpx v1[1][R1], v3[1][R3];
     if (b < CT::Fwd::B1) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int n = jj + r * (kColN / 16);
+      for (int r = 0; r < R1; ++r) {
+        const int n = jj + r * CT::S1;
+        const bool live = CT::kEvenSplit ? r < R1 / 2 : n < kLiveRows;
         if constexpr (kDma) {
-          v1[0][r] = r < 8 ? s_in[(r < 8 ? n : 0) * C + s] : cpx{0.f, 0.f};
+          v1[0][r] = live ? s_in[(live ? n : 0) * C + s] : cpx{0.f, 0.f};
         } else {
-          v1[0][r] = (HALF ? r < 8 : n < g.H) ? ldc(zk + (size_t)n * g.pW) : cpx{0.f, 0.f};
+          v1[0][r] = ((HALF && CT::kEvenSplit) ? r < R1 / 2 : n < g.H) ? ldc(zk + (size_t)n * g.pW)
+                                                                       : cpx{0.f, 0.f};
         }
       }
     }
@@ -446,110 +458,141 @@ __global__ __launch_bounds__(ColT<C>::NT, ColT<C>::kMinBlocks) void k_cols_adjoi
     if (b < CT::Fwd::B3) {
       const bool col_pass = g.band_mode < 2 || abs(sbin(kx, g.pW)) <= hp.kx_max;
 #pragma unroll
-      for (int q = 0; q < 9; ++q)
-        acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_from_q(hp, col_pass, s_q[q][b], jj + q * (kColN / 9), g));
+      for (int q = 0; q < R3; ++q)
+        acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_from_q(hp, col_pass, s_q[q][b], jj + q * CT::S3, g));
     }
     if constexpr (kDma)
       if (k + 1 < g.K) copies_visible();
   }
 #pragma unroll
-  for (int q = 0; q < 9; ++q) acc[0][q] = acc[0][q] * g.norm;
-  cpx w3[1][16];
+  for (int q = 0; q < R3; ++q) acc[0][q] = acc[0][q] * g.norm;
+  cpx w3[1][R1];
   CT::Inv::template run<CT::kLdsTw>(acc, w3, lds, twl);
   if (b < CT::Inv::B3) {
     float2* dst = w1out + (size_t)bl * g.H * g.pW + c0 + s;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int n = j + q * (kColN / 16);
-      if (HALF ? q < 8 : n < g.H) stc(dst + (size_t)n * g.pW, w3[0][q]);
+    for (int q = 0; q < R1; ++q) {
+      const int n = j + q * CT::S1;
+      if ((HALF && CT::kEvenSplit) ? q < R1 / 2 : n < g.H) stc(dst + (size_t)n * g.pW, w3[0][q]);
     }
   }
 }
 
+// Radix schedules of the tuned transforms (AsmGeom::row_plan, col_plan):
+//   rows of 3840:     0: 16 16 15   1: 16 15 16   2: 15 16 16
+//   columns of 2160:  0: 16 15 9    1: 16 9 15    2: 15 16 9    3: 12 12 15
+// (forward stage order).  Every schedule keeps one butterfly per thread in
+// the first and the last stage.
 using Row3840 = RowT<3840, 256, 16, 16, 15>;
 
 bool tuned_rows(const AsmGeom& g) { return g.pW == 3840; }
 // (band mode 0 with evanescent bins present needs the decaying continuation,
 // which only the generic passes form)
 bool tuned_cols(const AsmGeom& g) { return g.pH == kColN && g.pW % 128 == 0 && !(g.band_mode == 0 && g.evanescent); }
+int tuned_row_plans() { return 3; }
+int tuned_col_plans() { return 4; }
 
 static bool rows_half(const AsmGeom& g) { return 2 * g.W == g.pW; }
 static bool cols_half(const AsmGeom& g) { return 2 * g.H == g.pH; }
 
+// Calls f(RT{}) with the row transform type of the plan's radix schedule.
+template <class F>
+static hipError_t with_row_plan(const AsmGeom& g, F&& f) {
+  switch (g.row_plan) {
+    case 1: f(RowT<3840, 256, 16, 15, 16>{}); break;
+    case 2: f(RowT<3840, 256, 15, 16, 16>{}); break;
+    default: f(Row3840{}); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_rows_forward_t(const float2* in, float2* out, const AsmGeom& g, const FftDesc& fr, hipStream_t s) {
   const unsigned grid = (unsigned)(g.n_bl * g.H);
-  if (rows_half(g))
-    k_rows_forward_t<Row3840, true><<<grid, 256, 0, s>>>(in, out, g, fr);
-  else
-    k_rows_forward_t<Row3840, false><<<grid, 256, 0, s>>>(in, out, g, fr);
-  return hipGetLastError();
+  return with_row_plan(g, [&](auto rt) {
+    using RT = decltype(rt);
+    if (rows_half(g))
+      k_rows_forward_t<RT, true><<<grid, 256, 0, s>>>(in, out, g, fr);
+    else
+      k_rows_forward_t<RT, false><<<grid, 256, 0, s>>>(in, out, g, fr);
+  });
 }
 hipError_t launch_rows_inverse_t(float2* y, const AsmGeom& g, const FftDesc& fr, float2* prop_out, float* intensity,
                                  const float* target, float* loss_partial, float grad_coef, bool fuse, hipStream_t s) {
   const unsigned grid = (unsigned)(g.n_bl * g.K * g.H);
-  if (rows_half(g))
-    k_rows_inverse_t<Row3840, true><<<grid, 256, 0, s>>>(y, g, fr, prop_out, intensity, target, loss_partial,
-                                                         grad_coef, fuse ? 1 : 0);
-  else
-    k_rows_inverse_t<Row3840, false><<<grid, 256, 0, s>>>(y, g, fr, prop_out, intensity, target, loss_partial,
-                                                          grad_coef, fuse ? 1 : 0);
-  return hipGetLastError();
+  return with_row_plan(g, [&](auto rt) {
+    using RT = decltype(rt);
+    if (rows_half(g))
+      k_rows_inverse_t<RT, true><<<grid, 256, 0, s>>>(y, g, fr, prop_out, intensity, target, loss_partial, grad_coef,
+                                                      fuse ? 1 : 0);
+    else
+      k_rows_inverse_t<RT, false><<<grid, 256, 0, s>>>(y, g, fr, prop_out, intensity, target, loss_partial, grad_coef,
+                                                       fuse ? 1 : 0);
+  });
 }
 hipError_t launch_rows_adjoint_in_t(const float2* prop, const float* dL_dI, const float2* dL_dprop, float2* z,
                                     const AsmGeom& g, const FftDesc& fr, hipStream_t s) {
   const unsigned grid = (unsigned)(g.n_bl * g.K * g.H);
-  if (rows_half(g))
-    k_rows_adjoint_in_t<Row3840, true><<<grid, 256, 0, s>>>(prop, dL_dI, dL_dprop, z, g, fr);
-  else
-    k_rows_adjoint_in_t<Row3840, false><<<grid, 256, 0, s>>>(prop, dL_dI, dL_dprop, z, g, fr);
-  return hipGetLastError();
+  return with_row_plan(g, [&](auto rt) {
+    using RT = decltype(rt);
+    if (rows_half(g))
+      k_rows_adjoint_in_t<RT, true><<<grid, 256, 0, s>>>(prop, dL_dI, dL_dprop, z, g, fr);
+    else
+      k_rows_adjoint_in_t<RT, false><<<grid, 256, 0, s>>>(prop, dL_dI, dL_dprop, z, g, fr);
+  });
 }
 hipError_t launch_rows_adjoint_out_t(const float2* w1, const float2* dL_dfield, float2* grad_field, const AsmGeom& g,
                                      const FftDesc& fr, hipStream_t s) {
   const unsigned grid = (unsigned)(g.n_bl * g.H);
-  if (rows_half(g))
-    k_rows_adjoint_out_t<Row3840, true><<<grid, 256, 0, s>>>(w1, dL_dfield, grad_field, g, fr);
-  else
-    k_rows_adjoint_out_t<Row3840, false><<<grid, 256, 0, s>>>(w1, dL_dfield, grad_field, g, fr);
-  return hipGetLastError();
+  return with_row_plan(g, [&](auto rt) {
+    using RT = decltype(rt);
+    if (rows_half(g))
+      k_rows_adjoint_out_t<RT, true><<<grid, 256, 0, s>>>(w1, dL_dfield, grad_field, g, fr);
+    else
+      k_rows_adjoint_out_t<RT, false><<<grid, 256, 0, s>>>(w1, dL_dfield, grad_field, g, fr);
+  });
 }
 
-template <int C>
-static void cols_forward_c(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, hipStream_t s) {
-  const unsigned grid = (unsigned)(g.n_bl * (g.pW / C));
-  if (cols_half(g))
-    k_cols_forward_t<C, true><<<grid, ColT<C>::NT, 0, s>>>(x1, y, g, fc);
-  else
-    k_cols_forward_t<C, false><<<grid, ColT<C>::NT, 0, s>>>(x1, y, g, fc);
-}
-template <int C>
-static void cols_adjoint_c(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, hipStream_t s) {
-  const unsigned grid = (unsigned)(g.n_bl * (g.pW / C));
-  if (cols_half(g))
-    k_cols_adjoint_t<C, true><<<grid, ColT<C>::NT, 0, s>>>(z, w1, g, fc);
-  else
-    k_cols_adjoint_t<C, false><<<grid, ColT<C>::NT, 0, s>>>(z, w1, g, fc);
+// Calls f(CT{}) with the column transform type of (C, the plan's radix
+// schedule); schedules other than 0 exist for C = 2 only (plan creation
+// checks this).
+template <class F>
+static hipError_t with_col_plan(const AsmGeom& g, int C, F&& f) {
+  if (C == 1) {
+    f(ColT<1>{});
+  } else if (C == 4) {
+    f(ColT<4>{});
+  } else {
+    switch (g.col_plan) {
+      case 1: f(ColT<2, 16, 9, 15>{}); break;
+      case 2: f(ColT<2, 15, 16, 9>{}); break;
+      case 3: f(ColT<2, 12, 12, 15>{}); break;
+      default: f(ColT<2>{}); break;
+    }
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_cols_forward_t(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, int C,
                                  hipStream_t s) {
-  if (C == 1)
-    cols_forward_c<1>(x1, y, g, fc, s);
-  else if (C == 2)
-    cols_forward_c<2>(x1, y, g, fc, s);
-  else
-    cols_forward_c<4>(x1, y, g, fc, s);
-  return hipGetLastError();
+  const unsigned grid = (unsigned)(g.n_bl * (g.pW / C));
+  return with_col_plan(g, C, [&](auto ct) {
+    using CT = decltype(ct);
+    if (cols_half(g))
+      k_cols_forward_t<CT, true><<<grid, CT::NT, 0, s>>>(x1, y, g, fc);
+    else
+      k_cols_forward_t<CT, false><<<grid, CT::NT, 0, s>>>(x1, y, g, fc);
+  });
 }
 hipError_t launch_cols_adjoint_t(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, int C,
                                  hipStream_t s) {
-  if (C == 1)
-    cols_adjoint_c<1>(z, w1, g, fc, s);
-  else if (C == 2)
-    cols_adjoint_c<2>(z, w1, g, fc, s);
-  else
-    cols_adjoint_c<4>(z, w1, g, fc, s);
-  return hipGetLastError();
+  const unsigned grid = (unsigned)(g.n_bl * (g.pW / C));
+  return with_col_plan(g, C, [&](auto ct) {
+    using CT = decltype(ct);
+    if (cols_half(g))
+      k_cols_adjoint_t<CT, true><<<grid, CT::NT, 0, s>>>(z, w1, g, fc);
+    else
+      k_cols_adjoint_t<CT, false><<<grid, CT::NT, 0, s>>>(z, w1, g, fc);
+  });
 }
 
 }  // namespace chrf

@@ -187,6 +187,8 @@ AsmGeom geom(const chrf_plan* p) {
   g.ay = (float)(1.0 / (p->pH * p->d.pitch));
   g.norm = (float)(1.0 / ((double)p->pH * (double)p->pW));
   g.hp = p->hp_dev;
+  g.row_plan = p->d.fft_rows_plan;
+  g.col_plan = p->d.fft_cols_plan;
   return g;
 }
 
@@ -385,6 +387,14 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
       return bad(fail(CHRF_EUNSUPPORTED, "plan: cols_per_block does not fit the LDS or the padded width"));
   }
   p->cols_per_block = C;
+  // radix schedules of the tuned transforms
+  if (d.fft_rows_plan != 0 && (!tuned_rows(geom(p)) || d.fft_rows_plan < 0 || d.fft_rows_plan >= tuned_row_plans()))
+    return bad(fail(CHRF_EUNSUPPORTED, "plan: fft_rows_plan must be 0 unless the padded width is 3840 (then 0.." +
+                                           std::to_string(tuned_row_plans() - 1) + ")"));
+  if (d.fft_cols_plan != 0 && (!tuned_cols(geom(p)) || C != 2 || d.fft_cols_plan < 0 ||
+                               d.fft_cols_plan >= tuned_col_plans()))
+    return bad(fail(CHRF_EUNSUPPORTED, "plan: fft_cols_plan must be 0 unless the padded height is 2160 with two "
+                                       "columns per workgroup (then 0.." + std::to_string(tuned_col_plans() - 1) + ")"));
   // transfer-function parameters
   std::vector<HParam> hp(p->L * p->K);
   const double dfx = 1.0 / (p->pW * d.pitch), dfy = 1.0 / (p->pH * d.pitch);
@@ -906,6 +916,7 @@ static DensifyScratch densify_scratch(int64_t n) {
 }
 
 size_t chrf_densify_workspace_bytes(int64_t n) { return n < 0 ? 0 : densify_scratch(n).bytes; }
+
 
 chrf_status chrf_densify(const chrf_densify_desc* d, void* scratch, int64_t capacity, int32_t* src, int32_t* kind,
                          float* means_out, float* log_scales_out, float* phase_out, int64_t* n_out,

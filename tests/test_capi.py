@@ -51,8 +51,9 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", offsetof(chrf_plan_desc, pitch), offsetof(chrf_plan_desc, distances),
          offsetof(chrf_plan_desc, cols_per_block), offsetof(chrf_plan_desc, layered),
          offsetof(chrf_gaussians, logits), offsetof(chrf_grads, logits));
-  printf("%zu %zu %zu %zu\n", offsetof(chrf_plan_desc, loss_kind), offsetof(chrf_plan_desc, ssim_weight),
-         offsetof(chrf_plan_desc, phase_only), offsetof(chrf_plan_desc, deterministic));
+  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(chrf_plan_desc, loss_kind), offsetof(chrf_plan_desc, ssim_weight),
+         offsetof(chrf_plan_desc, phase_only), offsetof(chrf_plan_desc, deterministic),
+         offsetof(chrf_plan_desc, fft_rows_plan), offsetof(chrf_plan_desc, fft_cols_plan));
   printf("%zu %zu %zu %zu\n", sizeof(chrf_densify_desc), offsetof(chrf_densify_desc, zeta),
          offsetof(chrf_densify_desc, tau_grad), offsetof(chrf_densify_desc, shrink));
   return 0;
@@ -70,7 +71,7 @@ int main(void) {
                     ctypes.sizeof(_lib.Grads), P.k_sigma.offset, P.pitch.offset, P.distances.offset,
                     P.cols_per_block.offset, P.layered.offset, _lib.Gaussians.logits.offset,
                     _lib.Grads.logits.offset, P.loss_kind.offset, P.ssim_weight.offset, P.phase_only.offset,
-                    P.deterministic.offset,
+                    P.deterministic.offset, P.fft_rows_plan.offset, P.fft_cols_plan.offset,
                     ctypes.sizeof(D), D.zeta.offset, D.tau_grad.offset, D.shrink.offset]
 
 

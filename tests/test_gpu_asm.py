@@ -174,3 +174,42 @@ def test_full_size_plane_counts_and_views(views, zs):
     v = views - 1
     ref = sum(oracle.propagate_adjoint(G[v, 0, k].astype(np.complex128), lam, zs[k], 8e-6, 2, 2) for k in range(K))
     assert rel_l2(cplx(back[v, 0]), ref) < TOL
+
+
+@pytest.mark.parametrize("plans", [(1, 0), (2, 0), (0, 1), (0, 2), (0, 3)])
+def test_radix_schedules_at_full_size(plans):
+    """Every non-default radix schedule of the tuned transforms (rows of 3840,
+    columns of 2160) at the 1080 x 1920 x 3 wavelengths x 4 planes geometry:
+    one propagated plane against the oracle, and the fused training step's
+    dL/dU for one wavelength against the oracle's adjoint propagation of
+    2 u dL/dI computed from the GPU's own field (the fused inverse row pass
+    runs the row schedule forwards and backwards)."""
+    from paper_2506_08350_amd import _lib, api
+    from scenegen import make_gaussians, make_targets
+    from tests.gpu_helpers import to_device
+
+    announce(f"radix schedules {plans} at 1080x1920")
+    H, W = 1080, 1920
+    lams, zs = (639e-9, 515e-9, 473e-9), (0.5e-3, 1e-3, 1.5e-3, 2e-3)
+    opt = Optics(lams, zs, 8e-6, 2, 2)
+    cam = identity_camera(W, H)
+    r = make_renderer([cam], opt, 2000, fft_plans=plans)
+    rng = np.random.default_rng(5)
+    U = rng.uniform(0, 1, (1, 3, H, W)) * np.exp(2j * np.pi * rng.uniform(0, 1, (1, 3, H, W)))
+    prop, _ = r.propagate(_to_gpu(U), want_intensity=False)
+    torch.cuda.synchronize()
+    assert rel_l2(cplx(prop[0, 2, 1]), oracle.propagate(U[0, 2], lams[2], zs[1], 8e-6, 2, 2)) < TOL
+    del prop
+    sc = make_gaussians(2000, 3, 77, x_range=(-0.3, 0.3), y_range=(-0.2, 0.2), log_scale_mean=-3.5)
+    tg = make_targets((1, 3, 4, H, W), 78)
+    r.train_step(to_device(sc), api.pack_cameras([cam]), torch.from_numpy(tg).cuda())
+    torch.cuda.synchronize()
+    Uf = cplx(r.region(_lib.REGION_FIELD, torch.float32).view(1, 3, H, W, 2))
+    GU = cplx(r.region(_lib.REGION_GRAD_FIELD, torch.float32).view(1, 3, H, W, 2))
+    li, numel = 1, tg.size
+    ref = np.zeros((H, W), np.complex128)
+    for k, z in enumerate(zs):
+        u = oracle.propagate(Uf[0, li], lams[li], z, 8e-6, 2, 2)
+        I = np.abs(u) ** 2
+        ref += oracle.propagate_adjoint(2.0 * u * (2.0 * (I - tg[0, li, k]) / numel), lams[li], z, 8e-6, 2, 2)
+    assert rel_l2(GU[0, li], ref) < TOL

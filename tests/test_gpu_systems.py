@@ -89,15 +89,17 @@ def test_autotune_caches_a_runnable_choice(tmp_path):
     cam_t = api.pack_cameras(cams)
     target = torch.from_numpy(tg).cuda()
     cache = str(tmp_path / "tune.json")
-    tile, cols, entry = autotune.autotune(48, 64, o, params, cam_t, target, max_pairs=1 << 20, cache=cache,
-                                         tiles=((16, 16), (8, 8)), cols=(4, 2))
-    assert tile in ((16, 16), (8, 8))
+    best, entry = autotune.autotune(48, 64, o, params, cam_t, target, max_pairs=1 << 20, cache=cache,
+                                    tiles=((16, 16), (8, 8)), cols=(4, 2))
+    assert best["tile"] in ((16, 16), (8, 8))
+    assert best["fft_plans"] == (0, 0)   # no tuned transforms at this size: other schedules are refused
+    assert any("error" in c for c in entry["candidates"])
     assert os.path.exists(cache)
     data = json.load(open(cache))
     assert len(data) == 1
-    tile2, cols2, entry2 = autotune.autotune(48, 64, o, params, cam_t, target, max_pairs=1 << 20, cache=cache)
-    assert (tile2, cols2) == (tile, cols) and entry2["ms"] == entry["ms"]
-    r = api.Renderer(48, 64, o, max_gaussians=sc.n, tile=tile, cols_per_block=cols)
+    best2, entry2 = autotune.autotune(48, 64, o, params, cam_t, target, max_pairs=1 << 20, cache=cache)
+    assert best2 == best and entry2["ms"] == entry["ms"]
+    r = api.Renderer(48, 64, o, max_gaussians=sc.n, **best)
     loss, _, _ = r.train_step(params, cam_t, target)
     st = oracle.forward(sc, cams, opt, targets=tg)
     assert abs(float(loss) - st["loss"]) < 1e-4 * st["loss"]
