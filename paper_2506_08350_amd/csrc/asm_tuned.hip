@@ -98,6 +98,15 @@ __device__ inline cpx transfer_from_q(const HParam& hp, bool col_pass, float q, 
   return pass ? cpx{cs, sn} : cpx{0.f, 0.f};
 }
 
+// The same when no bin of the grid is masked (AsmGeom::mask_free): no band
+// tests, so the per-plane work per bin is one multiply-add, the range
+// reduction and the sine and cosine.
+__device__ inline cpx transfer_free(const HParam& hp, float q) {
+  float rev = hp.frac_rev - hp.z * q;
+  rev -= __builtin_rintf(rev);
+  return cpx{__builtin_amdgcn_cosf(rev), __builtin_amdgcn_sinf(rev)};
+}
+
 template <int N_, int NT, int R1_, int R2, int R3_>
 struct RowT {
   static constexpr int N = N_, R1 = R1_, R3 = R3_;
@@ -350,11 +359,19 @@ __global__ __launch_bounds__(CT::NT, CT::kMinBlocks) void k_cols_forward_t(const
     const int jj = opaque_v(j), kx = opaque_v(c0 + s);
     cpx w1[1][R3], w3[1][R1];
     if (b < CT::Inv::B1) {
-      const bool col_pass = g.band_mode < 2 || abs(sbin(kx, g.pW)) <= hp.kx_max;
+      if (g.mask_free) {   // uniform
 #pragma unroll
-      for (int q = 0; q < R3; ++q) {
-        const cpx sv = CT::kRegSpec ? sreg[CT::kRegSpec ? q : 0] : spec[b + q * CT::Inv::B1];
-        w1[0][q] = cmul(sv, transfer_from_q(hp, col_pass, qv[q], jj + q * CT::S3, g));
+        for (int q = 0; q < R3; ++q) {
+          const cpx sv = CT::kRegSpec ? sreg[CT::kRegSpec ? q : 0] : spec[b + q * CT::Inv::B1];
+          w1[0][q] = cmul(sv, transfer_free(hp, qv[q]));
+        }
+      } else {
+        const bool col_pass = g.band_mode < 2 || abs(sbin(kx, g.pW)) <= hp.kx_max;
+#pragma unroll
+        for (int q = 0; q < R3; ++q) {
+          const cpx sv = CT::kRegSpec ? sreg[CT::kRegSpec ? q : 0] : spec[b + q * CT::Inv::B1];
+          w1[0][q] = cmul(sv, transfer_from_q(hp, col_pass, qv[q], jj + q * CT::S3, g));
+        }
       }
     }
     if constexpr (CT::kLdsTw)
@@ -456,10 +473,15 @@ __global__ __launch_bounds__(CT::NT, CT::kMinBlocks) void k_cols_adjoint_t(const
     // C = 4 would spill with the table
     CT::Fwd::template run_hooked<CT::kLdsTw && CT::kRegSpec, 1, kDma>(v1, v3, lds, twl, start_next, opaque_v(b));
     if (b < CT::Fwd::B3) {
-      const bool col_pass = g.band_mode < 2 || abs(sbin(kx, g.pW)) <= hp.kx_max;
+      if (g.mask_free) {   // uniform
 #pragma unroll
-      for (int q = 0; q < R3; ++q)
-        acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_from_q(hp, col_pass, s_q[q][b], jj + q * CT::S3, g));
+        for (int q = 0; q < R3; ++q) acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_free(hp, s_q[q][b]));
+      } else {
+        const bool col_pass = g.band_mode < 2 || abs(sbin(kx, g.pW)) <= hp.kx_max;
+#pragma unroll
+        for (int q = 0; q < R3; ++q)
+          acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_from_q(hp, col_pass, s_q[q][b], jj + q * CT::S3, g));
+      }
     }
     if constexpr (kDma)
       if (k + 1 < g.K) copies_visible();

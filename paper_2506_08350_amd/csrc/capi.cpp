@@ -77,6 +77,8 @@ struct chrf_plan {
   int g2 = 0;
   bool deterministic = false;
   bool evanescent = false;
+  bool mask_free = false;   // no bin is masked by the band limits (and none is evanescent)
+  bool grad2d_zeroed = false;   // the last forward zeroed the 2D gradient rows and no backward has used them
   bool layered = false;
   int loss_kind = 0;
   // loss_kind 1: buffers of the last forward that the backward reads again
@@ -183,6 +185,7 @@ AsmGeom geom(const chrf_plan* p) {
   g.K = p->K;
   g.band_mode = p->d.band_limit;
   g.evanescent = p->evanescent ? 1 : 0;
+  g.mask_free = p->mask_free ? 1 : 0;
   g.ax = (float)(1.0 / (p->pW * p->d.pitch));
   g.ay = (float)(1.0 / (p->pH * p->d.pitch));
   g.norm = (float)(1.0 / ((double)p->pH * (double)p->pW));
@@ -398,6 +401,7 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   // transfer-function parameters
   std::vector<HParam> hp(p->L * p->K);
   const double dfx = 1.0 / (p->pW * d.pitch), dfy = 1.0 / (p->pH * d.pitch);
+  bool sampling_cut = false;   // some plane's sampling band limit removes a bin
   for (int l = 0; l < p->L; ++l)
     for (int k = 0; k < p->K; ++k) {
       // a layered plan propagates the hologram back to its layers (-Z_k);
@@ -414,6 +418,7 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
         const double fyl = 1.0 / (lam * std::sqrt((2.0 * dfy * z) * (2.0 * dfy * z) + 1.0));
         h.kx_max = (int)std::min(std::floor(fxl / dfx), 1e9);
         h.ky_max = (int)std::min(std::floor(fyl / dfy), 1e9);
+        if (h.kx_max < p->pW / 2 || h.ky_max < p->pH / 2) sampling_cut = true;   // |signed bin| <= padded size / 2
       } else {
         h.kx_max = h.ky_max = 1 << 30;
       }
@@ -426,6 +431,7 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
       if (hx * hx * p->pH * (double)p->pH + hy * hy * p->pW * (double)p->pW > (double)h.evan_bound)
         p->evanescent = true;
     }
+  p->mask_free = !p->evanescent && !sampling_cut;
   {
     hipError_t e = hipMalloc(&p->hp_dev, sizeof(HParam) * hp.size());
     if (e == hipSuccess) e = hipMemcpy(p->hp_dev, hp.data(), sizeof(HParam) * hp.size(), hipMemcpyHostToDevice);
@@ -572,8 +578,8 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
   uint32_t* status = at<uint32_t>(plan, ws, R_STATUS);
   uint64_t* total = reinterpret_cast<uint64_t*>(status);
 
-  RUN("status_clear", launch_fill_u32(status, 0u, 8, s));
-  RUN("precompute_v", launch_precompute_v(g->amp, g->phase, g->n, plan->L, at<float2>(plan, ws, R_V), s));
+  uint2* ranges = at<uint2>(plan, ws, R_RANGES);
+  float* grad2d = at<float>(plan, ws, R_GRAD2D);
   ProjArgs pa{};
   pa.means = g->means;
   pa.log_scales = g->log_scales;
@@ -597,8 +603,20 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
   pa.sort_key = at<uint64_t>(plan, ws, R_GKEY);
   pa.sort_val = at<uint32_t>(plan, ws, R_GVAL);
   pa.count = at<uint32_t>(plan, ws, R_GCOUNT);
-  pa.grad2d = nullptr;
+  // a training forward (a target is given) also zeroes the 2D gradient rows
+  // that the backward accumulates into, which spares the backward a clear
+  pa.grad2d = target ? grad2d : nullptr;
+  pa.grad2d_stride = plan->g2;
+  pa.amp = g->amp;
+  pa.phase = g->phase;
+  pa.v = at<float2>(plan, ws, R_V);
+  pa.n_lambda = plan->L;
+  pa.clear_a = status;
+  pa.n_clear_a = 8;
+  pa.clear_b = reinterpret_cast<uint32_t*>(ranges);
+  pa.n_clear_b = (int64_t)2 * plan->B * plan->n_tiles;
   RUN("project", launch_project(pa, s));
+  plan->grad2d_zeroed = target != nullptr;
 
   bool galt = false;
   RUN("sort_gaussians", radix_sort_u64(at<uint64_t>(plan, ws, R_GKEY), at<uint64_t>(plan, ws, R_GKEY_ALT),
@@ -609,8 +627,6 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
   RUN("gather_counts", launch_gather_counts(gval, at<uint32_t>(plan, ws, R_GCOUNT), at<uint32_t>(plan, ws, R_CNT_SORTED), BN, s));
   RUN("scan_counts", launch_scan_u64_from_u32(at<uint32_t>(plan, ws, R_CNT_SORTED), at<uint64_t>(plan, ws, R_OFFSETS),
                                               BN, at<uint64_t>(plan, ws, R_SCAN_TMP), total, s));
-  uint2* ranges = at<uint2>(plan, ws, R_RANGES);
-  RUN("ranges_clear", launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (int64_t)2 * plan->B * plan->n_tiles, s));
   RUN("emit_pairs", launch_emit_pairs(gval, at<uint64_t>(plan, ws, R_OFFSETS), at<uint32_t>(plan, ws, R_CNT_SORTED),
                                       at<int4>(plan, ws, R_RECT), BN, Nst, plan->d.tile_w, plan->d.tile_h,
                                       plan->tiles_x, plan->n_tiles, at<uint32_t>(plan, ws, R_PKEY),
@@ -754,7 +770,8 @@ chrf_status chrf_backward(chrf_plan* plan, const chrf_gaussians* g, const chrf_c
     grad_field = lgrad;
   }
   float* grad2d = at<float>(plan, ws, R_GRAD2D);
-  RUN("grad2d_clear", launch_fill_f32(grad2d, 0.f, (int64_t)plan->B * Nst * plan->g2, s));
+  if (!plan->grad2d_zeroed) RUN("grad2d_clear", launch_fill_f32(grad2d, 0.f, (int64_t)plan->B * Nst * plan->g2, s));
+  plan->grad2d_zeroed = false;   // this backward accumulates into the rows
   size_t o, b;
   chrf_plan_region(plan, CHRF_REGION_PAIR_VALUES, &o, &b);
   RasterArgs ra{};

@@ -50,6 +50,16 @@ struct ProjArgs {
   uint32_t* count;      // tiles covered (0 if culled)
   float* grad2d;        // zeroed when not null
   int grad2d_stride;
+  // folded into the same launch: v[g][l] = amp e^{j phase} for g < n (the
+  // view-0 threads), and zeroing of two word buffers (status, tile ranges)
+  const float* amp;
+  const float* phase;
+  float2* v;
+  int n_lambda;
+  uint32_t* clear_a;
+  int64_t n_clear_a;
+  uint32_t* clear_b;
+  int64_t n_clear_b;
 };
 
 struct FftDesc {
@@ -80,12 +90,12 @@ struct AsmGeom {
   float ax, ay;     // 1 / (pW pitch), 1 / (pH pitch)
   float norm;       // 1 / (pH pW)
   const HParam* hp; // [n_lambda][K]
+  int mask_free;    // no bin of the padded grid is masked for any wavelength and plane
   int row_plan;     // radix schedule of the tuned row transforms (0 = default)
   int col_plan;     // radix schedule of the tuned column transforms (0 = default)
 };
 
 // ---- launchers (each returns hipGetLastError after the launch) ----
-hipError_t launch_precompute_v(const float* amp, const float* phase, int n, int n_lambda, float2* v, hipStream_t s);
 hipError_t launch_project(const ProjArgs& a, hipStream_t s);
 hipError_t launch_project_backward(const float* means, const float* log_scales, const float* quats,
                                    const float* amp, const float* phase, const Cam* cams, int n, int n_stride,

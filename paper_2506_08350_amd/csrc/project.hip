@@ -13,28 +13,30 @@
 
 namespace chrf {
 
-__global__ void k_precompute_v(const float* __restrict__ amp, const float* __restrict__ phase, int n_el,
-                               float2* __restrict__ v) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_el) return;
-  float s, c;
-  sincosf(phase[i], &s, &c);
-  v[i] = make_float2(amp[i] * c, amp[i] * s);
-}
-
-hipError_t launch_precompute_v(const float* amp, const float* phase, int n, int n_lambda, float2* v, hipStream_t s) {
-  int n_el = n * n_lambda;
-  if (n_el == 0) return hipSuccess;
-  k_precompute_v<<<(n_el + 255) / 256, 256, 0, s>>>(amp, phase, n_el, v);
-  return hipGetLastError();
-}
-
 __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
 #pragma clang fp contract(off)
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
+  {
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x * gridDim.y;
+    const int64_t tid = (int64_t)b * gridDim.x * blockDim.x + g;
+    for (int64_t i = tid; i < a.n_clear_a; i += nthreads) a.clear_a[i] = 0u;
+    for (int64_t i = tid; i < a.n_clear_b; i += nthreads) a.clear_b[i] = 0u;
+  }
+  if (b == 0 && g < a.n && a.v) {
+    for (int l = 0; l < a.n_lambda; ++l) {
+      float sn, cs;
+      sincosf(a.phase[(size_t)g * a.n_lambda + l], &sn, &cs);
+      const float am = a.amp[(size_t)g * a.n_lambda + l];
+      a.v[(size_t)g * a.n_lambda + l] = make_float2(am * cs, am * sn);
+    }
+  }
   if (g >= a.n_stride) return;
   const size_t rid = (size_t)b * a.n_stride + g;
+  if (a.grad2d) {   // every row of the view, used or not
+    float* gp = a.grad2d + rid * a.grad2d_stride;
+    for (int c = 0; c < a.grad2d_stride; ++c) gp[c] = 0.0f;
+  }
   if (g >= a.n) {   // unused slots sort last and emit nothing
     a.count[rid] = 0;
     a.sort_key[rid] = ((uint64_t)b << 32) | 0xffffffffull;
@@ -125,10 +127,6 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
   const uint32_t depth_bits = visible ? __float_as_uint(tcz) : 0xffffffffu;
   a.sort_key[rid] = ((uint64_t)b << 32) | depth_bits;
   a.sort_val[rid] = (uint32_t)rid;
-  if (a.grad2d) {
-    float* gp = a.grad2d + rid * a.grad2d_stride;
-    for (int c = 0; c < a.grad2d_stride; ++c) gp[c] = 0.0f;
-  }
 }
 
 hipError_t launch_project(const ProjArgs& a, hipStream_t s) {
