@@ -354,6 +354,11 @@ def bench_ring(steps, warmup, log):
     torch.cuda.synchronize()
     batched_ms = (time.perf_counter() - t0) * 1000.0 / steps
     loss_b = float(cap_graph.loss)
+    rb.timing(True)
+    rb.train_step(params, cam_t, target)
+    torch.cuda.synchronize()
+    rb.timing(False)
+    kt_b = rb.timing_report()
     del cap_graph, rb
     torch.cuda.empty_cache()
 
@@ -380,6 +385,14 @@ def bench_ring(steps, warmup, log):
         sequential()
     torch.cuda.synchronize()
     seq_ms = (time.perf_counter() - t0) * 1000.0 / steps
+    r1.timing(True)
+    sequential()
+    torch.cuda.synchronize()
+    r1.timing(False)
+    kt_s = r1.timing_report()
+    for name in sorted(set(kt_b) | set(kt_s), key=lambda n: -kt_b.get(n, (0, 0.0))[1]):
+        log(f"ring kernel {name:18s} batched {kt_b.get(name, (0, 0.0))[1]:9.3f} ms   "
+            f"16 single views {kt_s.get(name, (0, 0.0))[1]:9.3f} ms")
     del r1
     torch.cuda.empty_cache()
     return {

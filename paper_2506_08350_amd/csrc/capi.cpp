@@ -41,6 +41,7 @@ enum Reg {
   R_UPROP, R_INTEN, R_DMU, R_DEXX, R_DEXY, R_DLDI, R_LOSS2,   // loss_kind 1 only
   R_PO_P, R_PO_V, R_PO_GV, R_PO_D, R_PO_GP, R_PO_PART,       // phase_only plans only
   R_DET_RID, R_DET_INV, R_DET_GRAD,                          // deterministic plans only
+  R_TILE_ORDER,
   R_NUM
 };
 
@@ -439,7 +440,8 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   }
   // sort geometry
   p->gsort_bits = 32 + bits_for(p->B - 1);
-  p->psort_bits = bits_for((int64_t)p->B * p->n_tiles - 1);
+  // pair keys are view << psort_bits | tile; the sort orders their low bits
+  p->psort_bits = bits_for((int64_t)p->n_tiles - 1);
   p->gsort_alt = ((p->gsort_bits + 7) / 8) % 2 == 1;
   p->psort_alt = ((p->psort_bits + 7) / 8) % 2 == 1;
   // workspace layout
@@ -460,6 +462,7 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   sz[R_HIST] = sizeof(uint32_t) * hist;
   sz[R_PKEY] = sz[R_PKEY_ALT] = sz[R_PVAL] = sz[R_PVAL_ALT] = sizeof(uint32_t) * cap;
   sz[R_RANGES] = sizeof(uint2) * (size_t)p->B * p->n_tiles;
+  sz[R_TILE_ORDER] = sizeof(uint32_t) * (size_t)p->B * p->n_tiles;
   sz[R_STATUS] = 256;
   sz[R_TFINAL] = sizeof(float) * pix;
   sz[R_LAST] = sizeof(uint32_t) * pix;
@@ -629,7 +632,7 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
                                               BN, at<uint64_t>(plan, ws, R_SCAN_TMP), total, s));
   RUN("emit_pairs", launch_emit_pairs(gval, at<uint64_t>(plan, ws, R_OFFSETS), at<uint32_t>(plan, ws, R_CNT_SORTED),
                                       at<int4>(plan, ws, R_RECT), BN, Nst, plan->d.tile_w, plan->d.tile_h,
-                                      plan->tiles_x, plan->n_tiles, at<uint32_t>(plan, ws, R_PKEY),
+                                      plan->tiles_x, plan->psort_bits, at<uint32_t>(plan, ws, R_PKEY),
                                       at<uint32_t>(plan, ws, R_PVAL), plan->cap, total, status + 2,
                                       plan->deterministic ? at<uint32_t>(plan, ws, R_DET_RID) : nullptr, s));
   bool palt = false;
@@ -639,10 +642,11 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
                                    at<uint32_t>(plan, ws, R_SCAN_TMP), status + 3, &palt, s));
   const uint32_t* pkey = at<uint32_t>(plan, ws, palt ? R_PKEY_ALT : R_PKEY);
   const uint32_t* pval = at<uint32_t>(plan, ws, palt ? R_PVAL_ALT : R_PVAL);
-  RUN("tile_ranges", launch_tile_ranges(pkey, total, plan->cap, ranges, s));
-  if (plan->deterministic)
+  if (plan->deterministic)   // the sorted values (emission slots) become record ids
     RUN("det_gather", launch_det_gather(const_cast<uint32_t*>(pval), at<uint32_t>(plan, ws, R_DET_RID),
                                         at<uint32_t>(plan, ws, R_DET_INV), total, plan->cap, s));
+  RUN("tile_ranges", launch_tile_ranges(pkey, plan->psort_bits, plan->n_tiles, total, plan->cap, ranges, s));
+  RUN("tile_order", launch_tile_order(ranges, plan->B * plan->n_tiles, at<uint32_t>(plan, ws, R_TILE_ORDER), s));
 
   RasterArgs ra{};
   ra.rec_g0 = at<float4>(plan, ws, R_G0);
@@ -651,6 +655,7 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
   ra.v = at<float2>(plan, ws, R_V);
   ra.pair_val = pval;
   ra.ranges = ranges;
+  ra.tile_order = at<uint32_t>(plan, ws, R_TILE_ORDER);
   ra.n_stride = Nst;
   ra.n_lambda = plan->L;
   ra.width = plan->W;
@@ -781,6 +786,7 @@ chrf_status chrf_backward(chrf_plan* plan, const chrf_gaussians* g, const chrf_c
   ra.v = at<float2>(plan, ws, R_V);
   ra.pair_val = reinterpret_cast<const uint32_t*>(static_cast<char*>(ws) + o);
   ra.ranges = at<uint2>(plan, ws, R_RANGES);
+  ra.tile_order = at<uint32_t>(plan, ws, R_TILE_ORDER);
   ra.n_stride = Nst;
   ra.n_lambda = plan->L;
   ra.width = plan->W;

@@ -123,7 +123,7 @@ hipError_t launch_gather_counts(const uint32_t* sorted_val, const uint32_t* coun
                                 hipStream_t s);
 hipError_t launch_emit_pairs(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* cnt_sorted,
                              const int4* rect, int64_t n, int n_stride, int tile_w, int tile_h, int tiles_x,
-                             int n_tiles, uint32_t* pair_key, uint32_t* pair_val, int64_t capacity,
+                             int tile_bits, uint32_t* pair_key, uint32_t* pair_val, int64_t capacity,
                              const uint64_t* total, uint32_t* status, uint32_t* det_rid, hipStream_t s);
 // deterministic gradient mode: slot bookkeeping after the pair sort, and the
 // fixed-order reduction of per-pair gradient rows into per-(view, Gaussian) rows
@@ -133,8 +133,8 @@ hipError_t launch_det_reduce(const uint32_t* sorted_val, const uint64_t* offsets
                              const uint32_t* inv, const float* pair_grad, int64_t n, int g2, int64_t capacity,
                              float* grad2d, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
-hipError_t launch_tile_ranges(const uint32_t* pair_key, const uint64_t* total, int64_t capacity, uint2* ranges,
-                              hipStream_t s);
+hipError_t launch_tile_ranges(const uint32_t* pair_key, int tile_bits, int n_tiles, const uint64_t* total,
+                              int64_t capacity, uint2* ranges, hipStream_t s);
 
 struct RasterArgs {
   const float4* rec_g0;
@@ -143,6 +143,7 @@ struct RasterArgs {
   const float2* v;          // [N][n_lambda]
   const uint32_t* pair_val;
   const uint2* ranges;
+  const uint32_t* tile_order;   // workgroup -> (view, tile) index, longest lists first; null: identity
   int n_stride, n_lambda;
   int width, height, tile_w, tile_h, tiles_x, tiles_y, n_views;
   float k_sigma, alpha_min, alpha_max, t_min;
@@ -160,6 +161,9 @@ struct RasterArgs {
   int n_layers;
   uint32_t* layer_stop;     // [B][n_layers][H][W]: pair index + 1 that ended the layer, ~0u if none
 };
+// Order of the (view, tile) work items for the raster launches: descending
+// list length in buckets of 1/8 octave (order within a bucket unspecified).
+hipError_t launch_tile_order(const uint2* ranges, int n, uint32_t* order, hipStream_t s);
 hipError_t launch_raster_forward(const RasterArgs& a, hipStream_t s);
 hipError_t launch_raster_backward(const RasterArgs& a, hipStream_t s);
 

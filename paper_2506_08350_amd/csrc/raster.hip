@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_fwd(RasterArgs a) {
 #pragma unroll
     for (int l = 0; l < NL; ++l) U[p][l] = make_float2(0.f, 0.f);
   }
-  const uint2 rg = a.ranges[blockIdx.x];
+  const uint2 rg = a.ranges[t.id];
   const float half_k2 = 0.5f * a.k_sigma * a.k_sigma;
   for (uint32_t start = rg.x; start < rg.y; start += kBatch) {
     bool all_done = true;
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
     for (int w = 0; w < NW; ++w) tile_last = max(tile_last, s_last[w]);
     tile_last = (uint32_t)__builtin_amdgcn_readfirstlane((int)tile_last);
   }
-  const uint2 rg = a.ranges[blockIdx.x];
+  const uint2 rg = a.ranges[t.id];
   const float half_k2 = 0.5f * a.k_sigma * a.k_sigma;
   for (int i = threadIdx.x; i < kBatch * G2; i += kLanes * NW) (&s_grad[0][0])[i] = 0.f;
 

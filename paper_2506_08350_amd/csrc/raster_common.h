@@ -17,14 +17,18 @@ constexpr int kLanes = 64;
 constexpr int kBatch = 64;
 
 struct TileGeom {
+  int id;   // (view, tile) index: view * tiles + tile
   int view, tx, ty;
 };
 
+// Workgroups take (view, tile) items in the order of a.tile_order (longest
+// pair lists first, so that the short ones fill the end of the launch).
 __device__ inline TileGeom tile_of(const RasterArgs& a) {
   const int n_tiles = a.tiles_x * a.tiles_y;
   TileGeom t;
-  t.view = blockIdx.x / n_tiles;
-  const int tile = blockIdx.x % n_tiles;
+  t.id = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
+  t.view = t.id / n_tiles;
+  const int tile = t.id % n_tiles;
   t.tx = tile % a.tiles_x;
   t.ty = tile / a.tiles_x;
   return t;

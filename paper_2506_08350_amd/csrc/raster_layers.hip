@@ -103,7 +103,7 @@ __global__ __launch_bounds__(64 * NWAVE, 8) void k_raster_layers_fwd(RasterArgs 
     for (int l = 0; l < NL; ++l) U[q][l] = make_float2(0.f, 0.f);
   }
   uint32_t live = inside ? (1u << a.n_layers) - 1u : 0u;   // layers still accepting contributions
-  const uint2 rg = a.ranges[blockIdx.x];
+  const uint2 rg = a.ranges[t.id];
   uint32_t walk_end = inside ? rg.y : 0u;
   const float half_k2 = 0.5f * a.k_sigma * a.k_sigma;
   for (uint32_t start = rg.x; start < rg.y; start += kBatch) {
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(64 * NWAVE, 4) void k_raster_layers_bwd(RasterArgs 
 #pragma unroll
   for (int w = 0; w < NWAVE; ++w) tile_last = max(tile_last, s_last[w]);
   tile_last = (uint32_t)__builtin_amdgcn_readfirstlane((int)tile_last);
-  const uint2 rg = a.ranges[blockIdx.x];
+  const uint2 rg = a.ranges[t.id];
   const float half_k2 = 0.5f * a.k_sigma * a.k_sigma;
 
   for (uint32_t top = tile_last; top > rg.x;) {

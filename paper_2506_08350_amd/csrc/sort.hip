@@ -600,7 +600,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
                                                     const uint64_t* __restrict__ offsets,
                                                     const uint32_t* __restrict__ cnt_sorted,
                                                     const int4* __restrict__ rect, int64_t n, int n_stride,
-                                                    int tile_w, int tile_h, int tiles_x, int n_tiles,
+                                                    int tile_w, int tile_h, int tiles_x, int tile_bits,
                                                     uint32_t* __restrict__ pair_key, uint32_t* __restrict__ pair_val,
                                                     int64_t capacity, const uint64_t* total, uint32_t* status,
                                                     uint32_t* __restrict__ det_rid) {
@@ -619,8 +619,13 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
   const int tx0 = rc.x / tile_w, tx1 = (rc.x + rc.y) / tile_w;
   const int ty0 = rc.z / tile_h;
   const int wt = tx1 - tx0 + 1;
+  // key = view << tile_bits | tile.  The list arrives view-major (the
+  // Gaussians are sorted by (view, depth)), so a stable sort by the low
+  // 8 * ceil(tile_bits / 8) bits keeps each (view, tile) run contiguous and
+  // in depth order: runs that share those bits belong to different views
+  // and stay in view order.
   const uint32_t view = rid / (uint32_t)n_stride;
-  const uint32_t k0 = view * (uint32_t)n_tiles + (uint32_t)(ty0 * tiles_x + tx0);
+  const uint32_t k0 = (view << tile_bits) | (uint32_t)(ty0 * tiles_x + tx0);
   for (int local = lane; local < lim; local += kEmitTeam) {
     const int dy = local / wt;
     const int dx = local - dy * wt;
@@ -637,12 +642,12 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
 
 hipError_t launch_emit_pairs(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* cnt_sorted,
                              const int4* rect, int64_t n, int n_stride, int tile_w, int tile_h, int tiles_x,
-                             int n_tiles, uint32_t* pair_key, uint32_t* pair_val, int64_t capacity,
+                             int tile_bits, uint32_t* pair_key, uint32_t* pair_val, int64_t capacity,
                              const uint64_t* total, uint32_t* status, uint32_t* det_rid, hipStream_t s) {
   if (n <= 0 || capacity <= 0) return hipSuccess;
   const int64_t threads = n * kEmitTeam;
   k_emit_pairs<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(sorted_val, offsets, cnt_sorted, rect, n,
-                                                                  n_stride, tile_w, tile_h, tiles_x, n_tiles,
+                                                                  n_stride, tile_w, tile_h, tiles_x, tile_bits,
                                                                   pair_key, pair_val, capacity, total, status,
                                                                   det_rid);
   return hipGetLastError();
@@ -728,10 +733,15 @@ hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s) {
 constexpr int kRangeKeys = 4;
 constexpr int kRangeMaxBlocks = 2048;
 
-__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ key, const uint64_t* total,
-                                                     int64_t capacity, uint2* __restrict__ ranges) {
+// [start, end) of every (view, tile) run of the sorted list; a key
+// view << tile_bits | tile is the run view * n_tiles + tile.
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ key, int tile_bits, uint32_t n_tiles,
+                                                     const uint64_t* total, int64_t capacity,
+                                                     uint2* __restrict__ ranges) {
   const uint64_t t = *total;
   const int64_t n = t < (uint64_t)capacity ? (int64_t)t : capacity;
+  const uint32_t tmask = (1u << tile_bits) - 1u;
+  auto run_of = [&](uint32_t k) { return (k >> tile_bits) * n_tiles + (k & tmask); };
   const int64_t stride = (int64_t)gridDim.x * blockDim.x * kRangeKeys;
   for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeKeys; i0 < n; i0 += stride) {
     uint32_t k[kRangeKeys];
@@ -754,18 +764,65 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict_
       if (i >= n) break;
       const bool first = e == 0 ? !has_prev || prev != k[0] : k[e - 1] != k[e];
       const bool last = i + 1 == n || (e + 1 < kRangeKeys ? k[e + 1] != k[e] : next != k[e]);
-      if (first) ranges[k[e]].x = (uint32_t)i;
-      if (last) ranges[k[e]].y = (uint32_t)(i + 1);
+      if (first) ranges[run_of(k[e])].x = (uint32_t)i;
+      if (last) ranges[run_of(k[e])].y = (uint32_t)(i + 1);
     }
   }
 }
 
-hipError_t launch_tile_ranges(const uint32_t* pair_key, const uint64_t* total, int64_t capacity, uint2* ranges,
-                              hipStream_t s) {
+hipError_t launch_tile_ranges(const uint32_t* pair_key, int tile_bits, int n_tiles, const uint64_t* total,
+                              int64_t capacity, uint2* ranges, hipStream_t s) {
   if (capacity <= 0) return hipSuccess;
   const int64_t per_block = 256 * kRangeKeys;
   const int64_t blocks = std::min<int64_t>((capacity + per_block - 1) / per_block, kRangeMaxBlocks);
-  k_tile_ranges<<<(unsigned)blocks, 256, 0, s>>>(pair_key, total, capacity, ranges);
+  k_tile_ranges<<<(unsigned)blocks, 256, 0, s>>>(pair_key, tile_bits, (uint32_t)n_tiles, total, capacity, ranges);
+  return hipGetLastError();
+}
+
+// One workgroup: histogram of the (view, tile) items over 256 buckets of
+// descending list length (8 per octave of length + 1), exclusive scan, then
+// each item takes the next slot of its bucket.
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges, int n,
+                                                     uint32_t* __restrict__ order) {
+  __shared__ uint32_t cnt[256];
+  if (threadIdx.x < 256) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  auto bucket = [&](int i) {
+    const uint2 r = ranges[i];
+    const uint32_t len = (r.y > r.x ? r.y - r.x : 0u) + 1u;
+    const int msb = 31 - __clz(len);
+    const int frac = msb >= 3 ? (int)((len >> (msb - 3)) & 7u) : (int)((len << (3 - msb)) & 7u);
+    return 255 - min(255, msb * 8 + frac);
+  };
+  for (int i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&cnt[bucket(i)], 1u);
+  __syncthreads();
+  // exclusive scan of the 256 counts: four waves scan 64 each, then add the
+  // totals of the waves before them
+  __shared__ uint32_t wave_tot[4];
+  uint32_t c = 0, incl = 0;
+  if (threadIdx.x < 256) {
+    c = cnt[threadIdx.x];
+    incl = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t t = __shfl_up(incl, off, 64);
+      if ((threadIdx.x & 63) >= off) incl += t;
+    }
+    if ((threadIdx.x & 63) == 63) wave_tot[threadIdx.x >> 6] = incl;
+  }
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    uint32_t before = 0;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) before += wave_tot[w];
+    cnt[threadIdx.x] = before + incl - c;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) order[atomicAdd(&cnt[bucket(i)], 1u)] = (uint32_t)i;
+}
+
+hipError_t launch_tile_order(const uint2* ranges, int n, uint32_t* order, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_tile_order<<<1, 1024, 0, s>>>(ranges, n, order);
   return hipGetLastError();
 }
 

@@ -54,10 +54,28 @@ def test_tile_lists_bit_exact(tile, views):
     keys = r.region(_lib.REGION_PAIR_KEYS, torch.int32)[:n].cpu().numpy().view(np.uint32)
     vals = r.region(_lib.REGION_PAIR_VALUES, torch.int32)[:n].cpu().numpy().view(np.uint32)
     ranges = r.region(_lib.REGION_TILE_RANGES, torch.int32).cpu().numpy().view(np.uint32).reshape(-1, 2)
-    assert np.array_equal(keys, ref["tile_key"])
-    assert np.array_equal(vals % n_max, ref["gauss"])
-    assert np.array_equal(vals // n_max, ref["tile_key"] // (ref["tiles_x"] * ref["tiles_y"]))
-    assert np.array_equal(ranges.astype(np.int64), ref["ranges"])
+    # The library's keys are view << b | tile, sorted by their low
+    # 8 ceil(b / 8) bits; the oracle orders by (view, tile, depth, Gaussian).
+    # Every (view, tile) run is the same sequence, bit for bit, and the
+    # ranges delimit it.
+    T = ref["tiles_x"] * ref["tiles_y"]
+    b = int(T - 1).bit_length()
+    view, tile = (keys >> b).astype(np.int64), (keys & ((1 << b) - 1)).astype(np.int64)
+    assert np.array_equal(view, (vals // n_max).astype(np.int64))
+    low = keys.astype(np.int64) & ((1 << (8 * ((b + 7) // 8))) - 1)
+    assert np.all(np.diff(low) >= 0)                                       # sorted by the low key bits
+    run = view * T + tile
+    order = np.argsort(run, kind="stable")
+    assert np.array_equal(run[order], ref["tile_key"].astype(np.int64))
+    assert np.array_equal(vals[order] % n_max, ref["gauss"])
+    lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    ref_lens = ref["ranges"][:, 1] - ref["ranges"][:, 0]
+    assert np.array_equal(np.where(ref_lens > 0, lens, 0), ref_lens)
+    for rk in np.nonzero(ref_lens)[0]:
+        s0, s1 = int(ranges[rk, 0]), int(ranges[rk, 1])
+        assert np.all(run[s0:s1] == rk)
+        r0, r1 = ref["ranges"][rk]
+        assert np.array_equal(vals[s0:s1] % n_max, ref["gauss"][r0:r1])
 
 
 @pytest.mark.parametrize("thr_name", ["default", "smooth"])
