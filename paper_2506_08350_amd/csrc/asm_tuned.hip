@@ -273,8 +273,13 @@ struct ColT {
   static constexpr int C = C_, R1 = R1_, R2 = R2_, R3 = R3_;
   static constexpr int NT = 256 * C;
   static constexpr int S1 = kColN / R1, S3 = kColN / R3;
-  using Fwd = Fft3<kColN, C, NT, R1, R2, R3, false>;
-  using Inv = Fft3<kColN, C, NT, R3, R2, R1, true>;
+  // LDS layouts with the fewest bank conflicts for the column strides: one
+  // padding slot per 16 values in the forward transform, none in the inverse
+  // (which then needs no address arithmetic either)
+  static constexpr int kPadFwd = 4, kPadInv = 0;
+  static constexpr int kLdsElems = lds_padded_size(kColN * C, kPadFwd);
+  using Fwd = Fft3<kColN, C, NT, R1, R2, R3, false, kPadFwd>;
+  using Inv = Fft3<kColN, C, NT, R3, R2, R1, true, kPadInv>;
   static_assert(Fwd::M1 == 1 && Fwd::M3 == 1 && Inv::M1 == 1 && Inv::M3 == 1, "one butterfly per thread");
   static_assert(Fwd::B3 == Inv::B1, "forward outputs feed the inverse inputs");
   static constexpr int SPAN = 128 / (8 * C);   // column groups per 128-byte line
@@ -310,7 +315,7 @@ __global__ __launch_bounds__(CT::NT, CT::kMinBlocks) void k_cols_forward_t(const
                                                                           float2* __restrict__ y, AsmGeom g,
                                                                           FftDesc fc) {
   constexpr int C = CT::C, R1 = CT::R1, R3 = CT::R3;
-  __shared__ cpx lds[lds_padded_size(kColN * C)];
+  __shared__ cpx lds[CT::kLdsElems];
   __shared__ cpx spec[CT::kRegSpec ? 1 : kColN * C];
   __shared__ cpx s_tw[CT::kLdsTw ? kColN : 1];
   const cpx* twl = CT::kLdsTw ? stage_twiddles<CT::NT>(s_tw, fc.tw) : fc.tw;
@@ -405,7 +410,7 @@ __global__ __launch_bounds__(CT::NT, CT::kMinBlocks) void k_cols_adjoint_t(const
   constexpr int C = CT::C, R1 = CT::R1, R3 = CT::R3;
   constexpr bool kDma = HALF && C == 2;
   constexpr int kLiveRows = kColN / 2;
-  __shared__ cpx lds[lds_padded_size(kColN * C)];
+  __shared__ cpx lds[CT::kLdsElems];
   __shared__ cpx s_tw[CT::kLdsTw ? kColN : 1];
   __shared__ cpx s_in[kDma ? kLiveRows * C : 1];   // [row][column]
   const cpx* twl = CT::kLdsTw ? stage_twiddles<CT::NT>(s_tw, fc.tw) : fc.tw;

@@ -298,22 +298,33 @@ __device__ inline cpx* fft_lds(cpx* buf0, cpx* buf1, int N, int C, int logC, con
 // LDS index with one padding slot per 32 complex values: the Stockham stages
 // write with strides of R or R * C elements, which without padding would send
 // every lane of a wave to the same few banks.
-__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 5); }
-__host__ __device__ constexpr int lds_padded_size(int n) { return n + (n >> 5) + 1; }
+// The padding period is a parameter of the transform (2^PAD values per
+// slot; PAD = 0: no padding): the column transforms take the layout with the
+// fewest bank conflicts for their stride pattern.
+template <int PAD = 5>
+__host__ __device__ constexpr int lds_pad(int i) {
+  if constexpr (PAD == 0)
+    return i;
+  else
+    return i + (i >> PAD);
+}
+__host__ __device__ constexpr int lds_padded_size(int n, int pad = 5) { return n + (pad ? (n >> pad) : 0) + 1; }
 
 // lds_pad(x + r S) from p0 = lds_pad(x): when the stride S is a multiple of
-// 32 the padding grows by exactly S / 32 per step, so the address is p0 plus
-// a compile-time offset (no per-access shift and add).
-template <int S>
+// the padding period the padding grows by exactly S / 2^PAD per step, so the
+// address is p0 plus a compile-time offset (no per-access shift and add).
+template <int S, int PAD = 5>
 __device__ inline int strided_pad(int p0, int x, int r) {
-  if constexpr (S % 32 == 0) {
-    return p0 + r * (S + S / 32);
+  if constexpr (PAD == 0) {
+    return p0 + r * S;
+  } else if constexpr (S % (1 << PAD) == 0) {
+    return p0 + r * (S + (S >> PAD));
   } else {
-    return lds_pad(x + r * S);
+    return lds_pad<PAD>(x + r * S);
   }
 }
 
-template <int N, int C, int NT, int R1, int R2, int R3, bool INV>
+template <int N, int C, int NT, int R1, int R2, int R3, bool INV, int PAD = 5>
 struct Fft3 {
   static_assert(R1 * R2 * R3 == N, "radices must multiply to N");
   static constexpr int B1 = C * N / R1, B2 = C * N / R2, B3 = C * N / R3;
@@ -437,14 +448,18 @@ struct Fft3 {
       if (B1 % NT == 0 || b < B1) {
         const int s = b % C, j = b / C;
         Dft<R1, INV>::run(v1[i]);
-        if constexpr ((R1 * C) % 32 == 0 && 32 % C == 0) {
-          // j R1 C is a multiple of 32 and q C + s never crosses one past it
-          const int p0 = lds_pad(j * R1 * C) + s;
+        if constexpr (PAD == 0) {
+          const int p0 = j * R1 * C + s;
 #pragma unroll
-          for (int q = 0; q < R1; ++q) lds[p0 + q * C + ((q * C) >> 5)] = v1[i][q];
+          for (int q = 0; q < R1; ++q) lds[p0 + q * C] = v1[i][q];
+        } else if constexpr ((R1 * C) % (1 << PAD) == 0 && (1 << PAD) % C == 0) {
+          // j R1 C is a multiple of the period and q C + s never crosses one past it
+          const int p0 = lds_pad<PAD>(j * R1 * C) + s;
+#pragma unroll
+          for (int q = 0; q < R1; ++q) lds[p0 + q * C + ((q * C) >> PAD)] = v1[i][q];
         } else {
 #pragma unroll
-          for (int q = 0; q < R1; ++q) lds[lds_pad((j * R1 + q) * C + s)] = v1[i][q];
+          for (int q = 0; q < R1; ++q) lds[lds_pad<PAD>((j * R1 + q) * C + s)] = v1[i][q];
         }
       }
     }
@@ -460,10 +475,10 @@ struct Fft3 {
       const int b = tid + i * NT;
       if (B2 % NT == 0 || b < B2) {
         const int s = b % C, j = b / C, k = j % R1;
-        const int p0 = lds_pad(j * C + s);
+        const int p0 = lds_pad<PAD>(j * C + s);
 #pragma unroll
         for (int r = 0; r < R2; ++r)
-          v2[i][r] = lds[strided_pad<(N / R2) * C>(p0, j * C + s, r)];
+          v2[i][r] = lds[strided_pad<(N / R2) * C, PAD>(p0, j * C + s, r)];
         if constexpr (GIVEN_TW)
           apply_twiddle_powers(v2[i], pinned(t.w2[i]));
         else
@@ -478,9 +493,9 @@ struct Fft3 {
       if (B2 % NT == 0 || b < B2) {
         const int s = b % C, j = b / C, k = j % R1;
         const int base = (j - k) * R2 + k;
-        const int p0 = lds_pad(base * C + s);
+        const int p0 = lds_pad<PAD>(base * C + s);
 #pragma unroll
-        for (int q = 0; q < R2; ++q) lds[strided_pad<R1 * C>(p0, base * C + s, q)] = v2[i][q];
+        for (int q = 0; q < R2; ++q) lds[strided_pad<R1 * C, PAD>(p0, base * C + s, q)] = v2[i][q];
       }
     }
     stage_barrier<EARLY_TW>();
@@ -494,9 +509,9 @@ struct Fft3 {
       const int b = tid + i * NT;
       if (B3 % NT == 0 || b < B3) {
         const int s = b % C, j = b / C;
-        const int p0 = lds_pad(j * C + s);
+        const int p0 = lds_pad<PAD>(j * C + s);
 #pragma unroll
-        for (int r = 0; r < R3; ++r) v3[i][r] = lds[strided_pad<(N / R3) * C>(p0, j * C + s, r)];
+        for (int r = 0; r < R3; ++r) v3[i][r] = lds[strided_pad<(N / R3) * C, PAD>(p0, j * C + s, r)];
         if constexpr (GIVEN_TW)
           apply_twiddle_powers(v3[i], pinned(t.w3[i]));
         else
