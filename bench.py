@@ -410,7 +410,7 @@ def bench_ring(steps, warmup, log):
     }
 
 
-def bench_2160p(steps, warmup):
+def bench_2160p(steps, warmup, log=None):
     """4 views of 2,000,000 Gaussians at 2160 x 3840, 3 wavelengths, 16
     planes: eager training steps (gradients summed over the views by the
     wave-reduced atomics)."""
@@ -446,6 +446,14 @@ def bench_2160p(steps, warmup):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1000.0 / steps
     finite = all(bool(torch.isfinite(g).all()) for g in grads.values())
+    if log:
+        r.timing(True)
+        r.train_step(params, cam_t, target)
+        torch.cuda.synchronize()
+        r.timing(False)
+        kt = r.timing_report()
+        for name, (c, t) in sorted(kt.items(), key=lambda kv: -kv[1][1])[:12]:
+            log(f"2160p kernel {name:18s} {c:3d} x {t / c:9.3f} ms")
     del r, target, grads
     torch.cuda.empty_cache()
     return {"workload": w.name, "gaussians": sc.n, "views_per_step": B, "height": H, "width": W,
@@ -717,7 +725,7 @@ def main(argv=None):
         log("ring of 16 views")
         line["ring_16_views"] = bench_ring(max(2, args.steps // 4), 2, log)
         log("2160p, 4 views")
-        line["views_2160p"] = bench_2160p(3, 1)
+        line["views_2160p"] = bench_2160p(3, 1, log)
     print(json.dumps(line), flush=True)
     return 0
 
