@@ -195,7 +195,8 @@ def forward_layers(scene, logits, cameras, optics, thr=DEFAULT, targets=None, we
     views = []
     for b, cam in enumerate(cameras):
         proj = project(scene.means, scene.log_scales, scene.quats, scene.amp, scene.phase, cam)
-        fp = fp32_footprint(scene.means, scene.log_scales, scene.quats, cam, 16, 16, thr.k_sigma)
+        fp = fp32_footprint(scene.means, scene.log_scales, scene.quats, cam, 16, 16, thr.k_sigma, scene.opacity,
+                            thr.alpha_min)
         res = render_layers(proj, scene.opacity, fp, w, W, H, thr)
         for li, lam in enumerate(optics.wavelengths):
             P[b, li] = record(res.U[:, li], lam, optics.distances, optics.pitch, optics.pad, optics.band_limit)

@@ -53,7 +53,8 @@ def forward(scene, cameras, optics, thr=DEFAULT, targets=None, tile=(16, 16), ke
     u = np.zeros((B, L, K, H, W), np.complex128)
     for b, cam in enumerate(cameras):
         proj = project(scene.means, scene.log_scales, scene.quats, scene.amp, scene.phase, cam)
-        fp = fp32_footprint(scene.means, scene.log_scales, scene.quats, cam, tile[0], tile[1], thr.k_sigma)
+        fp = fp32_footprint(scene.means, scene.log_scales, scene.quats, cam, tile[0], tile[1], thr.k_sigma,
+                            scene.opacity, thr.alpha_min)
         res = render_field(proj, scene.opacity, fp, W, H, thr)
         for li, lam in enumerate(optics.wavelengths):
             for ki, z in enumerate(optics.distances):

@@ -627,10 +627,13 @@ chrf_status chrf_forward(chrf_plan* plan, const chrf_gaussians* g, const chrf_ca
                                        nullptr, 0, plan->gsort_bits, at<uint32_t>(plan, ws, R_HIST),
                                        at<uint32_t>(plan, ws, R_SCAN_TMP), status + 3, &galt, s));
   const uint32_t* gval = at<uint32_t>(plan, ws, galt ? R_GVAL_ALT : R_GVAL);
-  RUN("gather_counts", launch_gather_counts(gval, at<uint32_t>(plan, ws, R_GCOUNT), at<uint32_t>(plan, ws, R_CNT_SORTED), BN, s));
+  RUN("count_pairs", launch_count_pairs(gval, at<uint32_t>(plan, ws, R_GCOUNT), at<float4>(plan, ws, R_G0),
+                                        at<float4>(plan, ws, R_G1), at<int4>(plan, ws, R_RECT), BN, plan->d.tile_w,
+                                        plan->d.tile_h, at<uint32_t>(plan, ws, R_CNT_SORTED), s));
   RUN("scan_counts", launch_scan_u64_from_u32(at<uint32_t>(plan, ws, R_CNT_SORTED), at<uint64_t>(plan, ws, R_OFFSETS),
                                               BN, at<uint64_t>(plan, ws, R_SCAN_TMP), total, s));
   RUN("emit_pairs", launch_emit_pairs(gval, at<uint64_t>(plan, ws, R_OFFSETS), at<uint32_t>(plan, ws, R_CNT_SORTED),
+                                      at<float4>(plan, ws, R_G0), at<float4>(plan, ws, R_G1),
                                       at<int4>(plan, ws, R_RECT), BN, Nst, plan->d.tile_w, plan->d.tile_h,
                                       plan->tiles_x, plan->psort_bits, at<uint32_t>(plan, ws, R_PKEY),
                                       at<uint32_t>(plan, ws, R_PVAL), plan->cap, total, status + 2,

@@ -119,12 +119,16 @@ hipError_t radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, ui
                           uint32_t* error, bool* result_in_alt, hipStream_t s);
 int64_t radix_hist_elems(int64_t n_max);
 
-hipError_t launch_gather_counts(const uint32_t* sorted_val, const uint32_t* count, uint32_t* out, int64_t n,
-                                hipStream_t s);
+// Pairs of every depth-sorted (view, Gaussian) entry: per tile row of its
+// support rectangle, the tiles its ellipse's column span reaches.
+hipError_t launch_count_pairs(const uint32_t* sorted_val, const uint32_t* count, const float4* rec_g0,
+                              const float4* rec_g1, const int4* rect, int64_t n, int tile_w, int tile_h,
+                              uint32_t* cnt_sorted, hipStream_t s);
 hipError_t launch_emit_pairs(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* cnt_sorted,
-                             const int4* rect, int64_t n, int n_stride, int tile_w, int tile_h, int tiles_x,
-                             int tile_bits, uint32_t* pair_key, uint32_t* pair_val, int64_t capacity,
-                             const uint64_t* total, uint32_t* status, uint32_t* det_rid, hipStream_t s);
+                             const float4* rec_g0, const float4* rec_g1, const int4* rect, int64_t n, int n_stride,
+                             int tile_w, int tile_h, int tiles_x, int tile_bits, uint32_t* pair_key,
+                             uint32_t* pair_val, int64_t capacity, const uint64_t* total, uint32_t* status,
+                             uint32_t* det_rid, hipStream_t s);
 // deterministic gradient mode: slot bookkeeping after the pair sort, and the
 // fixed-order reduction of per-pair gradient rows into per-(view, Gaussian) rows
 hipError_t launch_det_gather(uint32_t* pair_val, const uint32_t* det_rid, uint32_t* inv, const uint64_t* total,

@@ -114,11 +114,16 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
     const float A_ = syy / det, B_ = -sxy / det, C_ = sxx / det;
     // Largest power at which the Gaussian can still support a pixel:
     // power <= k^2 / 2, and o exp(-power) >= alpha_min (alpha_min < alpha_max)
-    // means power <= ln(o / alpha_min).  The raster kernels use it only to
-    // skip 8x8 blocks that the ellipse cannot reach.
+    // means power <= ln(o / alpha_min).  Pair emission uses it to bin a
+    // Gaussian only to the tiles its ellipse can reach, the raster kernels to
+    // skip 8x8 blocks.  The tile decision must be reproducible on the CPU, so
+    // the logarithm is taken in double precision and rounded once to float
+    // (equal to the correctly rounded float logarithm except when the exact
+    // value lies within a double ulp of a float rounding boundary).
     const float op = a.opacity[g];
     const float half_k2 = 0.5f * a.k_sigma * a.k_sigma;
-    const float pmax = a.alpha_min > 0.0f ? fminf(half_k2, logf(op / a.alpha_min)) : half_k2;
+    const float pmax =
+        a.alpha_min > 0.0f ? (float)fmin((double)half_k2, log((double)op / (double)a.alpha_min)) : half_k2;
     a.rec_g0[rid] = make_float4(mux, muy, A_, B_);
     a.rec_g1[rid] = make_float4(C_, op, pmax, 0.0f);
     a.rec_rect[rid] = make_int4(c0, c1 - c0, r0, r1 - r0);

@@ -576,80 +576,213 @@ hipError_t radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, ui
 }
 
 // -------------------------------------------------------- pair emission ---
-__global__ void k_gather_counts(const uint32_t* __restrict__ sorted_val, const uint32_t* __restrict__ count,
-                                uint32_t* __restrict__ out, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = count[sorted_val[i]];
+// Which tiles of its support rectangle a Gaussian is binned to.  A pixel is
+// supported only where power = (A dx^2 + C dy^2) / 2 + B dx dy <= pmax
+// (dx, dy: pixel centre - mu; pmax = min(k^2/2, ln(o / alpha_min)), set by
+// the projection).  For one tile row, whose pixel centres span dy in
+// [y0, y1], the centres dx of that band inside the ellipse power <= pm form
+// one interval (the projection of a convex set): its right end is the
+// largest root dx of power(dx, dy) = pm over dy in the band, a concave
+// function of dy that peaks at the ellipse's rightmost point dy = -B xr / C
+// (xr = sqrt(2 pm C / D), D = AC - B^2), so it is attained at that dy
+// clamped to the band; the left end likewise.  The row keeps the tiles that
+// the interval's pixel columns touch.  pm exceeds pmax by a margin that
+// covers the rounding of the per-pixel power (1e-4 plus 4e-6 times the
+// form's size over the rectangle) and of this computation (1e-3 |pmax|), so
+// no tile holding a supported pixel is dropped.  The result decides the
+// tile lists, so it is one fixed single-precision recipe (no contraction,
+// IEEE division and square root; D from exact double products rounded once)
+// that the CPU reference reproduces bit for bit.
+struct SpanGeom {
+  float mx, my, A, B, D, t, ymax, ytip;
+  int c0, c1, r0, r1;
+  bool none, full;   // no tile at all / every tile of the rectangle
+};
+
+__device__ inline SpanGeom span_geom(const float4& g0, const float4& g1, const int4& rc) {
+#pragma clang fp contract(off)
+  SpanGeom s;
+  s.mx = g0.x;
+  s.my = g0.y;
+  s.A = g0.z;
+  s.B = g0.w;
+  const float C = g1.x, P = g1.z;
+  s.c0 = rc.x;
+  s.c1 = rc.x + rc.y;
+  s.r0 = rc.z;
+  s.r1 = rc.z + rc.w;
+  const float x0 = ((float)s.c0 + 0.5f) - s.mx, x1 = ((float)s.c1 + 0.5f) - s.mx;
+  const float y0 = ((float)s.r0 + 0.5f) - s.my, y1 = ((float)s.r1 + 0.5f) - s.my;
+  const float xm = fmaxf(-x0, x1), ym = fmaxf(-y0, y1);   // largest |dx|, |dy| over the rectangle
+  const float mag = 0.5f * ((s.A * xm) * xm + (C * ym) * ym) + (fabsf(s.B) * xm) * ym;
+  const float pm = P + ((1e-4f + 1e-3f * fabsf(P)) + 4e-6f * mag);
+  s.D = (float)((double)s.A * (double)C - (double)s.B * (double)s.B);
+  const float w = (2.0f * pm) / s.D;
+  s.t = (2.0f * pm) * s.A;
+  s.ymax = __builtin_sqrtf(w * s.A);   // the ellipse's half-height
+  const float xr = __builtin_sqrtf(w * C);
+  s.ytip = -(s.B * xr) / C;             // dy of its rightmost point
+  s.none = !(pm > 0.0f);
+  s.full = !s.none && !(s.D > 0.0f && s.A > 0.0f && C > 0.0f && __builtin_isfinite(s.t) &&
+                        __builtin_isfinite(s.ymax) && __builtin_isfinite(s.ytip));
+  return s;
 }
 
-hipError_t launch_gather_counts(const uint32_t* sorted_val, const uint32_t* count, uint32_t* out, int64_t n,
-                                hipStream_t s) {
+// Pixel columns [*clo, *chi] of tile row ty that the ellipse reaches; returns
+// the number of tiles they touch (0: none, *clo > *chi).
+__device__ inline int row_span(const SpanGeom& s, int ty, int tile_w, int tile_h, int* clo, int* chi) {
+#pragma clang fp contract(off)
+  int lo = s.c0, hi = s.c1;
+  if (s.none) {
+    hi = lo - 1;
+  } else if (!s.full) {
+    const int ylo = max(ty * tile_h, s.r0), yhi = min(ty * tile_h + tile_h - 1, s.r1);
+    const float y0 = ((float)ylo + 0.5f) - s.my, y1 = ((float)yhi + 0.5f) - s.my;
+    const float a = fmaxf(y0, -s.ymax), b = fminf(y1, s.ymax);
+    if (!(a <= b)) {
+      hi = lo - 1;                       // the band misses the ellipse
+    } else {
+      const float dr = fminf(fmaxf(s.ytip, a), b), dl = fminf(fmaxf(-s.ytip, a), b);
+      const float sr = __builtin_sqrtf(fmaxf(s.t - (s.D * dr) * dr, 0.0f));
+      const float sl = __builtin_sqrtf(fmaxf(s.t - (s.D * dl) * dl, 0.0f));
+      const float xh = (s.mx + (sr - s.B * dr) / s.A) - 0.5f;
+      const float xl = (s.mx + (-sl - s.B * dl) / s.A) - 0.5f;
+      if (xl == xl && xh == xh) {       // a NaN keeps the whole row
+        const float cl = (float)s.c0 - 1.0f, ch = (float)s.c1 + 1.0f;
+        lo = max((int)ceilf(fminf(fmaxf(xl, cl), ch)), s.c0);
+        hi = min((int)floorf(fminf(fmaxf(xh, cl), ch)), s.c1);
+      }
+    }
+  }
+  *clo = lo;
+  *chi = hi;
+  return lo <= hi ? hi / tile_w - lo / tile_w + 1 : 0;
+}
+
+// A team of kEmitTeam consecutive lanes per sorted (view, Gaussian) entry i;
+// lane r takes the tile rows r, r + kEmitTeam, ... of its rectangle.
+constexpr int kEmitTeam = 16;
+
+__device__ inline int team_sum(int v) {
+#pragma unroll
+  for (int m = kEmitTeam / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kEmitTeam);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_count_pairs(const uint32_t* __restrict__ sorted_val,
+                                                     const uint32_t* __restrict__ count,
+                                                     const float4* __restrict__ rec_g0,
+                                                     const float4* __restrict__ rec_g1,
+                                                     const int4* __restrict__ rect, int64_t n, int tile_w, int tile_h,
+                                                     uint32_t* __restrict__ cnt_sorted) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kEmitTeam;
+  const int lane = threadIdx.x % kEmitTeam;
+  const bool live = i < n;
+  const uint32_t rid = live ? sorted_val[i] : 0u;
+  int kept = 0;
+  if (live && count[rid] > 0) {          // visible, with a non-empty rectangle
+    const SpanGeom g = span_geom(rec_g0[rid], rec_g1[rid], rect[rid]);
+    const int ty1 = g.r1 / tile_h;
+    for (int ty = g.r0 / tile_h + lane; ty <= ty1; ty += kEmitTeam) {
+      int lo, hi;
+      kept += row_span(g, ty, tile_w, tile_h, &lo, &hi);
+    }
+  }
+  kept = team_sum(kept);
+  if (live && lane == 0) cnt_sorted[i] = (uint32_t)kept;
+}
+
+hipError_t launch_count_pairs(const uint32_t* sorted_val, const uint32_t* count, const float4* rec_g0,
+                              const float4* rec_g1, const int4* rect, int64_t n, int tile_w, int tile_h,
+                              uint32_t* cnt_sorted, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_gather_counts<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(sorted_val, count, out, n);
+  const int64_t threads = n * kEmitTeam;
+  k_count_pairs<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(sorted_val, count, rec_g0, rec_g1, rect, n, tile_w,
+                                                                   tile_h, cnt_sorted);
   return hipGetLastError();
 }
 
-// A team of kTeam consecutive lanes per sorted (view, Gaussian) entry i: its
-// count[i] pairs are the tiles of its rectangle in row-major order, written
-// to offsets[i] + local by consecutive lanes, so every store of a team is one
-// contiguous run.  Pairs past the capacity are dropped and flagged, so every
-// write stays in bounds.
-constexpr int kEmitTeam = 16;
-
+// Emission: the team computes the spans of kEmitTeam tile rows at once (lane
+// r: row base + r) and scans their tile counts; the rows' ends and first
+// keys go to LDS, and the team then writes the chunk's pairs as one flat run,
+// consecutive lanes on consecutive slots, each lane finding its row by a
+// binary search over the ends.  Pairs past the capacity are dropped and
+// flagged, so every write stays in bounds.
 __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ sorted_val,
                                                     const uint64_t* __restrict__ offsets,
                                                     const uint32_t* __restrict__ cnt_sorted,
+                                                    const float4* __restrict__ rec_g0,
+                                                    const float4* __restrict__ rec_g1,
                                                     const int4* __restrict__ rect, int64_t n, int n_stride,
                                                     int tile_w, int tile_h, int tiles_x, int tile_bits,
                                                     uint32_t* __restrict__ pair_key, uint32_t* __restrict__ pair_val,
                                                     int64_t capacity, const uint64_t* total, uint32_t* status,
                                                     uint32_t* __restrict__ det_rid) {
+  __shared__ int s_end[256 / kEmitTeam][kEmitTeam];
+  __shared__ uint32_t s_key[256 / kEmitTeam][kEmitTeam];
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kEmitTeam;
-  const int lane = threadIdx.x % kEmitTeam;
+  const int lane = threadIdx.x % kEmitTeam, team = threadIdx.x / kEmitTeam;
   if (i == 0 && lane == 0 && *total > (uint64_t)capacity) status[0] = 1u;
-  if (i >= n) return;
-  const uint32_t cnt = cnt_sorted[i];
-  if (cnt == 0) return;
-  const uint64_t base = offsets[i];
-  if (base >= (uint64_t)capacity) return;
-  const int64_t room = capacity - (int64_t)base;
-  const int lim = room < (int64_t)cnt ? (int)room : (int)cnt;
+  if (i >= n || cnt_sorted[i] == 0) return;   // whole teams leave together
   const uint32_t rid = sorted_val[i];
-  const int4 rc = rect[rid];
-  const int tx0 = rc.x / tile_w, tx1 = (rc.x + rc.y) / tile_w;
-  const int ty0 = rc.z / tile_h;
-  const int wt = tx1 - tx0 + 1;
+  uint64_t out = offsets[i];
+  const SpanGeom g = span_geom(rec_g0[rid], rec_g1[rid], rect[rid]);
   // key = view << tile_bits | tile.  The list arrives view-major (the
   // Gaussians are sorted by (view, depth)), so a stable sort by the low
   // 8 * ceil(tile_bits / 8) bits keeps each (view, tile) run contiguous and
   // in depth order: runs that share those bits belong to different views
   // and stay in view order.
-  const uint32_t view = rid / (uint32_t)n_stride;
-  const uint32_t k0 = (view << tile_bits) | (uint32_t)(ty0 * tiles_x + tx0);
-  for (int local = lane; local < lim; local += kEmitTeam) {
-    const int dy = local / wt;
-    const int dx = local - dy * wt;
-    pair_key[base + local] = k0 + (uint32_t)(dy * tiles_x + dx);
-    if (det_rid) {
-      // deterministic mode: the sort carries the emission slot, the record id waits aside
-      pair_val[base + local] = (uint32_t)(base + local);
-      det_rid[base + local] = rid;
-    } else {
-      pair_val[base + local] = rid;
+  const uint32_t vkey = (rid / (uint32_t)n_stride) << tile_bits;
+  const int ty0 = g.r0 / tile_h, ty1 = g.r1 / tile_h;
+  for (int base = ty0; base <= ty1; base += kEmitTeam) {
+    const int ty = base + lane;
+    int lo = 0, hi = -1, nt = 0;
+    if (ty <= ty1) nt = row_span(g, ty, tile_w, tile_h, &lo, &hi);
+    int end = nt;   // inclusive scan of the rows' tile counts
+#pragma unroll
+    for (int d = 1; d < kEmitTeam; d <<= 1) {
+      const int v = __shfl_up(end, d, kEmitTeam);
+      if (lane >= d) end += v;
     }
+    const int tot = __shfl(end, kEmitTeam - 1, kEmitTeam);
+    // pair j of the chunk in row r has key s_key[r] + j (vkey + tile equals
+    // vkey | tile; the offset by the row's first j may wrap, the sum does not)
+    s_end[team][lane] = end;
+    s_key[team][lane] = vkey + (uint32_t)(ty * tiles_x + lo / tile_w - (end - nt));
+    __builtin_amdgcn_wave_barrier();
+    for (int j = lane; j < tot; j += kEmitTeam) {
+      int r = 0;   // first row whose end exceeds j
+#pragma unroll
+      for (int step = kEmitTeam / 2; step >= 1; step >>= 1)
+        if (s_end[team][r + step - 1] <= j) r += step;
+      const uint64_t slot = out + (uint64_t)j;
+      if (slot < (uint64_t)capacity) {
+        pair_key[slot] = s_key[team][r] + (uint32_t)j;
+        if (det_rid) {
+          // deterministic mode: the sort carries the emission slot, the record id waits aside
+          pair_val[slot] = (uint32_t)slot;
+          det_rid[slot] = rid;
+        } else {
+          pair_val[slot] = rid;
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    out += (uint64_t)tot;
   }
 }
 
 hipError_t launch_emit_pairs(const uint32_t* sorted_val, const uint64_t* offsets, const uint32_t* cnt_sorted,
-                             const int4* rect, int64_t n, int n_stride, int tile_w, int tile_h, int tiles_x,
-                             int tile_bits, uint32_t* pair_key, uint32_t* pair_val, int64_t capacity,
-                             const uint64_t* total, uint32_t* status, uint32_t* det_rid, hipStream_t s) {
+                             const float4* rec_g0, const float4* rec_g1, const int4* rect, int64_t n, int n_stride,
+                             int tile_w, int tile_h, int tiles_x, int tile_bits, uint32_t* pair_key,
+                             uint32_t* pair_val, int64_t capacity, const uint64_t* total, uint32_t* status,
+                             uint32_t* det_rid, hipStream_t s) {
   if (n <= 0 || capacity <= 0) return hipSuccess;
   const int64_t threads = n * kEmitTeam;
-  k_emit_pairs<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(sorted_val, offsets, cnt_sorted, rect, n,
-                                                                  n_stride, tile_w, tile_h, tiles_x, tile_bits,
-                                                                  pair_key, pair_val, capacity, total, status,
-                                                                  det_rid);
+  k_emit_pairs<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(sorted_val, offsets, cnt_sorted, rec_g0, rec_g1,
+                                                                  rect, n, n_stride, tile_w, tile_h, tiles_x,
+                                                                  tile_bits, pair_key, pair_val, capacity, total,
+                                                                  status, det_rid);
   return hipGetLastError();
 }
 

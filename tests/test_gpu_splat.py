@@ -47,7 +47,9 @@ def test_tile_lists_bit_exact(tile, views):
         cams = yaw_cameras((0.0, -15.0, 25.0), (0.0, 0.0, 2.0), 200, 150, f=160)
     n_max = sc.n + 37              # unused slots must sort last and emit nothing
     r, out, need = _run(sc, cams, OPT1, tile=tile, n_max=n_max)
-    fps = [binning.fp32_footprint(sc.means, sc.log_scales, sc.quats, c, *tile) for c in cams]
+    thr = oracle.DEFAULT
+    fps = [binning.fp32_footprint(sc.means, sc.log_scales, sc.quats, c, *tile, thr.k_sigma, sc.opacity,
+                                  thr.alpha_min) for c in cams]
     ref = binning.bin_pairs(fps, 200, 150, *tile)
     n = len(ref["tile_key"])
     assert need == n

@@ -67,15 +67,12 @@ def _tile_checks(w, r):
     ranges = r.region(_lib.REGION_TILE_RANGES, torch.int32).cpu().numpy().view(np.uint32).reshape(-1, 2)
     vals = r.region(_lib.REGION_PAIR_VALUES, torch.int32)
     for b, cam in enumerate(w.cameras[:4]):
-        fp = binning.fp32_footprint(sc.means, sc.log_scales, sc.quats, cam)
-        vis = np.nonzero(fp["visible"])[0]
-        tiles = fp["tiles"][vis]
+        fp = binning.fp32_footprint(sc.means, sc.log_scales, sc.quats, cam, 16, 16, oracle.DEFAULT.k_sigma,
+                                    sc.opacity, oracle.DEFAULT.alpha_min)
         for (fr, fc) in WINDOWS:
             t_r, t_c = int(fr * ty), int(fc * tx)
             t = b * n_tiles + t_r * tx + t_c
-            inside = (tiles[:, 0] <= t_c) & (t_c <= tiles[:, 1]) & (tiles[:, 2] <= t_r) & (t_r <= tiles[:, 3])
-            g = vis[inside]
-            ref = g[np.lexsort((g, fp["key"][g].astype(np.int64)))]
+            ref = binning.tile_members(fp, t_c, t_r)
             s, e = ranges[t]
             got = vals[int(s):int(e)].cpu().numpy().view(np.uint32).astype(np.int64) - b * sc.n
             assert np.array_equal(got, ref), (b, t)

@@ -187,22 +187,37 @@ def test_fp32_footprint_encloses_support_and_keys_match_depth():
 
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
 def test_bin_pairs_structure(tile):
+    """Every tile holding a pixel that a Gaussian supports (FP64 oracle
+    compositing rule) lists it; it is listed only in tiles of its rectangle;
+    each list is in depth order and the ranges delimit it."""
+    thr = oracle.DEFAULT
     sc = make_gaussians(200, 1, seed=12, log_scale_mean=-3.5)
     cams = [identity_camera(70, 45, f=64), identity_camera(70, 45, f=90)]
-    fps = [binning.fp32_footprint(sc.means, sc.log_scales, sc.quats, c, *tile) for c in cams]
+    fps = [binning.fp32_footprint(sc.means, sc.log_scales, sc.quats, c, *tile, thr.k_sigma, sc.opacity,
+                                  thr.alpha_min) for c in cams]
     out = binning.bin_pairs(fps, 70, 45, *tile)
     key, gid, ranges = out["tile_key"].astype(np.int64), out["gauss"].astype(np.int64), out["ranges"]
     assert np.all(np.diff(key) >= 0)
     tx = out["tiles_x"]
     n_tiles = tx * out["tiles_y"]
-    for v, fp in enumerate(fps):
+    n_rect_pairs = 0
+    for v, (fp, cam) in enumerate(zip(fps, cams)):
+        p = projection.project(sc.means, sc.log_scales, sc.quats, sc.amp, sc.phase, cam)
         for g in np.nonzero(fp["visible"])[0]:
             c0, c1, r0, r1 = fp["rect"][g]
+            in_rect = set()
             for ty_ in range(r0 // tile[1], r1 // tile[1] + 1):
                 for tx_ in range(c0 // tile[0], c1 // tile[0] + 1):
-                    t = v * n_tiles + ty_ * tx + tx_
-                    s, e = ranges[t]
-                    assert g in gid[s:e]
+                    in_rect.add(v * n_tiles + ty_ * tx + tx_)
+            n_rect_pairs += len(in_rect)
+            listed = set(int(t) for t in key[gid == g] if t // n_tiles == v)
+            assert listed <= in_rect
+            sp = raster._support(g, p, sc.opacity, fp["rect"], thr)
+            rows, cols = np.nonzero(sp[7])
+            rows, cols = rows + sp[0][0].start, cols + sp[0][1].start
+            needed = set((v * n_tiles + (rows // tile[1]) * tx + cols // tile[0]).tolist())
+            assert needed <= listed, (v, g)
+    assert key.size < n_rect_pairs          # tiles the ellipse cannot reach are dropped
     for t in range(len(ranges)):
         s, e = ranges[t]
         assert np.all(key[s:e] == t)
@@ -211,3 +226,23 @@ def test_bin_pairs_structure(tile):
         order = np.lexsort((gid[s:e], d))
         assert np.all(order == np.arange(e - s))
     assert ranges[:, 1].max() == key.size
+
+
+def test_tile_members_match_bin_pairs():
+    thr = oracle.DEFAULT
+    sc = make_gaussians(300, 1, seed=13, log_scale_mean=-3.0)
+    cam = identity_camera(64, 48, f=70)
+    fp = binning.fp32_footprint(sc.means, sc.log_scales, sc.quats, cam, 16, 16, thr.k_sigma, sc.opacity,
+                                thr.alpha_min)
+    out = binning.bin_pairs([fp], 64, 48)
+    for t, (s, e) in enumerate(out["ranges"]):
+        got = binning.tile_members(fp, t % out["tiles_x"], t // out["tiles_x"])
+        assert np.array_equal(got, out["gauss"][s:e].astype(np.int64))
+
+
+def test_bin_pairs_requires_the_support_limit():
+    sc = make_gaussians(20, 1, seed=14)
+    cam = identity_camera(32, 32, f=40)
+    fp = binning.fp32_footprint(sc.means, sc.log_scales, sc.quats, cam)
+    with pytest.raises(ValueError):
+        binning.bin_pairs([fp], 32, 32)
