@@ -158,12 +158,15 @@ typedef struct chrf_grads {
  *                      4 (2 + per-Gaussian row length) bytes per pair and
  *                      two extra passes over it.
  *   fft_rows_plan      radix schedule of the row transforms when the padded
- *                      width is 3840 (0: 16*16*15, 1: 16*15*16, 2: 15*16*16);
+ *                      width is 3840 (0: 16*16*15, 1: 16*15*16, 2: 15*16*16)
+ *                      or 7680 (0: 16*20*24, 1: 16*24*20, 2: 24*20*16);
  *                      must be 0 for other widths
  *   fft_cols_plan      radix schedule of the column transforms when the
  *                      padded height is 2160 and cols_per_block is 2 (0:
- *                      16*15*9, 1: 16*9*15, 2: 15*16*9, 3: 12*12*15, forward
- *                      stage order); must be 0 otherwise.  Schedules change
+ *                      16*15*9, 1: 16*9*15, 2: 15*16*9, 3: 12*12*15), or
+ *                      4320 (cols_per_block 0 or 1; 0: 16*15*18, 1: 18*15*16,
+ *                      2: 15*18*16, 3: 16*18*15, 4: 18*16*15), in forward
+ *                      stage order; must be 0 otherwise.  Schedules change
  *                      rounding only (CHRF_EUNSUPPORTED for a value out of
  *                      range); the autotuner picks them.
  */

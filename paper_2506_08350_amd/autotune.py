@@ -2,8 +2,8 @@
 
 The searched configuration is the raster tile shape, the columns per
 workgroup of the column FFT pass and, where the padded grid has tuned
-transforms (width 3840, height 2160), the radix schedules of the row and of
-the column transforms.  Each candidate builds a plan, runs the fused training
+transforms (widths 3840 and 7680, heights 2160 and 4320), the radix schedules
+of the row and of the column transforms.  Each candidate builds a plan, runs the fused training
 step a few times and is timed with HIP events on the launch stream (median of
 the timed repetitions).  The search is coordinate-wise: the tile with the
 default transforms first, then the columns per workgroup, then the row
@@ -24,9 +24,10 @@ from . import api
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "chrf_autotune.json")
 
 TILES = ((16, 16), (16, 8), (8, 16), (32, 8), (8, 8))
-COLS = (2, 4, 1)
-ROW_PLANS = (0, 1, 2)       # 3840: 16*16*15, 16*15*16, 15*16*16
-COL_PLANS = (0, 1, 2, 3)    # 2160: 16*15*9, 16*9*15, 15*16*9, 12*12*15 (two columns per workgroup)
+COLS = (0, 4, 1)            # 0: the library's choice for the padded height (2 at 2160, 1 at 4320)
+ROW_PLANS = (0, 1, 2)       # 3840: 16*16*15, 16*15*16, 15*16*16; 7680: 16*20*24, 16*24*20, 24*20*16
+COL_PLANS = (0, 1, 2, 3, 4)  # 2160 (two columns per workgroup): 16*15*9, 16*9*15, 15*16*9, 12*12*15;
+#                             4320: 16*15*18, 18*15*16, 15*18*16, 16*18*15, 18*16*15
 
 
 def shape_key(height, width, n_lambda, n_planes, n_views, n_gaussians, pad):

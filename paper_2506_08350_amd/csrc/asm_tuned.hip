@@ -107,9 +107,12 @@ __device__ inline cpx transfer_free(const HParam& hp, float q) {
   return cpx{__builtin_amdgcn_cosf(rev), __builtin_amdgcn_sinf(rev)};
 }
 
-template <int N_, int NT, int R1_, int R2, int R3_>
+template <int N_, int NT_, int R1_, int R2, int R3_>
 struct RowT {
-  static constexpr int N = N_, R1 = R1_, R3 = R3_;
+  static constexpr int N = N_, NT = NT_, R1 = R1_, R3 = R3_;
+  // 512-thread rows keep 4 waves per SIMD (two workgroups per CU, as their
+  // LDS allows): at most 128 VGPRs
+  static constexpr int kMinWaves = NT > 256 ? 4 : 1;
   using Fwd = Fft3<N, 1, NT, R1, R2, R3, false>;
   using Inv = Fft3<N, 1, NT, R1, R2, R3, true>;
   using FwdRev = Fft3<N, 1, NT, R3, R2, R1, false>;   // takes Inv's outputs as inputs
@@ -122,7 +125,7 @@ struct RowT {
 // cropped is known at compile time and the corresponding butterfly
 // arithmetic folds away.
 template <class RT, bool HALF>
-__global__ __launch_bounds__(256) void k_rows_forward_t(const float2* __restrict__ in, float2* __restrict__ out,
+__global__ __launch_bounds__(RT::NT, RT::kMinWaves) void k_rows_forward_t(const float2* __restrict__ in, float2* __restrict__ out,
                                                         AsmGeom g, FftDesc fr) {
   __shared__ cpx lds[lds_padded_size(RT::N)];
   const size_t row = blockIdx.x;
@@ -146,12 +149,12 @@ __global__ __launch_bounds__(256) void k_rows_forward_t(const float2* __restrict
 }
 
 template <class RT, bool HALF>
-__global__ __launch_bounds__(256) void k_rows_inverse_t(float2* __restrict__ y, AsmGeom g, FftDesc fr,
+__global__ __launch_bounds__(RT::NT, RT::kMinWaves) void k_rows_inverse_t(float2* __restrict__ y, AsmGeom g, FftDesc fr,
                                                         float2* __restrict__ prop_out, float* __restrict__ intensity,
                                                         const float* __restrict__ target,
                                                         float* __restrict__ loss_partial, float grad_coef, int fuse) {
   __shared__ cpx lds[lds_padded_size(RT::N)];
-  __shared__ float red[4];
+  __shared__ float red[RT::NT / 64];
   const size_t row = blockIdx.x;
   float2* yrow = y + row * (size_t)g.pW;
   const int j = threadIdx.x;
@@ -185,7 +188,12 @@ __global__ __launch_bounds__(256) void k_rows_inverse_t(float2* __restrict__ y, 
     for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
     __syncthreads();
-    if (threadIdx.x == 0) loss_partial[row] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) {
+      float t = red[0];
+#pragma unroll
+      for (int w = 1; w < RT::NT / 64; ++w) t += red[w];
+      loss_partial[row] = t;
+    }
   }
   if (fuse) {
     cpx w3[1][RT::R1];
@@ -198,7 +206,7 @@ __global__ __launch_bounds__(256) void k_rows_inverse_t(float2* __restrict__ y, 
 }
 
 template <class RT, bool HALF>
-__global__ __launch_bounds__(256) void k_rows_adjoint_in_t(const float2* __restrict__ prop,
+__global__ __launch_bounds__(RT::NT, RT::kMinWaves) void k_rows_adjoint_in_t(const float2* __restrict__ prop,
                                                            const float* __restrict__ dL_dI,
                                                            const float2* __restrict__ dL_dprop,
                                                            float2* __restrict__ z, AsmGeom g, FftDesc fr) {
@@ -228,7 +236,7 @@ __global__ __launch_bounds__(256) void k_rows_adjoint_in_t(const float2* __restr
 }
 
 template <class RT, bool HALF>
-__global__ __launch_bounds__(256) void k_rows_adjoint_out_t(const float2* __restrict__ w1,
+__global__ __launch_bounds__(RT::NT, RT::kMinWaves) void k_rows_adjoint_out_t(const float2* __restrict__ w1,
                                                             const float2* __restrict__ dL_dfield,
                                                             float2* __restrict__ grad_field, AsmGeom g, FftDesc fr) {
   __shared__ cpx lds[lds_padded_size(RT::N)];
@@ -263,29 +271,35 @@ __global__ __launch_bounds__(256) void k_rows_adjoint_out_t(const float2* __rest
 //          inverse transforms read) and the twiddles are read through the
 //          vector cache, so the LDS holds only the work buffer and two
 //          workgroups share a CU.
-constexpr int kColN = 2160;
-
+//   Columns of 4320 (the 2160 x 3840 field): one column per workgroup of 320
+//          threads (the largest stage has 288 butterflies), spectrum in
+//          registers.
+//
 // R1 R2 R3: radices of the forward column transform in stage order; the
 // inverse runs them in reverse order, so that each thread's R3 forward
-// outputs are the inputs of its inverse butterfly.
-template <int C_, int R1_ = 16, int R2_ = 15, int R3_ = 9>
+// outputs are the inputs of its inverse butterfly.  N: column length; NT:
+// threads, at least the butterflies of every stage.
+template <int C_, int R1_ = 16, int R2_ = 15, int R3_ = 9, int N_ = 2160, int NT_ = 256 * C_>
 struct ColT {
-  static constexpr int C = C_, R1 = R1_, R2 = R2_, R3 = R3_;
-  static constexpr int NT = 256 * C;
-  static constexpr int S1 = kColN / R1, S3 = kColN / R3;
+  static constexpr int C = C_, R1 = R1_, R2 = R2_, R3 = R3_, N = N_;
+  static constexpr int NT = NT_;
+  static constexpr int S1 = N / R1, S3 = N / R3;
   // LDS layouts with the fewest bank conflicts for the column strides: one
   // padding slot per 16 values in the forward transform, none in the inverse
   // (which then needs no address arithmetic either)
   static constexpr int kPadFwd = 4, kPadInv = 0;
-  static constexpr int kLdsElems = lds_padded_size(kColN * C, kPadFwd);
-  using Fwd = Fft3<kColN, C, NT, R1, R2, R3, false, kPadFwd>;
-  using Inv = Fft3<kColN, C, NT, R3, R2, R1, true, kPadInv>;
+  static constexpr int kLdsElems = lds_padded_size(N * C, kPadFwd);
+  using Fwd = Fft3<N, C, NT, R1, R2, R3, false, kPadFwd>;
+  using Inv = Fft3<N, C, NT, R3, R2, R1, true, kPadInv>;
   static_assert(Fwd::M1 == 1 && Fwd::M3 == 1 && Inv::M1 == 1 && Inv::M3 == 1, "one butterfly per thread");
   static_assert(Fwd::B3 == Inv::B1, "forward outputs feed the inverse inputs");
   static constexpr int SPAN = 128 / (8 * C);   // column groups per 128-byte line
   static constexpr bool kRegSpec = C <= 2;      // spectrum in registers, twiddles from memory
   static constexpr bool kLdsTw = !kRegSpec;     // twiddle table in LDS, read per power
-  static constexpr int kMinBlocks = C == 1 ? 4 : (C == 2 ? 2 : 1);
+  // occupancy hint, in waves per SIMD (bounds the VGPRs: 512 / waves); the
+  // 4320 transforms take three, below which their radix-15..18 butterflies
+  // and register-held spectrum would spill
+  static constexpr int kMinWaves = N != 2160 ? 3 : (C == 1 ? 4 : (C == 2 ? 2 : 1));
   // half-height field: input (and kept output) r of a first-stage butterfly
   // is a field row iff r < R1 / 2 when R1 is even; otherwise decided per row
   static constexpr bool kEvenSplit = R1 % 2 == 0;
@@ -303,22 +317,22 @@ __device__ inline int col_remap(int id, int nblocks, int span) {
 
 // The N twiddles are copied to LDS once per workgroup: the stages of every
 // plane read them there instead of through the vector caches.
-template <int NT>
+template <int N, int NT>
 __device__ inline const cpx* stage_twiddles(cpx* s_tw, const cpx* __restrict__ tw) {
-  for (int i = threadIdx.x; i < kColN; i += NT) s_tw[i] = tw[i];
+  for (int i = threadIdx.x; i < N; i += NT) s_tw[i] = tw[i];
   __syncthreads();
   return s_tw;
 }
 
 template <class CT, bool HALF>
-__global__ __launch_bounds__(CT::NT, CT::kMinBlocks) void k_cols_forward_t(const float2* __restrict__ x1,
+__global__ __launch_bounds__(CT::NT, CT::kMinWaves) void k_cols_forward_t(const float2* __restrict__ x1,
                                                                           float2* __restrict__ y, AsmGeom g,
                                                                           FftDesc fc) {
   constexpr int C = CT::C, R1 = CT::R1, R3 = CT::R3;
   __shared__ cpx lds[CT::kLdsElems];
-  __shared__ cpx spec[CT::kRegSpec ? 1 : kColN * C];
-  __shared__ cpx s_tw[CT::kLdsTw ? kColN : 1];
-  const cpx* twl = CT::kLdsTw ? stage_twiddles<CT::NT>(s_tw, fc.tw) : fc.tw;
+  __shared__ cpx spec[CT::kRegSpec ? 1 : CT::N * C];
+  __shared__ cpx s_tw[CT::kLdsTw ? CT::N : 1];
+  const cpx* twl = CT::kLdsTw ? stage_twiddles<CT::N, CT::NT>(s_tw, fc.tw) : fc.tw;
   cpx sreg[CT::kRegSpec ? R3 : 1];
   const int ngroups = g.pW / C;
   const int gid = col_remap(blockIdx.x, gridDim.x, CT::SPAN);
@@ -404,16 +418,16 @@ typedef __attribute__((address_space(1))) void gmem_void;
 typedef __attribute__((address_space(3))) void lds_void;
 
 template <class CT, bool HALF>
-__global__ __launch_bounds__(CT::NT, CT::kMinBlocks) void k_cols_adjoint_t(const float2* __restrict__ z,
+__global__ __launch_bounds__(CT::NT, CT::kMinWaves) void k_cols_adjoint_t(const float2* __restrict__ z,
                                                                           float2* __restrict__ w1out, AsmGeom g,
                                                                           FftDesc fc) {
   constexpr int C = CT::C, R1 = CT::R1, R3 = CT::R3;
   constexpr bool kDma = HALF && C == 2;
-  constexpr int kLiveRows = kColN / 2;
+  constexpr int kLiveRows = CT::N / 2;
   __shared__ cpx lds[CT::kLdsElems];
-  __shared__ cpx s_tw[CT::kLdsTw ? kColN : 1];
+  __shared__ cpx s_tw[CT::kLdsTw ? CT::N : 1];
   __shared__ cpx s_in[kDma ? kLiveRows * C : 1];   // [row][column]
-  const cpx* twl = CT::kLdsTw ? stage_twiddles<CT::NT>(s_tw, fc.tw) : fc.tw;
+  const cpx* twl = CT::kLdsTw ? stage_twiddles<CT::N, CT::NT>(s_tw, fc.tw) : fc.tw;
   const int ngroups = g.pW / C;
   const int gid = col_remap(blockIdx.x, gridDim.x, CT::SPAN);
   const int bl = gid / ngroups;
@@ -506,18 +520,23 @@ __global__ __launch_bounds__(CT::NT, CT::kMinBlocks) void k_cols_adjoint_t(const
 }
 
 // Radix schedules of the tuned transforms (AsmGeom::row_plan, col_plan):
-//   rows of 3840:     0: 16 16 15   1: 16 15 16   2: 15 16 16
-//   columns of 2160:  0: 16 15 9    1: 16 9 15    2: 15 16 9    3: 12 12 15
+//   rows of 3840 (256 threads):     0: 16 16 15   1: 16 15 16   2: 15 16 16
+//   rows of 7680 (512 threads):     0: 16 20 24   1: 16 24 20   2: 24 20 16
+//   columns of 2160 (C = 2):        0: 16 15 9    1: 16 9 15    2: 15 16 9    3: 12 12 15
+//   columns of 4320 (C = 1):        0: 16 15 18   1: 18 15 16   2: 15 18 16   3: 16 18 15   4: 18 16 15
 // (forward stage order).  Every schedule keeps one butterfly per thread in
 // the first and the last stage.
 using Row3840 = RowT<3840, 256, 16, 16, 15>;
 
-bool tuned_rows(const AsmGeom& g) { return g.pW == 3840; }
+bool tuned_rows(const AsmGeom& g) { return g.pW == 3840 || g.pW == 7680; }
 // (band mode 0 with evanescent bins present needs the decaying continuation,
 // which only the generic passes form)
-bool tuned_cols(const AsmGeom& g) { return g.pH == kColN && g.pW % 128 == 0 && !(g.band_mode == 0 && g.evanescent); }
-int tuned_row_plans() { return 3; }
-int tuned_col_plans() { return 4; }
+bool tuned_cols(const AsmGeom& g) {
+  return (g.pH == 2160 || g.pH == 4320) && g.pW % 128 == 0 && !(g.band_mode == 0 && g.evanescent);
+}
+int tuned_row_plans(const AsmGeom&) { return 3; }
+int tuned_col_plans(const AsmGeom& g) { return g.pH == 4320 ? 5 : 4; }
+int tuned_cols_per_block(const AsmGeom& g) { return g.pH == 4320 ? 1 : 2; }
 
 static bool rows_half(const AsmGeom& g) { return 2 * g.W == g.pW; }
 static bool cols_half(const AsmGeom& g) { return 2 * g.H == g.pH; }
@@ -525,10 +544,18 @@ static bool cols_half(const AsmGeom& g) { return 2 * g.H == g.pH; }
 // Calls f(RT{}) with the row transform type of the plan's radix schedule.
 template <class F>
 static hipError_t with_row_plan(const AsmGeom& g, F&& f) {
-  switch (g.row_plan) {
-    case 1: f(RowT<3840, 256, 16, 15, 16>{}); break;
-    case 2: f(RowT<3840, 256, 15, 16, 16>{}); break;
-    default: f(Row3840{}); break;
+  if (g.pW == 7680) {
+    switch (g.row_plan) {
+      case 1: f(RowT<7680, 512, 16, 24, 20>{}); break;
+      case 2: f(RowT<7680, 512, 24, 20, 16>{}); break;
+      default: f(RowT<7680, 512, 16, 20, 24>{}); break;
+    }
+  } else {
+    switch (g.row_plan) {
+      case 1: f(RowT<3840, 256, 16, 15, 16>{}); break;
+      case 2: f(RowT<3840, 256, 15, 16, 16>{}); break;
+      default: f(Row3840{}); break;
+    }
   }
   return hipGetLastError();
 }
@@ -538,9 +565,9 @@ hipError_t launch_rows_forward_t(const float2* in, float2* out, const AsmGeom& g
   return with_row_plan(g, [&](auto rt) {
     using RT = decltype(rt);
     if (rows_half(g))
-      k_rows_forward_t<RT, true><<<grid, 256, 0, s>>>(in, out, g, fr);
+      k_rows_forward_t<RT, true><<<grid, RT::NT, 0, s>>>(in, out, g, fr);
     else
-      k_rows_forward_t<RT, false><<<grid, 256, 0, s>>>(in, out, g, fr);
+      k_rows_forward_t<RT, false><<<grid, RT::NT, 0, s>>>(in, out, g, fr);
   });
 }
 hipError_t launch_rows_inverse_t(float2* y, const AsmGeom& g, const FftDesc& fr, float2* prop_out, float* intensity,
@@ -549,10 +576,10 @@ hipError_t launch_rows_inverse_t(float2* y, const AsmGeom& g, const FftDesc& fr,
   return with_row_plan(g, [&](auto rt) {
     using RT = decltype(rt);
     if (rows_half(g))
-      k_rows_inverse_t<RT, true><<<grid, 256, 0, s>>>(y, g, fr, prop_out, intensity, target, loss_partial, grad_coef,
+      k_rows_inverse_t<RT, true><<<grid, RT::NT, 0, s>>>(y, g, fr, prop_out, intensity, target, loss_partial, grad_coef,
                                                       fuse ? 1 : 0);
     else
-      k_rows_inverse_t<RT, false><<<grid, 256, 0, s>>>(y, g, fr, prop_out, intensity, target, loss_partial, grad_coef,
+      k_rows_inverse_t<RT, false><<<grid, RT::NT, 0, s>>>(y, g, fr, prop_out, intensity, target, loss_partial, grad_coef,
                                                        fuse ? 1 : 0);
   });
 }
@@ -562,9 +589,9 @@ hipError_t launch_rows_adjoint_in_t(const float2* prop, const float* dL_dI, cons
   return with_row_plan(g, [&](auto rt) {
     using RT = decltype(rt);
     if (rows_half(g))
-      k_rows_adjoint_in_t<RT, true><<<grid, 256, 0, s>>>(prop, dL_dI, dL_dprop, z, g, fr);
+      k_rows_adjoint_in_t<RT, true><<<grid, RT::NT, 0, s>>>(prop, dL_dI, dL_dprop, z, g, fr);
     else
-      k_rows_adjoint_in_t<RT, false><<<grid, 256, 0, s>>>(prop, dL_dI, dL_dprop, z, g, fr);
+      k_rows_adjoint_in_t<RT, false><<<grid, RT::NT, 0, s>>>(prop, dL_dI, dL_dprop, z, g, fr);
   });
 }
 hipError_t launch_rows_adjoint_out_t(const float2* w1, const float2* dL_dfield, float2* grad_field, const AsmGeom& g,
@@ -573,18 +600,26 @@ hipError_t launch_rows_adjoint_out_t(const float2* w1, const float2* dL_dfield, 
   return with_row_plan(g, [&](auto rt) {
     using RT = decltype(rt);
     if (rows_half(g))
-      k_rows_adjoint_out_t<RT, true><<<grid, 256, 0, s>>>(w1, dL_dfield, grad_field, g, fr);
+      k_rows_adjoint_out_t<RT, true><<<grid, RT::NT, 0, s>>>(w1, dL_dfield, grad_field, g, fr);
     else
-      k_rows_adjoint_out_t<RT, false><<<grid, 256, 0, s>>>(w1, dL_dfield, grad_field, g, fr);
+      k_rows_adjoint_out_t<RT, false><<<grid, RT::NT, 0, s>>>(w1, dL_dfield, grad_field, g, fr);
   });
 }
 
 // Calls f(CT{}) with the column transform type of (C, the plan's radix
-// schedule); schedules other than 0 exist for C = 2 only (plan creation
-// checks this).
+// schedule); at height 2160, schedules other than 0 exist for C = 2 only
+// (plan creation checks this).
 template <class F>
 static hipError_t with_col_plan(const AsmGeom& g, int C, F&& f) {
-  if (C == 1) {
+  if (g.pH == 4320) {   // one column per workgroup (plan creation checks C)
+    switch (g.col_plan) {
+      case 1: f(ColT<1, 18, 15, 16, 4320, 320>{}); break;
+      case 2: f(ColT<1, 15, 18, 16, 4320, 320>{}); break;
+      case 3: f(ColT<1, 16, 18, 15, 4320, 320>{}); break;
+      case 4: f(ColT<1, 18, 16, 15, 4320, 320>{}); break;
+      default: f(ColT<1, 16, 15, 18, 4320, 320>{}); break;
+    }
+  } else if (C == 1) {
     f(ColT<1>{});
   } else if (C == 4) {
     f(ColT<4>{});

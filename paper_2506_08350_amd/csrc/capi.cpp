@@ -374,7 +374,12 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   if ((int64_t)2 * 8 * p->pW > ctx->lds_per_block)
     return bad(fail(CHRF_EUNSUPPORTED, "plan: a padded row does not fit the LDS"));
   int C = d.cols_per_block;
-  if (tuned_cols(geom(p))) {
+  if (tuned_cols(geom(p)) && p->pH == 4320) {
+    // tuned column pass of 4320: one column per workgroup
+    if (C != 0 && C != 1)
+      return bad(fail(CHRF_EUNSUPPORTED, "plan: cols_per_block must be 1 for a padded height of 4320"));
+    C = 1;
+  } else if (tuned_cols(geom(p))) {
     // tuned column pass: 2 columns x 512 threads (default), 1 x 256 or 4 x 1024
     if (C != 0 && C != 1 && C != 2 && C != 4)
       return bad(fail(CHRF_EUNSUPPORTED, "plan: cols_per_block must be 1, 2 or 4 for this padded height"));
@@ -392,13 +397,14 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   }
   p->cols_per_block = C;
   // radix schedules of the tuned transforms
-  if (d.fft_rows_plan != 0 && (!tuned_rows(geom(p)) || d.fft_rows_plan < 0 || d.fft_rows_plan >= tuned_row_plans()))
-    return bad(fail(CHRF_EUNSUPPORTED, "plan: fft_rows_plan must be 0 unless the padded width is 3840 (then 0.." +
-                                           std::to_string(tuned_row_plans() - 1) + ")"));
-  if (d.fft_cols_plan != 0 && (!tuned_cols(geom(p)) || C != 2 || d.fft_cols_plan < 0 ||
-                               d.fft_cols_plan >= tuned_col_plans()))
+  if (d.fft_rows_plan != 0 && (!tuned_rows(geom(p)) || d.fft_rows_plan < 0 ||
+                               d.fft_rows_plan >= tuned_row_plans(geom(p))))
+    return bad(fail(CHRF_EUNSUPPORTED, "plan: fft_rows_plan must be 0 unless the padded width is 3840 or 7680 (then "
+                                       "0.." + std::to_string(tuned_row_plans(geom(p)) - 1) + ")"));
+  if (d.fft_cols_plan != 0 && (!tuned_cols(geom(p)) || C != tuned_cols_per_block(geom(p)) || d.fft_cols_plan < 0 ||
+                               d.fft_cols_plan >= tuned_col_plans(geom(p))))
     return bad(fail(CHRF_EUNSUPPORTED, "plan: fft_cols_plan must be 0 unless the padded height is 2160 with two "
-                                       "columns per workgroup (then 0.." + std::to_string(tuned_col_plans() - 1) + ")"));
+                                       "columns per workgroup (then 0..3) or 4320 (then 0..4)"));
   // transfer-function parameters
   std::vector<HParam> hp(p->L * p->K);
   const double dfx = 1.0 / (p->pW * d.pitch), dfy = 1.0 / (p->pH * d.pitch);

@@ -213,3 +213,69 @@ def test_radix_schedules_at_full_size(plans):
         I = np.abs(u) ** 2
         ref += oracle.propagate_adjoint(2.0 * u * (2.0 * (I - tg[0, li, k]) / numel), lams[li], z, 8e-6, 2, 2)
     assert rel_l2(GU[0, li], ref) < TOL
+
+
+_LAMS_2160P, _ZS_2160P = (515e-9,), (0.8e-3, 1.6e-3)
+
+
+@pytest.fixture(scope="module")
+def field_2160p():
+    """A 2160 x 3840 field (padded 4320 x 7680), the adjoint inputs of two
+    planes, and the oracle's propagated second plane and summed adjoint,
+    computed once for every radix schedule below."""
+    H, W = 2160, 3840
+    rng = np.random.default_rng(21)
+    U = rng.uniform(0, 1, (1, 1, H, W)) * np.exp(2j * np.pi * rng.uniform(0, 1, (1, 1, H, W)))
+    G = (rng.normal(size=(1, 1, 2, H, W)) + 1j * rng.normal(size=(1, 1, 2, H, W))).astype(np.complex64)
+    lam = _LAMS_2160P[0]
+    prop_ref = oracle.propagate(U[0, 0], lam, _ZS_2160P[1], 8e-6, 2, 2)
+    adj_ref = sum(oracle.propagate_adjoint(G[0, 0, k].astype(np.complex128), lam, z, 8e-6, 2, 2)
+                  for k, z in enumerate(_ZS_2160P))
+    return U, G, prop_ref, adj_ref
+
+
+@pytest.mark.parametrize("plans", [(0, 0), (1, 0), (2, 0), (0, 1), (0, 2), (0, 3), (0, 4)])
+def test_radix_schedules_at_2160p(field_2160p, plans):
+    """The tuned transforms of the 2160 x 3840 geometry (rows of 7680 with
+    512 threads, columns of 4320 with one column per workgroup), every radix
+    schedule: one propagated plane and the adjoint summed over two planes
+    against the oracle."""
+    announce(f"radix schedules {plans} at 2160x3840")
+    U, G, prop_ref, adj_ref = field_2160p
+    H, W = U.shape[2:]
+    opt = Optics(_LAMS_2160P, _ZS_2160P, 8e-6, 2, 2)
+    r = make_renderer([identity_camera(W, H)], opt, 1, fft_plans=plans)
+    prop, _ = r.propagate(_to_gpu(U), want_intensity=False)
+    torch.cuda.synchronize()
+    assert rel_l2(cplx(prop[0, 0, 1]), prop_ref) < TOL
+    del prop
+    back = r.propagate_adjoint(torch.from_numpy(np.stack([G.real, G.imag], -1)).cuda())
+    torch.cuda.synchronize()
+    assert rel_l2(cplx(back[0, 0]), adj_ref) < TOL
+
+
+@pytest.mark.parametrize("row_plan", [0, 1, 2])
+def test_fused_training_rows_at_2160p(row_plan):
+    """The fused inverse row pass of 7680 (inverse transform, |u|^2, MSE, then
+    G = 2 u dL/dI transformed forward again with the reversed schedule) in a
+    training step at 2160 x 3840, one plane: dL/dU against the oracle's
+    adjoint propagation of 2 u dL/dI computed from the GPU's own field."""
+    from paper_2506_08350_amd import _lib, api
+    from scenegen import make_gaussians, make_targets
+    from tests.gpu_helpers import to_device
+
+    announce(f"fused training rows, row plan {row_plan}, 2160x3840")
+    H, W = 2160, 3840
+    lam, z = 515e-9, 1.2e-3
+    opt = Optics((lam,), (z,), 8e-6, 2, 2)
+    cam = identity_camera(W, H)
+    r = make_renderer([cam], opt, 3000, fft_plans=(row_plan, 0))
+    sc = make_gaussians(3000, 1, 91, x_range=(-0.3, 0.3), y_range=(-0.2, 0.2), log_scale_mean=-3.0)
+    tg = make_targets((1, 1, 1, H, W), 92)
+    r.train_step(to_device(sc), api.pack_cameras([cam]), torch.from_numpy(tg).cuda())
+    torch.cuda.synchronize()
+    Uf = cplx(r.region(_lib.REGION_FIELD, torch.float32).view(1, 1, H, W, 2))
+    GU = cplx(r.region(_lib.REGION_GRAD_FIELD, torch.float32).view(1, 1, H, W, 2))
+    u = oracle.propagate(Uf[0, 0], lam, z, 8e-6, 2, 2)
+    ref = oracle.propagate_adjoint(2.0 * u * (2.0 * (np.abs(u) ** 2 - tg[0, 0, 0]) / tg.size), lam, z, 8e-6, 2, 2)
+    assert rel_l2(GU[0, 0], ref) < TOL
