@@ -163,10 +163,11 @@ typedef struct chrf_grads {
  *                      must be 0 for other widths
  *   fft_cols_plan      radix schedule of the column transforms when the
  *                      padded height is 2160 and cols_per_block is 2 (0:
- *                      16*15*9, 1: 16*9*15, 2: 15*16*9, 3: 12*12*15), or
- *                      4320 (cols_per_block 0 or 1; 0: 16*15*18, 1: 18*15*16,
- *                      2: 15*18*16, 3: 16*18*15, 4: 18*16*15), in forward
- *                      stage order; must be 0 otherwise.  Schedules change
+ *                      16*15*9, 1: 16*9*15, 2: 15*16*9, 3: 12*12*15, in
+ *                      forward stage order), or 4320 with height = 2160
+ *                      (cols_per_block 0 or 1; each column runs as two
+ *                      transforms of 2160 with the same four schedules);
+ *                      must be 0 otherwise.  Schedules change
  *                      rounding only (CHRF_EUNSUPPORTED for a value out of
  *                      range); the autotuner picks them.
  */

@@ -26,8 +26,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "chrf_autotune.j
 TILES = ((16, 16), (16, 8), (8, 16), (32, 8), (8, 8))
 COLS = (0, 4, 1)            # 0: the library's choice for the padded height (2 at 2160, 1 at 4320)
 ROW_PLANS = (0, 1, 2)       # 3840: 16*16*15, 16*15*16, 15*16*16; 7680: 16*20*24, 16*24*20, 24*20*16
-COL_PLANS = (0, 1, 2, 3, 4)  # 2160 (two columns per workgroup): 16*15*9, 16*9*15, 15*16*9, 12*12*15;
-#                             4320: 16*15*18, 18*15*16, 15*18*16, 16*18*15, 18*16*15
+COL_PLANS = (0, 1, 2, 3)    # 2160 (and 4320 as two of 2160): 16*15*9, 16*9*15, 15*16*9, 12*12*15
 
 
 def shape_key(height, width, n_lambda, n_planes, n_views, n_gaussians, pad):

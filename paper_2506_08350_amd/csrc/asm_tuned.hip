@@ -271,10 +271,6 @@ __global__ __launch_bounds__(RT::NT, RT::kMinWaves) void k_rows_adjoint_out_t(co
 //          inverse transforms read) and the twiddles are read through the
 //          vector cache, so the LDS holds only the work buffer and two
 //          workgroups share a CU.
-//   Columns of 4320 (the 2160 x 3840 field): one column per workgroup of 320
-//          threads (the largest stage has 288 butterflies), spectrum in
-//          registers.
-//
 // R1 R2 R3: radices of the forward column transform in stage order; the
 // inverse runs them in reverse order, so that each thread's R3 forward
 // outputs are the inputs of its inverse butterfly.  N: column length; NT:
@@ -296,10 +292,8 @@ struct ColT {
   static constexpr int SPAN = 128 / (8 * C);   // column groups per 128-byte line
   static constexpr bool kRegSpec = C <= 2;      // spectrum in registers, twiddles from memory
   static constexpr bool kLdsTw = !kRegSpec;     // twiddle table in LDS, read per power
-  // occupancy hint, in waves per SIMD (bounds the VGPRs: 512 / waves); the
-  // 4320 transforms take three, below which their radix-15..18 butterflies
-  // and register-held spectrum would spill
-  static constexpr int kMinWaves = N != 2160 ? 3 : (C == 1 ? 4 : (C == 2 ? 2 : 1));
+  // occupancy hint, in waves per SIMD (bounds the VGPRs: 512 / waves)
+  static constexpr int kMinWaves = C == 1 ? 4 : (C == 2 ? 2 : 1);
   // half-height field: input (and kept output) r of a first-stage butterfly
   // is a field row iff r < R1 / 2 when R1 is even; otherwise decided per row
   static constexpr bool kEvenSplit = R1 % 2 == 0;
@@ -519,11 +513,186 @@ __global__ __launch_bounds__(CT::NT, CT::kMinWaves) void k_cols_adjoint_t(const 
   }
 }
 
+// ------------------------------------------------- columns of 2 x 2160 ---
+// Columns of pH = 2 NH whose lower half is zero padding (H = NH) as two
+// transforms of NH.  With w = exp(-2 pi i / pH), the spectrum's even bins 2m
+// are the NH-point transform of x[n] and its odd bins 2m + 1 that of
+// x[n] w^n; after the transfer function, the kept rows n < NH of the inverse
+// are a[n] + w^-n b[n], a and b the (unnormalised) NH-point inverse
+// transforms of the even and of the odd bins.  The two halves run as the two
+// interleaved sequences of a C = 2 transform of NH (s = 0: even bins, s = 1:
+// odd bins), so one column takes the layout, schedules and occupancy of the
+// tuned NH transforms; the lanes (s = 0, 1) of each butterfly index j hold
+// a and b at the same rows and exchange them to combine.  w^n, n < NH, is
+// staged in LDS once per workgroup.
+constexpr int kSplitSpan = 16;   // one 8-byte column per workgroup: 16 share a 128-byte line
+
+template <class CT>
+__device__ inline void stage_split_twiddles(cpx* s_w, const cpx* __restrict__ tw) {
+  for (int i = threadIdx.x; i < CT::N; i += CT::NT) s_w[i] = tw[i];
+}
+
+// Rows n = j + q S1 of a (s = 0) and b (s = 1) in w3: lane s stores the rows
+// with q = s mod 2, out[n] = a[n] + conj(w^n) b[n] (column pointer col).
+template <class CT>
+__device__ inline void store_split(cpx (&w3)[1][CT::R1], const cpx* s_w, float2* col, int pW, int j, int s) {
+#pragma unroll
+  for (int q = 0; q < CT::R1; ++q) {
+    const cpx mine = w3[0][q];
+    const cpx other{__shfl_xor(mine.x, 1, 64), __shfl_xor(mine.y, 1, 64)};
+    if ((q & 1) == s) {
+      const int n = j + q * CT::S1;
+      const cpx a = s ? other : mine, b = s ? mine : other;
+      stc(col + (size_t)n * pW, a + cmulc(b, s_w[n]));
+    }
+  }
+}
+
+template <class CT>
+__global__ __launch_bounds__(CT::NT, 4) void k_cols_forward_split(const float2* __restrict__ x1,
+                                                                  float2* __restrict__ y, AsmGeom g, FftDesc fc) {
+  static_assert(CT::C == 2 && CT::kRegSpec, "two half-length sequences, spectrum in registers");
+  constexpr int R1 = CT::R1, R3 = CT::R3;
+  __shared__ cpx lds[CT::kLdsElems];
+  __shared__ cpx s_w[CT::N];
+  __shared__ float s_q[R3][CT::NT];   // plane-independent transfer terms (each thread reads its own)
+  const int gid = col_remap(blockIdx.x, gridDim.x, kSplitSpan);
+  const int bl = gid / g.pW, col = gid % g.pW;
+  const int lam = bl % g.n_lambda;
+  const int b = threadIdx.x;
+  const int s = b & 1, j = b >> 1;
+  stage_split_twiddles<CT>(s_w, fc.tw);
+  __syncthreads();
+  cpx sreg[R3];
+  {
+    cpx v1[1][R1], v3[1][R3];
+    if (b < CT::Fwd::B1) {
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const int n = j + r * CT::S1;
+        const cpx x = ldc(x1 + ((size_t)bl * g.H + n) * g.pW + col);
+        v1[0][r] = s ? cmul(x, s_w[n]) : x;
+      }
+    }
+    if (b < CT::Inv::B1) {
+      const HParam hp0 = load_hparam(g.hp, lam * g.K);
+      const ColFreq cf = col_freq(hp0, col, g);
+#pragma unroll
+      for (int q = 0; q < R3; ++q) s_q[q][b] = transfer_q(hp0, cf, 2 * (j + q * CT::S3) + s, g);
+    }
+    CT::Fwd::template run<false>(v1, v3, lds, fc.tw_half);
+    if (b < CT::Fwd::B3) {
+#pragma unroll
+      for (int q = 0; q < R3; ++q) sreg[q] = v3[0][q] * g.norm;
+    }
+  }
+  const typename CT::Inv::StageTw itw = CT::Inv::stage_twiddles_of(fc.tw_half, b);
+  for (int k = 0; k < g.K; ++k) {
+    const HParam hp = load_hparam(g.hp, lam * g.K + k);
+    const int jj = opaque_v(j), kx = opaque_v(col);
+    cpx w1[1][R3], w3[1][R1];
+    if (b < CT::Inv::B1) {
+      if (g.mask_free) {   // uniform
+#pragma unroll
+        for (int q = 0; q < R3; ++q) w1[0][q] = cmul(sreg[q], transfer_free(hp, s_q[q][b]));
+      } else {
+        const bool col_pass = g.band_mode < 2 || abs(sbin(kx, g.pW)) <= hp.kx_max;
+#pragma unroll
+        for (int q = 0; q < R3; ++q)
+          w1[0][q] = cmul(sreg[q], transfer_from_q(hp, col_pass, s_q[q][b], 2 * (jj + q * CT::S3) + s, g));
+      }
+    }
+    CT::Inv::run_with_twiddles(w1, w3, lds, itw, opaque_v(b));
+    if (b < CT::Inv::B3)
+      store_split<CT>(w3, s_w, y + ((size_t)bl * g.K + k) * g.H * g.pW + kx, g.pW, jj, s);
+  }
+}
+
+// The adjoint reads K input columns, one per plane: plane k + 1 is copied
+// from HBM straight into an LDS buffer (global_load_lds, 4 bytes per lane,
+// so a wave moves 32 rows of the column) while plane k's transform runs.
+// The transfer terms are formed per plane (the LDS holds the copy instead).
+template <class CT>
+__global__ __launch_bounds__(CT::NT, 4) void k_cols_adjoint_split(const float2* __restrict__ z,
+                                                                  float2* __restrict__ w1out, AsmGeom g,
+                                                                  FftDesc fc) {
+  static_assert(CT::C == 2, "two half-length sequences");
+  constexpr int R1 = CT::R1, R3 = CT::R3;
+  constexpr int kFloats = 2 * CT::N;   // one plane of the column
+  __shared__ cpx lds[CT::kLdsElems];
+  __shared__ float s_in[kFloats];
+  __shared__ cpx s_w[CT::N];
+  const int gid = col_remap(blockIdx.x, gridDim.x, kSplitSpan);
+  const int bl = gid / g.pW, col = gid % g.pW;
+  const int lam = bl % g.n_lambda;
+  const int b = threadIdx.x;
+  const int s = b & 1, j = b >> 1;
+  // wave w copies floats 64 i .. 64 i + 63 of the plane for i = w, w + NT / 64, ...
+  auto copy_plane = [&](int k) {
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const float* zk = reinterpret_cast<const float*>(z + ((size_t)bl * g.K + k) * g.H * g.pW + col);
+    for (int i = w; i * 64 < kFloats; i += CT::NT / 64) {
+      const int e = i * 64 + lane;
+      if (e < kFloats)
+        __builtin_amdgcn_global_load_lds((const gmem_void*)(zk + (size_t)(e >> 1) * 2 * g.pW + (e & 1)),
+                                         (lds_void*)&s_in[i * 64], 4, 0, 0);
+    }
+  };
+  auto copies_visible = [] {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    __syncthreads();
+  };
+  stage_split_twiddles<CT>(s_w, fc.tw);
+  copy_plane(0);
+  copies_visible();
+  cpx acc[1][R3];
+#pragma unroll
+  for (int q = 0; q < R3; ++q) acc[0][q] = cpx{0.f, 0.f};
+  for (int k = 0; k < g.K; ++k) {
+    const HParam hp = load_hparam(g.hp, lam * g.K + k);
+    const int jj = opaque_v(j), kx = opaque_v(col);
+    cpx v1[1][R1], v3[1][R3];
+    if (b < CT::Fwd::B1) {
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const int n = jj + r * CT::S1;
+        const cpx x{s_in[2 * n], s_in[2 * n + 1]};
+        v1[0][r] = s ? cmul(x, s_w[n]) : x;
+      }
+    }
+    // stage 1 has read its inputs once the hook runs: the buffer is free
+    auto start_next = [&] {
+      if (k + 1 < g.K) copy_plane(k + 1);
+    };
+    CT::Fwd::template run_hooked<false, 1, true>(v1, v3, lds, fc.tw_half, start_next, opaque_v(b));
+    if (b < CT::Fwd::B3) {
+      const ColFreq cf = col_freq(hp, kx, g);
+      if (g.mask_free) {   // uniform
+#pragma unroll
+        for (int q = 0; q < R3; ++q)
+          acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_free(hp, transfer_q(hp, cf, 2 * (jj + q * CT::S3) + s, g)));
+      } else {
+#pragma unroll
+        for (int q = 0; q < R3; ++q) {
+          const int ky = 2 * (jj + q * CT::S3) + s;
+          acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_from_q(hp, cf.pass, transfer_q(hp, cf, ky, g), ky, g));
+        }
+      }
+    }
+    if (k + 1 < g.K) copies_visible();
+  }
+#pragma unroll
+  for (int q = 0; q < R3; ++q) acc[0][q] = acc[0][q] * g.norm;
+  cpx w3[1][R1];
+  CT::Inv::template run<false>(acc, w3, lds, fc.tw_half);
+  if (b < CT::Inv::B3) store_split<CT>(w3, s_w, w1out + (size_t)bl * g.H * g.pW + col, g.pW, j, s);
+}
+
 // Radix schedules of the tuned transforms (AsmGeom::row_plan, col_plan):
 //   rows of 3840 (256 threads):     0: 16 16 15   1: 16 15 16   2: 15 16 16
 //   rows of 7680 (512 threads):     0: 16 20 24   1: 16 24 20   2: 24 20 16
-//   columns of 2160 (C = 2):        0: 16 15 9    1: 16 9 15    2: 15 16 9    3: 12 12 15
-//   columns of 4320 (C = 1):        0: 16 15 18   1: 18 15 16   2: 15 18 16   3: 16 18 15   4: 18 16 15
+//   columns of 2160 (C = 2), and
+//   columns of 4320 as two of 2160: 0: 16 15 9    1: 16 9 15    2: 15 16 9    3: 12 12 15
 // (forward stage order).  Every schedule keeps one butterfly per thread in
 // the first and the last stage.
 using Row3840 = RowT<3840, 256, 16, 16, 15>;
@@ -531,11 +700,14 @@ using Row3840 = RowT<3840, 256, 16, 16, 15>;
 bool tuned_rows(const AsmGeom& g) { return g.pW == 3840 || g.pW == 7680; }
 // (band mode 0 with evanescent bins present needs the decaying continuation,
 // which only the generic passes form)
+// (columns of 4320 run as two transforms of 2160, which needs the lower
+// half to be zero padding)
 bool tuned_cols(const AsmGeom& g) {
-  return (g.pH == 2160 || g.pH == 4320) && g.pW % 128 == 0 && !(g.band_mode == 0 && g.evanescent);
+  return (g.pH == 2160 || (g.pH == 4320 && 2 * g.H == g.pH)) && g.pW % 128 == 0 &&
+         !(g.band_mode == 0 && g.evanescent);
 }
 int tuned_row_plans(const AsmGeom&) { return 3; }
-int tuned_col_plans(const AsmGeom& g) { return g.pH == 4320 ? 5 : 4; }
+int tuned_col_plans(const AsmGeom&) { return 4; }
 int tuned_cols_per_block(const AsmGeom& g) { return g.pH == 4320 ? 1 : 2; }
 
 static bool rows_half(const AsmGeom& g) { return 2 * g.W == g.pW; }
@@ -611,15 +783,7 @@ hipError_t launch_rows_adjoint_out_t(const float2* w1, const float2* dL_dfield, 
 // (plan creation checks this).
 template <class F>
 static hipError_t with_col_plan(const AsmGeom& g, int C, F&& f) {
-  if (g.pH == 4320) {   // one column per workgroup (plan creation checks C)
-    switch (g.col_plan) {
-      case 1: f(ColT<1, 18, 15, 16, 4320, 320>{}); break;
-      case 2: f(ColT<1, 15, 18, 16, 4320, 320>{}); break;
-      case 3: f(ColT<1, 16, 18, 15, 4320, 320>{}); break;
-      case 4: f(ColT<1, 18, 16, 15, 4320, 320>{}); break;
-      default: f(ColT<1, 16, 15, 18, 4320, 320>{}); break;
-    }
-  } else if (C == 1) {
+  if (C == 1) {
     f(ColT<1>{});
   } else if (C == 4) {
     f(ColT<4>{});
@@ -634,8 +798,26 @@ static hipError_t with_col_plan(const AsmGeom& g, int C, F&& f) {
   return hipGetLastError();
 }
 
+// Columns of 4320 as two transforms of 2160 (the 2160 schedules, C = 2).
+template <class F>
+static hipError_t with_split_plan(const AsmGeom& g, F&& f) {
+  switch (g.col_plan) {
+    case 1: f(ColT<2, 16, 9, 15>{}); break;
+    case 2: f(ColT<2, 15, 16, 9>{}); break;
+    case 3: f(ColT<2, 12, 12, 15>{}); break;
+    default: f(ColT<2>{}); break;
+  }
+  return hipGetLastError();
+}
+static bool cols_split(const AsmGeom& g) { return g.pH == 4320; }
+
 hipError_t launch_cols_forward_t(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, int C,
                                  hipStream_t s) {
+  if (cols_split(g))
+    return with_split_plan(g, [&](auto ct) {
+      using CT = decltype(ct);
+      k_cols_forward_split<CT><<<(unsigned)(g.n_bl * g.pW), CT::NT, 0, s>>>(x1, y, g, fc);
+    });
   const unsigned grid = (unsigned)(g.n_bl * (g.pW / C));
   return with_col_plan(g, C, [&](auto ct) {
     using CT = decltype(ct);
@@ -647,6 +829,11 @@ hipError_t launch_cols_forward_t(const float2* x1, float2* y, const AsmGeom& g, 
 }
 hipError_t launch_cols_adjoint_t(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, int C,
                                  hipStream_t s) {
+  if (cols_split(g))
+    return with_split_plan(g, [&](auto ct) {
+      using CT = decltype(ct);
+      k_cols_adjoint_split<CT><<<(unsigned)(g.n_bl * g.pW), CT::NT, 0, s>>>(z, w1, g, fc);
+    });
   const unsigned grid = (unsigned)(g.n_bl * (g.pW / C));
   return with_col_plan(g, C, [&](auto ct) {
     using CT = decltype(ct);

@@ -172,6 +172,11 @@ chrf_status make_fft(chrf_ctx* ctx, int n, FftDesc* fd) {
   fd->n = n;
   fd->nstages = fft_plan_radices(n, fd->radix);
   if (fd->nstages == 0 && n != 1) return fail(CHRF_EUNSUPPORTED, "FFT length " + std::to_string(n) + " is not 2^a 3^b 5^c");
+  fd->tw_half = nullptr;
+  if (n % 2 == 0 && n > 2) {
+    const chrf_status st = get_twiddles(ctx, n / 2, &fd->tw_half);
+    if (st != CHRF_OK) return st;
+  }
   return get_twiddles(ctx, n, &fd->tw);
 }
 
@@ -375,7 +380,7 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
     return bad(fail(CHRF_EUNSUPPORTED, "plan: a padded row does not fit the LDS"));
   int C = d.cols_per_block;
   if (tuned_cols(geom(p)) && p->pH == 4320) {
-    // tuned column pass of 4320: one column per workgroup
+    // tuned column pass of 4320 (two transforms of 2160): one column per workgroup
     if (C != 0 && C != 1)
       return bad(fail(CHRF_EUNSUPPORTED, "plan: cols_per_block must be 1 for a padded height of 4320"));
     C = 1;
@@ -404,7 +409,7 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   if (d.fft_cols_plan != 0 && (!tuned_cols(geom(p)) || C != tuned_cols_per_block(geom(p)) || d.fft_cols_plan < 0 ||
                                d.fft_cols_plan >= tuned_col_plans(geom(p))))
     return bad(fail(CHRF_EUNSUPPORTED, "plan: fft_cols_plan must be 0 unless the padded height is 2160 with two "
-                                       "columns per workgroup (then 0..3) or 4320 (then 0..4)"));
+                                       "columns per workgroup, or 4320 (then 0..3)"));
   // transfer-function parameters
   std::vector<HParam> hp(p->L * p->K);
   const double dfx = 1.0 / (p->pW * d.pitch), dfy = 1.0 / (p->pH * d.pitch);

@@ -66,7 +66,8 @@ struct FftDesc {
   int n;
   int nstages;
   int radix[kMaxStages];
-  const cpx* tw;  // exp(-2 pi i m / n), m < n
+  const cpx* tw;       // exp(-2 pi i m / n), m < n
+  const cpx* tw_half;  // exp(-2 pi i m / (n / 2)), m < n / 2 (n even; else null)
 };
 
 // Transfer-function parameters of one (wavelength, distance) pair.
