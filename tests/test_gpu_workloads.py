@@ -4,8 +4,9 @@ At these sizes the oracle cannot render whole frames in test time, so the
 checks are
 * the rendered field on sampled windows of every view against the FP64 oracle
   restricted to those windows (relative L2 <= 1e-4);
-* the tile lists of sampled tiles against the oracle's single-precision
-  binning (bit-exact);
+* the tile lists against the oracle's single-precision binning, bit for bit:
+  every tile of the 1080p frame and of two views of the 16-view ring, and
+  sampled tiles of the 2160p views;
 * the fused loss against the intensities the same call returned;
 * the gradient against a central difference of the loss along the gradient
   direction with the means held fixed (a property that holds at any size).
@@ -78,6 +79,40 @@ def _tile_checks(w, r):
             assert np.array_equal(got, ref), (b, t)
 
 
+def _full_list_check(w, r, views):
+    """Every (view, tile) run of the listed views, and its range, against the
+    oracle's binning of that view (bit-exact; pairs are selected on the
+    device, so only one view's list is copied back)."""
+    sc = w.scene
+    thr = oracle.DEFAULT
+    H, W = w.cameras[0].height, w.cameras[0].width
+    tx, ty = (W + 15) // 16, (H + 15) // 16
+    T = tx * ty
+    b = int(T - 1).bit_length()
+    n = r.read_status()[1]
+    keys = r.region(_lib.REGION_PAIR_KEYS, torch.int32)[:n]
+    vals = r.region(_lib.REGION_PAIR_VALUES, torch.int32)[:n]
+    ranges = r.region(_lib.REGION_TILE_RANGES, torch.int32).view(-1, 2)
+    for v in views:
+        fp = binning.fp32_footprint(sc.means, sc.log_scales, sc.quats, w.cameras[v], 16, 16, thr.k_sigma,
+                                    sc.opacity, thr.alpha_min)
+        ref = binning.bin_pairs([fp], W, H)
+        sel = torch.nonzero((keys >> b) == v).squeeze(1)
+        tiles, order = torch.sort(keys[sel] & ((1 << b) - 1), stable=True)
+        gauss = (vals[sel][order] - v * sc.n).cpu().numpy()
+        assert np.array_equal(tiles.cpu().numpy(), ref["tile_key"].astype(np.int64)), v
+        assert np.array_equal(gauss, ref["gauss"].astype(np.int64)), v
+        # the ranges delimit each run inside the whole list
+        rg = ranges[v * T:(v + 1) * T].cpu().numpy().view(np.uint32).astype(np.int64)
+        ref_len = ref["ranges"][:, 1] - ref["ranges"][:, 0]
+        assert np.array_equal(np.where(ref_len > 0, rg[:, 1] - rg[:, 0], 0), ref_len), v
+        live = np.nonzero(ref_len)[0]
+        idx = np.repeat(rg[live, 0] - np.cumsum(ref_len[live]) + ref_len[live], ref_len[live]) + np.arange(
+            int(ref_len.sum()))
+        run_vals = vals[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.int64) - v * sc.n
+        assert np.array_equal(run_vals, ref["gauss"].astype(np.int64)), v
+
+
 def _directional_check(r, params, cam_t, target, loss0, grads):
     gnorm2 = sum(float((grads[k].double() ** 2).sum()) for k in api.PARAM_NAMES)
     d = {k: grads[k] / np.sqrt(gnorm2) for k in api.PARAM_NAMES}
@@ -105,7 +140,7 @@ def test_forward_backward_1080p_100k():
     ref_loss = float(((I - target.double()) ** 2).mean())
     assert abs(float(out["loss"]) - ref_loss) < 1e-5 * ref_loss
     _window_checks(w, out["field"], r)
-    _tile_checks(w, r)
+    _full_list_check(w, r, [0])
     for k in api.PARAM_NAMES:
         assert torch.isfinite(grads[k]).all(), k
 
@@ -142,14 +177,15 @@ def test_batched_16_views_ring_500k():
     assert len(set(counts)) > 1      # uneven post-culling counts per view
     _window_checks(w, out["field"], r)
     _tile_checks(w, r)
+    _full_list_check(w, r, [0, 9])
     for k in api.PARAM_NAMES:
         assert torch.isfinite(grads[k]).all(), k
 
 
 def test_four_views_2160p_2m_16_planes():
     """The largest configuration: 2,000,000 Gaussians, four yawed views of
-    2160 x 3840, pitch 4 um, 16 planes (padded 4320 x 7680, the mixed-radix
-    generic transforms)."""
+    2160 x 3840, pitch 4 um, 16 planes (padded 4320 x 7680: rows of 7680,
+    columns of 4320 as two transforms of 2160)."""
     w = make_workload("c5")
     announce("workload 4 views 2160p 2m 16 planes")
     r, params, cam_t = _renderer(w, cap_factor=1.05)
