@@ -165,7 +165,7 @@ typedef struct chrf_grads {
  *                      padded height is 2160 and cols_per_block is 2 (0:
  *                      16*15*9, 1: 16*9*15, 2: 15*16*9, 3: 12*12*15, in
  *                      forward stage order), or 4320 with height = 2160
- *                      (cols_per_block 0 or 1; each column runs as two
+ *                      (cols_per_block 0, 1 or 2; each column runs as two
  *                      transforms of 2160 with the same four schedules);
  *                      must be 0 otherwise.  Schedules change
  *                      rounding only (CHRF_EUNSUPPORTED for a value out of

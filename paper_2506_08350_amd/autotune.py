@@ -24,7 +24,7 @@ from . import api
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "chrf_autotune.json")
 
 TILES = ((16, 16), (16, 8), (8, 16), (32, 8), (8, 8))
-COLS = (0, 4, 1)            # 0: the library's choice for the padded height (2 at 2160, 1 at 4320)
+COLS = (0, 4, 1)            # 0: the library's choice for the padded height (2 at 2160 and at 4320)
 ROW_PLANS = (0, 1, 2)       # 3840: 16*16*15, 16*15*16, 15*16*16; 7680: 16*20*24, 16*24*20, 24*20*16
 COL_PLANS = (0, 1, 2, 3)    # 2160 (and 4320 as two of 2160): 16*15*9, 16*9*15, 15*16*9, 12*12*15
 

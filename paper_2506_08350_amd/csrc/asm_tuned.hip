@@ -519,30 +519,30 @@ __global__ __launch_bounds__(CT::NT, CT::kMinWaves) void k_cols_adjoint_t(const 
 // are the NH-point transform of x[n] and its odd bins 2m + 1 that of
 // x[n] w^n; after the transfer function, the kept rows n < NH of the inverse
 // are a[n] + w^-n b[n], a and b the (unnormalised) NH-point inverse
-// transforms of the even and of the odd bins.  The two halves run as the two
-// interleaved sequences of a C = 2 transform of NH (s = 0: even bins, s = 1:
-// odd bins), so one column takes the layout, schedules and occupancy of the
-// tuned NH transforms; the lanes (s = 0, 1) of each butterfly index j hold
-// a and b at the same rows and exchange them to combine.  w^n, n < NH, is
-// staged in LDS once per workgroup.
-constexpr int kSplitSpan = 16;   // one 8-byte column per workgroup: 16 share a 128-byte line
-
+// transforms of the even and of the odd bins.  A workgroup takes P adjacent
+// columns, whose 2P halves run as the interleaved sequences of a C = 2P
+// transform of NH (sequence s: column s / 2, h = s mod 2: 0 even bins, 1 odd
+// bins), so the columns take the layout, schedules and occupancy of the
+// tuned NH transforms; the lanes (h = 0, 1) of each column and butterfly
+// index j hold a and b at the same rows and exchange them to combine.  w^n,
+// n < NH, is staged in LDS once per workgroup.
 template <class CT>
 __device__ inline void stage_split_twiddles(cpx* s_w, const cpx* __restrict__ tw) {
   for (int i = threadIdx.x; i < CT::N; i += CT::NT) s_w[i] = tw[i];
 }
 
-// Rows n = j + q S1 of a (s = 0) and b (s = 1) in w3: lane s stores the rows
-// with q = s mod 2, out[n] = a[n] + conj(w^n) b[n] (column pointer col).
+// Rows n = j + q S1 of a (h = 0) and b (h = 1) in w3: the lane of half h
+// stores the rows with q = h mod 2, out[n] = a[n] + conj(w^n) b[n] (column
+// pointer col).
 template <class CT>
-__device__ inline void store_split(cpx (&w3)[1][CT::R1], const cpx* s_w, float2* col, int pW, int j, int s) {
+__device__ inline void store_split(cpx (&w3)[1][CT::R1], const cpx* s_w, float2* col, int pW, int j, int h) {
 #pragma unroll
   for (int q = 0; q < CT::R1; ++q) {
     const cpx mine = w3[0][q];
     const cpx other{__shfl_xor(mine.x, 1, 64), __shfl_xor(mine.y, 1, 64)};
-    if ((q & 1) == s) {
+    if ((q & 1) == h) {
       const int n = j + q * CT::S1;
-      const cpx a = s ? other : mine, b = s ? mine : other;
+      const cpx a = h ? other : mine, b = h ? mine : other;
       stc(col + (size_t)n * pW, a + cmulc(b, s_w[n]));
     }
   }
@@ -551,16 +551,18 @@ __device__ inline void store_split(cpx (&w3)[1][CT::R1], const cpx* s_w, float2*
 template <class CT>
 __global__ __launch_bounds__(CT::NT, 4) void k_cols_forward_split(const float2* __restrict__ x1,
                                                                   float2* __restrict__ y, AsmGeom g, FftDesc fc) {
-  static_assert(CT::C == 2 && CT::kRegSpec, "two half-length sequences, spectrum in registers");
-  constexpr int R1 = CT::R1, R3 = CT::R3;
+  constexpr int C = CT::C, P = C / 2, R1 = CT::R1, R3 = CT::R3;
+  static_assert(C == 2 || C == 4, "one or two columns of two halves");
   __shared__ cpx lds[CT::kLdsElems];
   __shared__ cpx s_w[CT::N];
   __shared__ float s_q[R3][CT::NT];   // plane-independent transfer terms (each thread reads its own)
-  const int gid = col_remap(blockIdx.x, gridDim.x, kSplitSpan);
-  const int bl = gid / g.pW, col = gid % g.pW;
-  const int lam = bl % g.n_lambda;
+  const int ngroups = g.pW / P;
+  const int gid = col_remap(blockIdx.x, gridDim.x, 16 / P);
+  const int bl = gid / ngroups;
   const int b = threadIdx.x;
-  const int s = b & 1, j = b >> 1;
+  const int s = b % C, h = s & 1, j = b / C;
+  const int col = (gid % ngroups) * P + (s >> 1);
+  const int lam = bl % g.n_lambda;
   stage_split_twiddles<CT>(s_w, fc.tw);
   __syncthreads();
   cpx sreg[R3];
@@ -571,14 +573,14 @@ __global__ __launch_bounds__(CT::NT, 4) void k_cols_forward_split(const float2* 
       for (int r = 0; r < R1; ++r) {
         const int n = j + r * CT::S1;
         const cpx x = ldc(x1 + ((size_t)bl * g.H + n) * g.pW + col);
-        v1[0][r] = s ? cmul(x, s_w[n]) : x;
+        v1[0][r] = h ? cmul(x, s_w[n]) : x;
       }
     }
     if (b < CT::Inv::B1) {
       const HParam hp0 = load_hparam(g.hp, lam * g.K);
       const ColFreq cf = col_freq(hp0, col, g);
 #pragma unroll
-      for (int q = 0; q < R3; ++q) s_q[q][b] = transfer_q(hp0, cf, 2 * (j + q * CT::S3) + s, g);
+      for (int q = 0; q < R3; ++q) s_q[q][b] = transfer_q(hp0, cf, 2 * (j + q * CT::S3) + h, g);
     }
     CT::Fwd::template run<false>(v1, v3, lds, fc.tw_half);
     if (b < CT::Fwd::B3) {
@@ -599,43 +601,53 @@ __global__ __launch_bounds__(CT::NT, 4) void k_cols_forward_split(const float2* 
         const bool col_pass = g.band_mode < 2 || abs(sbin(kx, g.pW)) <= hp.kx_max;
 #pragma unroll
         for (int q = 0; q < R3; ++q)
-          w1[0][q] = cmul(sreg[q], transfer_from_q(hp, col_pass, s_q[q][b], 2 * (jj + q * CT::S3) + s, g));
+          w1[0][q] = cmul(sreg[q], transfer_from_q(hp, col_pass, s_q[q][b], 2 * (jj + q * CT::S3) + h, g));
       }
     }
     CT::Inv::run_with_twiddles(w1, w3, lds, itw, opaque_v(b));
     if (b < CT::Inv::B3)
-      store_split<CT>(w3, s_w, y + ((size_t)bl * g.K + k) * g.H * g.pW + kx, g.pW, jj, s);
+      store_split<CT>(w3, s_w, y + ((size_t)bl * g.K + k) * g.H * g.pW + kx, g.pW, jj, h);
   }
 }
 
 // The adjoint reads K input columns, one per plane: plane k + 1 is copied
-// from HBM straight into an LDS buffer (global_load_lds, 4 bytes per lane,
-// so a wave moves 32 rows of the column) while plane k's transform runs.
-// The transfer terms are formed per plane (the LDS holds the copy instead).
+// from HBM straight into an LDS buffer (global_load_lds: a lane moves 4
+// bytes of one column, or one row of both columns) while plane k's transform
+// runs.  The transfer terms are formed per plane (the LDS holds the copy
+// instead).
 template <class CT>
 __global__ __launch_bounds__(CT::NT, 4) void k_cols_adjoint_split(const float2* __restrict__ z,
                                                                   float2* __restrict__ w1out, AsmGeom g,
                                                                   FftDesc fc) {
-  static_assert(CT::C == 2, "two half-length sequences");
-  constexpr int R1 = CT::R1, R3 = CT::R3;
-  constexpr int kFloats = 2 * CT::N;   // one plane of the column
+  constexpr int C = CT::C, P = C / 2, R1 = CT::R1, R3 = CT::R3;
+  static_assert(C == 2 || C == 4, "one or two columns of two halves");
+  constexpr int kLaneBytes = P == 1 ? 4 : 16;
+  constexpr int kUnits = CT::N * P * 8 / kLaneBytes;   // copy units of one plane
   __shared__ cpx lds[CT::kLdsElems];
-  __shared__ float s_in[kFloats];
+  __shared__ float s_in[CT::N * P * 2];   // [row][column] of one plane
   __shared__ cpx s_w[CT::N];
-  const int gid = col_remap(blockIdx.x, gridDim.x, kSplitSpan);
-  const int bl = gid / g.pW, col = gid % g.pW;
-  const int lam = bl % g.n_lambda;
+  const int ngroups = g.pW / P;
+  const int gid = col_remap(blockIdx.x, gridDim.x, 16 / P);
+  const int bl = gid / ngroups;
+  const int c0 = (gid % ngroups) * P;
   const int b = threadIdx.x;
-  const int s = b & 1, j = b >> 1;
-  // wave w copies floats 64 i .. 64 i + 63 of the plane for i = w, w + NT / 64, ...
+  const int s = b % C, h = s & 1, j = b / C;
+  const int col = c0 + (s >> 1);
+  const int lam = bl % g.n_lambda;
+  // wave w copies units 64 i .. 64 i + 63 of the plane for i = w, w + NT / 64, ...
   auto copy_plane = [&](int k) {
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const float* zk = reinterpret_cast<const float*>(z + ((size_t)bl * g.K + k) * g.H * g.pW + col);
-    for (int i = w; i * 64 < kFloats; i += CT::NT / 64) {
+    const float* zk = reinterpret_cast<const float*>(z + ((size_t)bl * g.K + k) * g.H * g.pW + c0);
+    for (int i = w; i * 64 < kUnits; i += CT::NT / 64) {
       const int e = i * 64 + lane;
-      if (e < kFloats)
-        __builtin_amdgcn_global_load_lds((const gmem_void*)(zk + (size_t)(e >> 1) * 2 * g.pW + (e & 1)),
-                                         (lds_void*)&s_in[i * 64], 4, 0, 0);
+      if (e < kUnits) {
+        if constexpr (P == 1)   // float e of the column (row e / 2)
+          __builtin_amdgcn_global_load_lds((const gmem_void*)(zk + (size_t)(e >> 1) * 2 * g.pW + (e & 1)),
+                                           (lds_void*)&s_in[i * 64], 4, 0, 0);
+        else   // row e, both columns
+          __builtin_amdgcn_global_load_lds((const gmem_void*)(zk + (size_t)e * 2 * g.pW), (lds_void*)&s_in[i * 64 * 4],
+                                           16, 0, 0);
+      }
     }
   };
   auto copies_visible = [] {
@@ -656,8 +668,9 @@ __global__ __launch_bounds__(CT::NT, 4) void k_cols_adjoint_split(const float2* 
 #pragma unroll
       for (int r = 0; r < R1; ++r) {
         const int n = jj + r * CT::S1;
-        const cpx x{s_in[2 * n], s_in[2 * n + 1]};
-        v1[0][r] = s ? cmul(x, s_w[n]) : x;
+        const int e = 2 * (n * P + (s >> 1));
+        const cpx x{s_in[e], s_in[e + 1]};
+        v1[0][r] = h ? cmul(x, s_w[n]) : x;
       }
     }
     // stage 1 has read its inputs once the hook runs: the buffer is free
@@ -670,11 +683,11 @@ __global__ __launch_bounds__(CT::NT, 4) void k_cols_adjoint_split(const float2* 
       if (g.mask_free) {   // uniform
 #pragma unroll
         for (int q = 0; q < R3; ++q)
-          acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_free(hp, transfer_q(hp, cf, 2 * (jj + q * CT::S3) + s, g)));
+          acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_free(hp, transfer_q(hp, cf, 2 * (jj + q * CT::S3) + h, g)));
       } else {
 #pragma unroll
         for (int q = 0; q < R3; ++q) {
-          const int ky = 2 * (jj + q * CT::S3) + s;
+          const int ky = 2 * (jj + q * CT::S3) + h;
           acc[0][q] = acc[0][q] + cmulc(v3[0][q], transfer_from_q(hp, cf.pass, transfer_q(hp, cf, ky, g), ky, g));
         }
       }
@@ -685,7 +698,7 @@ __global__ __launch_bounds__(CT::NT, 4) void k_cols_adjoint_split(const float2* 
   for (int q = 0; q < R3; ++q) acc[0][q] = acc[0][q] * g.norm;
   cpx w3[1][R1];
   CT::Inv::template run<false>(acc, w3, lds, fc.tw_half);
-  if (b < CT::Inv::B3) store_split<CT>(w3, s_w, w1out + (size_t)bl * g.H * g.pW + col, g.pW, j, s);
+  if (b < CT::Inv::B3) store_split<CT>(w3, s_w, w1out + (size_t)bl * g.H * g.pW + col, g.pW, j, h);
 }
 
 // Radix schedules of the tuned transforms (AsmGeom::row_plan, col_plan):
@@ -708,7 +721,7 @@ bool tuned_cols(const AsmGeom& g) {
 }
 int tuned_row_plans(const AsmGeom&) { return 3; }
 int tuned_col_plans(const AsmGeom&) { return 4; }
-int tuned_cols_per_block(const AsmGeom& g) { return g.pH == 4320 ? 1 : 2; }
+bool tuned_col_plan_fits(const AsmGeom& g, int C) { return g.pH == 4320 ? (C == 1 || C == 2) : C == 2; }
 
 static bool rows_half(const AsmGeom& g) { return 2 * g.W == g.pW; }
 static bool cols_half(const AsmGeom& g) { return 2 * g.H == g.pH; }
@@ -798,15 +811,23 @@ static hipError_t with_col_plan(const AsmGeom& g, int C, F&& f) {
   return hipGetLastError();
 }
 
-// Columns of 4320 as two transforms of 2160 (the 2160 schedules, C = 2).
-template <class F>
-static hipError_t with_split_plan(const AsmGeom& g, F&& f) {
+// Columns of 4320 as two transforms of 2160 (the 2160 schedules), one (C =
+// 2) or two (C = 4) columns per workgroup.
+template <int C, class F>
+static void split_plans(const AsmGeom& g, F&& f) {
   switch (g.col_plan) {
-    case 1: f(ColT<2, 16, 9, 15>{}); break;
-    case 2: f(ColT<2, 15, 16, 9>{}); break;
-    case 3: f(ColT<2, 12, 12, 15>{}); break;
-    default: f(ColT<2>{}); break;
+    case 1: f(ColT<C, 16, 9, 15>{}); break;
+    case 2: f(ColT<C, 15, 16, 9>{}); break;
+    case 3: f(ColT<C, 12, 12, 15>{}); break;
+    default: f(ColT<C>{}); break;
   }
+}
+template <class F>
+static hipError_t with_split_plan(const AsmGeom& g, int P, F&& f) {
+  if (P == 2)
+    split_plans<4>(g, f);
+  else
+    split_plans<2>(g, f);
   return hipGetLastError();
 }
 static bool cols_split(const AsmGeom& g) { return g.pH == 4320; }
@@ -814,9 +835,9 @@ static bool cols_split(const AsmGeom& g) { return g.pH == 4320; }
 hipError_t launch_cols_forward_t(const float2* x1, float2* y, const AsmGeom& g, const FftDesc& fc, int C,
                                  hipStream_t s) {
   if (cols_split(g))
-    return with_split_plan(g, [&](auto ct) {
+    return with_split_plan(g, C, [&](auto ct) {
       using CT = decltype(ct);
-      k_cols_forward_split<CT><<<(unsigned)(g.n_bl * g.pW), CT::NT, 0, s>>>(x1, y, g, fc);
+      k_cols_forward_split<CT><<<(unsigned)(g.n_bl * (g.pW / (CT::C / 2))), CT::NT, 0, s>>>(x1, y, g, fc);
     });
   const unsigned grid = (unsigned)(g.n_bl * (g.pW / C));
   return with_col_plan(g, C, [&](auto ct) {
@@ -830,9 +851,9 @@ hipError_t launch_cols_forward_t(const float2* x1, float2* y, const AsmGeom& g, 
 hipError_t launch_cols_adjoint_t(const float2* z, float2* w1, const AsmGeom& g, const FftDesc& fc, int C,
                                  hipStream_t s) {
   if (cols_split(g))
-    return with_split_plan(g, [&](auto ct) {
+    return with_split_plan(g, C, [&](auto ct) {
       using CT = decltype(ct);
-      k_cols_adjoint_split<CT><<<(unsigned)(g.n_bl * g.pW), CT::NT, 0, s>>>(z, w1, g, fc);
+      k_cols_adjoint_split<CT><<<(unsigned)(g.n_bl * (g.pW / (CT::C / 2))), CT::NT, 0, s>>>(z, w1, g, fc);
     });
   const unsigned grid = (unsigned)(g.n_bl * (g.pW / C));
   return with_col_plan(g, C, [&](auto ct) {

@@ -380,10 +380,10 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
     return bad(fail(CHRF_EUNSUPPORTED, "plan: a padded row does not fit the LDS"));
   int C = d.cols_per_block;
   if (tuned_cols(geom(p)) && p->pH == 4320) {
-    // tuned column pass of 4320 (two transforms of 2160): one column per workgroup
-    if (C != 0 && C != 1)
-      return bad(fail(CHRF_EUNSUPPORTED, "plan: cols_per_block must be 1 for a padded height of 4320"));
-    C = 1;
+    // tuned column pass of 4320 (two transforms of 2160): one or two columns per workgroup
+    if (C != 0 && C != 1 && C != 2)
+      return bad(fail(CHRF_EUNSUPPORTED, "plan: cols_per_block must be 1 or 2 for a padded height of 4320"));
+    if (C == 0) C = 2;
   } else if (tuned_cols(geom(p))) {
     // tuned column pass: 2 columns x 512 threads (default), 1 x 256 or 4 x 1024
     if (C != 0 && C != 1 && C != 2 && C != 4)
@@ -406,7 +406,7 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
                                d.fft_rows_plan >= tuned_row_plans(geom(p))))
     return bad(fail(CHRF_EUNSUPPORTED, "plan: fft_rows_plan must be 0 unless the padded width is 3840 or 7680 (then "
                                        "0.." + std::to_string(tuned_row_plans(geom(p)) - 1) + ")"));
-  if (d.fft_cols_plan != 0 && (!tuned_cols(geom(p)) || C != tuned_cols_per_block(geom(p)) || d.fft_cols_plan < 0 ||
+  if (d.fft_cols_plan != 0 && (!tuned_cols(geom(p)) || !tuned_col_plan_fits(geom(p), C) || d.fft_cols_plan < 0 ||
                                d.fft_cols_plan >= tuned_col_plans(geom(p))))
     return bad(fail(CHRF_EUNSUPPORTED, "plan: fft_cols_plan must be 0 unless the padded height is 2160 with two "
                                        "columns per workgroup, or 4320 (then 0..3)"));

@@ -228,7 +228,7 @@ bool tuned_rows(const AsmGeom& g);
 bool tuned_cols(const AsmGeom& g);
 int tuned_row_plans(const AsmGeom& g);        // radix schedules of the tuned row transforms
 int tuned_col_plans(const AsmGeom& g);        // radix schedules of the tuned column transforms
-int tuned_cols_per_block(const AsmGeom& g);   // the columns per workgroup those schedules take
+bool tuned_col_plan_fits(const AsmGeom& g, int C);   // those schedules exist for C columns per workgroup
 hipError_t launch_rows_forward_t(const float2* in, float2* out, const AsmGeom& g, const FftDesc& fr, hipStream_t s);
 hipError_t launch_rows_inverse_t(float2* y, const AsmGeom& g, const FftDesc& fr, float2* prop_out, float* intensity,
                                  const float* target, float* loss_partial, float grad_coef, bool fuse, hipStream_t s);

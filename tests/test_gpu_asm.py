@@ -234,17 +234,19 @@ def field_2160p():
     return U, G, prop_ref, adj_ref
 
 
-@pytest.mark.parametrize("plans", [(0, 0), (1, 0), (2, 0), (0, 1), (0, 2), (0, 3)])
-def test_radix_schedules_at_2160p(field_2160p, plans):
+@pytest.mark.parametrize("plans,cols", [((0, 0), 2), ((1, 0), 2), ((2, 0), 2), ((0, 1), 2), ((0, 2), 2), ((0, 3), 2),
+                                        ((0, 0), 1), ((0, 3), 1)])
+def test_radix_schedules_at_2160p(field_2160p, plans, cols):
     """The tuned transforms of the 2160 x 3840 geometry (rows of 7680 with
     512 threads; columns of 4320 as two transforms of 2160, even and odd
-    bins, combined with w^-n), every radix schedule: one propagated plane
-    and the adjoint summed over two planes against the oracle."""
-    announce(f"radix schedules {plans} at 2160x3840")
+    bins, combined with w^-n, one or two columns per workgroup), every radix
+    schedule: one propagated plane and the adjoint summed over two planes
+    against the oracle."""
+    announce(f"radix schedules {plans}, {cols} columns per workgroup at 2160x3840")
     U, G, prop_ref, adj_ref = field_2160p
     H, W = U.shape[2:]
     opt = Optics(_LAMS_2160P, _ZS_2160P, 8e-6, 2, 2)
-    r = make_renderer([identity_camera(W, H)], opt, 1, fft_plans=plans)
+    r = make_renderer([identity_camera(W, H)], opt, 1, fft_plans=plans, cols_per_block=cols)
     prop, _ = r.propagate(_to_gpu(U), want_intensity=False)
     torch.cuda.synchronize()
     assert rel_l2(cplx(prop[0, 0, 1]), prop_ref) < TOL
