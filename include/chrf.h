@@ -194,9 +194,11 @@ typedef struct chrf_plan_desc {
 
 /* Named regions of the workspace, for inspection by tests and tools. */
 typedef enum chrf_region {
-  CHRF_REGION_PAIR_KEYS = 0,   /* uint32 [max_pairs]: view << b | tile, b = bits of n_tiles - 1, sorted by
-                                  the low 8 ceil(b / 8) bits; each (view, tile) run is contiguous and front
-                                  to back (runs sharing those bits follow in view order) */
+  CHRF_REGION_PAIR_KEYS = 0,   /* uint32 [max_pairs]: view << b | tile, b = bits of n_tiles - 1, stably
+                                  sorted by the b tile bits (or by the low 8 ceil(b / 8) bits when the
+                                  capacity takes single-sweep passes); each (view, tile) run is
+                                  contiguous and front to back (runs sharing the sorted bits follow in
+                                  view order) */
   CHRF_REGION_PAIR_VALUES = 1, /* uint32 [max_pairs]: view * max_gaussians + gaussian */
   CHRF_REGION_TILE_RANGES = 2, /* uint32 [n_views * n_tiles][2]: [start, end) of (view, tile) view * n_tiles + tile */
   CHRF_REGION_STATUS = 3,      /* uint64 [0] pairs needed, uint32 [2] overflow flag */

@@ -179,7 +179,7 @@ __device__ inline int64_t live_count(int64_t n_max, const uint64_t* n_dev) {
 // Digit histogram of one pass per block: hist[digit * nblocks + block].
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* __restrict__ keys, int64_t n_max,
-                                                             const uint64_t* n_dev, int shift,
+                                                             const uint64_t* n_dev, int shift, uint32_t mask,
                                                              uint32_t* __restrict__ hist, int nblocks) {
   __shared__ uint32_t cnt[256];
   cnt[threadIdx.x] = 0;
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* __restrict
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
       if (t0 + i >= n) break;
-      const uint32_t d = (uint32_t)(k[i] >> shift) & 255u;
+      const uint32_t d = (uint32_t)(k[i] >> shift) & mask;
       if (run_c != 0 && d != run_d) {
         atomicAdd(&cnt[run_d], run_c);
         run_c = 0;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* __restrict
     if (run_c != 0) atomicAdd(&cnt[run_d], run_c);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
 // Stable scatter of one pass.  Each wave ranks a contiguous quarter of the
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
                                                                 const uint32_t* __restrict__ vals_in,
                                                                 K* __restrict__ keys_out,
                                                                 uint32_t* __restrict__ vals_out, int64_t n_max,
-                                                                const uint64_t* n_dev, int shift,
+                                                                const uint64_t* n_dev, int shift, uint32_t mask,
                                                                 const uint32_t* __restrict__ offsets, int nblocks) {
   constexpr int NW = kSortThreads / 64;
   constexpr int kWaveKeys = kSortItems * 64;   // keys ranked by one wave
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
   if (base >= n) return;   // uniform per block
 #pragma unroll
   for (int i = lane; i < 256; i += 64) wcnt[wave][i] = 0;   // read back only by this wave until the barrier
-  goff[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+  goff[tid] = tid <= (int)mask ? offsets[(int64_t)tid * nblocks + blockIdx.x] : 0u;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   K key[kSortItems];
   uint32_t val[kSortItems], dig[kSortItems], rank[kSortItems];
@@ -273,12 +273,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
     if (valid) {
       key[r] = keys_in[idx];
       val[r] = vals_in[idx];
-      dig[r] = (uint32_t)(key[r] >> shift) & 255u;
+      dig[r] = (uint32_t)(key[r] >> shift) & mask;
     }
     const uint32_t d = dig[r];
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
+      if ((mask >> bit) == 0u) break;   // uniform: no digit has this bit
       const bool on = (d >> bit) & 1u;
       const uint64_t m = __ballot(on);
       peers &= on ? m : ~m;
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* __restr
   const int nv = (int)(n - base < kSortTile ? n - base : kSortTile);
   for (int i = tid; i < nv; i += kSortThreads) {
     const K k = skey[i];
-    const uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const uint32_t d = (uint32_t)(k >> shift) & mask;
     const uint32_t pos = goff[d] + (uint32_t)i - lstart[d];
     if (pos < (uint64_t)n) {   // always true for consistent offsets; keeps every write in bounds
       keys_out[pos] = k;
@@ -539,20 +540,27 @@ static hipError_t radix_sort_impl(K* keys, K* keys_alt, uint32_t* vals, uint32_t
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  // The three-kernel passes split the key bits evenly (13 bits: 7 + 6), so
+  // that each block's keys of one digit leave it in longer runs; single
+  // sweeps take 8-bit digits.
+  int shift = begin_bit;
   for (int pass = 0; pass < npasses; ++pass) {
-    const int shift = begin_bit + 8 * pass;
+    const int bits = end_bit - begin_bit;
+    const int width = sweep ? 8 : bits / npasses + (pass < bits % npasses ? 1 : 0);
+    const uint32_t mask = (1u << width) - 1u;
     if (sweep) {
       k_onesweep<K, kSweepItems><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n_max, n_dev, shift,
                                                                   counts + pass * 256,
                                                                   status + (size_t)pass * 256 * nblocks,
                                                                   tickets + pass, error);
     } else {
-      k_radix_hist<K><<<nblocks, kSortThreads, 0, s>>>(kin, n_max, n_dev, shift, hist, nblocks);
-      e = launch_scan_u32(hist, hist, (int64_t)256 * nblocks, scan_tmp, s);
+      k_radix_hist<K><<<nblocks, kSortThreads, 0, s>>>(kin, n_max, n_dev, shift, mask, hist, nblocks);
+      e = launch_scan_u32(hist, hist, (int64_t)(mask + 1) * nblocks, scan_tmp, s);
       if (e != hipSuccess) return e;
-      k_radix_scatter<K><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n_max, n_dev, shift, hist,
+      k_radix_scatter<K><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n_max, n_dev, shift, mask, hist,
                                                           nblocks);
     }
+    shift += width;
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     K* tk = kin; kin = kout; kout = tk;
@@ -729,9 +737,9 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
   const SpanGeom g = span_geom(rec_g0[rid], rec_g1[rid], rect[rid]);
   // key = view << tile_bits | tile.  The list arrives view-major (the
   // Gaussians are sorted by (view, depth)), so a stable sort by the low
-  // 8 * ceil(tile_bits / 8) bits keeps each (view, tile) run contiguous and
-  // in depth order: runs that share those bits belong to different views
-  // and stay in view order.
+  // tile_bits bits (or by any more low bits) keeps each (view, tile) run
+  // contiguous and in depth order: runs that share those bits belong to
+  // different views and stay in view order.
   const uint32_t vkey = (rid / (uint32_t)n_stride) << tile_bits;
   const int ty0 = g.r0 / tile_h, ty1 = g.r1 / tile_h;
   for (int base = ty0; base <= ty1; base += kEmitTeam) {
