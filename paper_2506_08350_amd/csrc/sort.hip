@@ -667,13 +667,16 @@ __device__ inline int row_span(const SpanGeom& s, int ty, int tile_w, int tile_h
   return lo <= hi ? hi / tile_w - lo / tile_w + 1 : 0;
 }
 
-// A team of kEmitTeam consecutive lanes per sorted (view, Gaussian) entry i;
-// lane r takes the tile rows r, r + kEmitTeam, ... of its rectangle.
+// A team of consecutive lanes per sorted (view, Gaussian) entry i; lane r
+// takes the tile rows r, r + team, ... of its rectangle.  Counting, which
+// only sums, takes teams of 8; emission, which writes the rows' tiles, 16.
+constexpr int kCountTeam = 8;
 constexpr int kEmitTeam = 16;
 
+template <int TEAM>
 __device__ inline int team_sum(int v) {
 #pragma unroll
-  for (int m = kEmitTeam / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kEmitTeam);
+  for (int m = TEAM / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, TEAM);
   return v;
 }
 
@@ -683,20 +686,20 @@ __global__ __launch_bounds__(256) void k_count_pairs(const uint32_t* __restrict_
                                                      const float4* __restrict__ rec_g1,
                                                      const int4* __restrict__ rect, int64_t n, int tile_w, int tile_h,
                                                      uint32_t* __restrict__ cnt_sorted) {
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kEmitTeam;
-  const int lane = threadIdx.x % kEmitTeam;
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kCountTeam;
+  const int lane = threadIdx.x % kCountTeam;
   const bool live = i < n;
   const uint32_t rid = live ? sorted_val[i] : 0u;
   int kept = 0;
   if (live && count[rid] > 0) {          // visible, with a non-empty rectangle
     const SpanGeom g = span_geom(rec_g0[rid], rec_g1[rid], rect[rid]);
     const int ty1 = g.r1 / tile_h;
-    for (int ty = g.r0 / tile_h + lane; ty <= ty1; ty += kEmitTeam) {
+    for (int ty = g.r0 / tile_h + lane; ty <= ty1; ty += kCountTeam) {
       int lo, hi;
       kept += row_span(g, ty, tile_w, tile_h, &lo, &hi);
     }
   }
-  kept = team_sum(kept);
+  kept = team_sum<kCountTeam>(kept);
   if (live && lane == 0) cnt_sorted[i] = (uint32_t)kept;
 }
 
@@ -704,7 +707,7 @@ hipError_t launch_count_pairs(const uint32_t* sorted_val, const uint32_t* count,
                               const float4* rec_g1, const int4* rect, int64_t n, int tile_w, int tile_h,
                               uint32_t* cnt_sorted, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const int64_t threads = n * kEmitTeam;
+  const int64_t threads = n * kCountTeam;
   k_count_pairs<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(sorted_val, count, rec_g0, rec_g1, rect, n, tile_w,
                                                                    tile_h, cnt_sorted);
   return hipGetLastError();
