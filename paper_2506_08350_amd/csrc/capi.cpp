@@ -375,6 +375,41 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
   if (st != CHRF_OK) return bad(st);
   st = make_fft(ctx, p->pH, &p->fcol);
   if (st != CHRF_OK) return bad(st);
+  // transfer-function parameters (before the column-pass choice, which
+  // depends on whether any bin is evanescent)
+  std::vector<HParam> hp(p->L * p->K);
+  const double dfx = 1.0 / (p->pW * d.pitch), dfy = 1.0 / (p->pH * d.pitch);
+  bool sampling_cut = false;   // some plane's sampling band limit removes a bin
+  for (int l = 0; l < p->L; ++l)
+    for (int k = 0; k < p->K; ++k) {
+      // a layered plan propagates the hologram back to its layers (-Z_k);
+      // the recording (+Z_l) is the adjoint of that map
+      const double lam = d.wavelengths[l], z = p->layered ? -d.distances[k] : d.distances[k];
+      HParam& h = hp[l * p->K + k];
+      const double zl = z / lam;
+      h.frac_rev = (float)(zl - std::floor(zl));
+      h.z = (float)z;
+      h.inv_lam = (float)(1.0 / lam);
+      h.inv_lam2 = (float)(1.0 / (lam * lam));
+      if (d.band_limit >= 2) {
+        const double fxl = 1.0 / (lam * std::sqrt((2.0 * dfx * z) * (2.0 * dfx * z) + 1.0));
+        const double fyl = 1.0 / (lam * std::sqrt((2.0 * dfy * z) * (2.0 * dfy * z) + 1.0));
+        h.kx_max = (int)std::min(std::floor(fxl / dfx), 1e9);
+        h.ky_max = (int)std::min(std::floor(fyl / dfy), 1e9);
+        if (h.kx_max < p->pW / 2 || h.ky_max < p->pH / 2) sampling_cut = true;   // |signed bin| <= padded size / 2
+      } else {
+        h.kx_max = h.ky_max = 1 << 30;
+      }
+      const double e = (double)p->pW * p->pH * d.pitch / lam;
+      const double bound = std::floor(e * e);
+      h.evan_bound = bound > 9e18 ? (long long)9e18 : (long long)bound;
+      h.decay = (float)(2.0 * M_PI * std::fabs(z));
+      // the corner bin (pW/2, pH/2) has the largest |f|
+      const double hx = (double)(p->pW / 2), hy = (double)(p->pH / 2);
+      if (hx * hx * p->pH * (double)p->pH + hy * hy * p->pW * (double)p->pW > (double)h.evan_bound)
+        p->evanescent = true;
+    }
+  p->mask_free = !p->evanescent && !sampling_cut;
   // columns per workgroup in the column passes (two LDS buffers of pH * C)
   if ((int64_t)2 * 8 * p->pW > ctx->lds_per_block)
     return bad(fail(CHRF_EUNSUPPORTED, "plan: a padded row does not fit the LDS"));
@@ -410,40 +445,6 @@ chrf_status chrf_plan_create(chrf_ctx* ctx, const chrf_plan_desc* desc, chrf_pla
                                d.fft_cols_plan >= tuned_col_plans(geom(p))))
     return bad(fail(CHRF_EUNSUPPORTED, "plan: fft_cols_plan must be 0 unless the padded height is 2160 with two "
                                        "columns per workgroup, or 4320 (then 0..3)"));
-  // transfer-function parameters
-  std::vector<HParam> hp(p->L * p->K);
-  const double dfx = 1.0 / (p->pW * d.pitch), dfy = 1.0 / (p->pH * d.pitch);
-  bool sampling_cut = false;   // some plane's sampling band limit removes a bin
-  for (int l = 0; l < p->L; ++l)
-    for (int k = 0; k < p->K; ++k) {
-      // a layered plan propagates the hologram back to its layers (-Z_k);
-      // the recording (+Z_l) is the adjoint of that map
-      const double lam = d.wavelengths[l], z = p->layered ? -d.distances[k] : d.distances[k];
-      HParam& h = hp[l * p->K + k];
-      const double zl = z / lam;
-      h.frac_rev = (float)(zl - std::floor(zl));
-      h.z = (float)z;
-      h.inv_lam = (float)(1.0 / lam);
-      h.inv_lam2 = (float)(1.0 / (lam * lam));
-      if (d.band_limit >= 2) {
-        const double fxl = 1.0 / (lam * std::sqrt((2.0 * dfx * z) * (2.0 * dfx * z) + 1.0));
-        const double fyl = 1.0 / (lam * std::sqrt((2.0 * dfy * z) * (2.0 * dfy * z) + 1.0));
-        h.kx_max = (int)std::min(std::floor(fxl / dfx), 1e9);
-        h.ky_max = (int)std::min(std::floor(fyl / dfy), 1e9);
-        if (h.kx_max < p->pW / 2 || h.ky_max < p->pH / 2) sampling_cut = true;   // |signed bin| <= padded size / 2
-      } else {
-        h.kx_max = h.ky_max = 1 << 30;
-      }
-      const double e = (double)p->pW * p->pH * d.pitch / lam;
-      const double bound = std::floor(e * e);
-      h.evan_bound = bound > 9e18 ? (long long)9e18 : (long long)bound;
-      h.decay = (float)(2.0 * M_PI * std::fabs(z));
-      // the corner bin (pW/2, pH/2) has the largest |f|
-      const double hx = (double)(p->pW / 2), hy = (double)(p->pH / 2);
-      if (hx * hx * p->pH * (double)p->pH + hy * hy * p->pW * (double)p->pW > (double)h.evan_bound)
-        p->evanescent = true;
-    }
-  p->mask_free = !p->evanescent && !sampling_cut;
   {
     hipError_t e = hipMalloc(&p->hp_dev, sizeof(HParam) * hp.size());
     if (e == hipSuccess) e = hipMemcpy(p->hp_dev, hp.data(), sizeof(HParam) * hp.size(), hipMemcpyHostToDevice);

@@ -215,6 +215,33 @@ def test_radix_schedules_at_full_size(plans):
     assert rel_l2(GU[0, li], ref) < TOL
 
 
+@pytest.mark.parametrize("H,mode,cols", [(1080, 2, 2), (1080, 1, 4), (2160, 2, 2), (2160, 2, 1), (2160, 1, 2),
+                                         (2160, 0, 0)])
+def test_tuned_columns_with_band_masks(H, mode, cols):
+    """Columns of 2160 and of 4320 (tuned transforms; 4320 as two of 2160,
+    one or two columns per workgroup) where the band limits mask bins: a
+    pitch of 0.2 um puts evanescent bins on the grid, band mode 1 cuts them,
+    mode 2 also applies the sampling limit, and mode 0 keeps their decaying
+    continuation (which the generic transforms form).  Narrow rows keep the
+    oracle cheap; two planes of two wavelengths and the adjoint."""
+    announce(f"masked columns H={H} mode={mode} cols={cols}")
+    W, pitch = 64, 0.2e-6
+    lams, zs = (515e-9, 639e-9), (4e-6, 1e-5)
+    opt = Optics(lams, zs, pitch, 2, mode)
+    r = make_renderer([identity_camera(W, H)], opt, 1, cols_per_block=cols)
+    U = _field((1, 2, H, W), 31)
+    prop, _ = r.propagate(_to_gpu(U), want_intensity=False)
+    torch.cuda.synchronize()
+    for li, ki in ((0, 0), (1, 1)):
+        ref = oracle.propagate(U[0, li], lams[li], zs[ki], pitch, 2, mode)
+        assert rel_l2(cplx(prop[0, li, ki]), ref) < TOL, (li, ki)
+    G = _field((1, 2, 2, H, W), 32)
+    back = r.propagate_adjoint(_to_gpu(G))
+    torch.cuda.synchronize()
+    ref = sum(oracle.propagate_adjoint(G[0, 1, k], lams[1], zs[k], pitch, 2, mode) for k in range(2))
+    assert rel_l2(cplx(back[0, 1]), ref) < TOL
+
+
 _LAMS_2160P, _ZS_2160P = (515e-9,), (0.8e-3, 1.6e-3)
 
 
