@@ -144,6 +144,26 @@ def test_wide_rows_propagation_and_fused_loss(W):
     assert abs(float(out["loss"]) - float((tgt.double() ** 2).mean())) < 1e-5
 
 
+def test_tuned_rows_without_padding():
+    """Rows of 3840 with pad factor 1 (the tuned row transforms with every
+    input live and every output kept; rows of 7680 always come from a padded
+    width of 3840, the largest the plans take): one propagated plane and the
+    adjoint against the oracle."""
+    announce("tuned rows, no padding, W=3840")
+    H, W, lam, zs = 4, 3840, 515e-9, (1e-3, 2e-3)
+    opt = Optics((lam,), zs, 8e-6, 1, 2)
+    r = make_renderer([identity_camera(W, H)], opt, 1)
+    U = _field((1, 1, H, W), 41)
+    prop, _ = r.propagate(_to_gpu(U), want_intensity=False)
+    torch.cuda.synchronize()
+    assert rel_l2(cplx(prop[0, 0, 1]), oracle.propagate(U[0, 0], lam, zs[1], 8e-6, 1, 2)) < TOL
+    G = _field((1, 1, 2, H, W), 42)
+    back = r.propagate_adjoint(_to_gpu(G))
+    torch.cuda.synchronize()
+    ref = sum(oracle.propagate_adjoint(G[0, 0, k], lam, z, 8e-6, 1, 2) for k, z in enumerate(zs))
+    assert rel_l2(cplx(back[0, 0]), ref) < TOL
+
+
 @pytest.mark.parametrize("views,zs", [
     (1, (1e-3,)),                                                  # one plane: no copy in flight
     (2, (0.4e-3, 0.9e-3, 1.3e-3, 1.7e-3, 2.2e-3, 2.6e-3, 3e-3)),   # seven planes, two views
