@@ -36,6 +36,42 @@ def _run(scene, cams, opt, thr=oracle.DEFAULT, tile=(16, 16), n_max=None):
     return r, out, need
 
 
+@pytest.mark.parametrize("kind", ["faint", "needles"])
+def test_tile_lists_of_faint_and_needle_gaussians(kind):
+    """The tile spans at their edges: Gaussians whose opacity is below
+    alpha_min (largest supporting power < 0: no tile) or just above it (tiny
+    ellipses), and needle-thin, rotated ones (long diagonal spans, the form's
+    terms far larger than the power).  Bit-exact lists and ranges."""
+    announce(f"binning edge cases: {kind}")
+    thr = oracle.DEFAULT
+    if kind == "faint":
+        sc = make_gaussians(2000, 1, 131, log_scale_mean=-3.0, opacity_logit_mean=-5.5, opacity_logit_std=0.4)
+    else:
+        sc = make_gaussians(2000, 1, 132, log_scale_mean=-3.5, log_scale_std=0.2)
+        sc.log_scales[:, 0] += 2.0        # long axis
+        sc.log_scales[:, 1] -= 2.5        # thin axis
+    cams = [identity_camera(200, 150, f=160)]
+    r, out, need = _run(sc, cams, OPT1)
+    fps = [binning.fp32_footprint(sc.means, sc.log_scales, sc.quats, c, 16, 16, thr.k_sigma, sc.opacity,
+                                  thr.alpha_min) for c in cams]
+    ref = binning.bin_pairs(fps, 200, 150)
+    n = len(ref["tile_key"])
+    assert need == n
+    if kind == "faint":
+        assert np.mean(sc.opacity < thr.alpha_min) > 0.2 and n > 0
+    keys = r.region(_lib.REGION_PAIR_KEYS, torch.int32)[:n].cpu().numpy().view(np.uint32).astype(np.int64)
+    vals = r.region(_lib.REGION_PAIR_VALUES, torch.int32)[:n].cpu().numpy().view(np.uint32).astype(np.int64)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(keys[order], ref["tile_key"].astype(np.int64))
+    assert np.array_equal(vals[order], ref["gauss"].astype(np.int64))
+    ranges = r.region(_lib.REGION_TILE_RANGES, torch.int32).cpu().numpy().view(np.uint32).reshape(-1, 2)
+    ref_len = ref["ranges"][:, 1] - ref["ranges"][:, 0]
+    assert np.array_equal(np.where(ref_len > 0, ranges[:, 1].astype(np.int64) - ranges[:, 0], 0), ref_len)
+    # the field is the oracle's: dropped tiles held no supported pixel
+    U = cplx(out["field"][0])
+    assert rel_l2(U, _oracle_field(sc, cams[0], thr).U) < 1e-4
+
+
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8), (8, 16)])
 @pytest.mark.parametrize("views", ["one", "yaw3"])
 def test_tile_lists_bit_exact(tile, views):
