@@ -35,7 +35,11 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
   const size_t rid = (size_t)b * a.n_stride + g;
   if (a.grad2d) {   // every row of the view, used or not
     float* gp = a.grad2d + rid * a.grad2d_stride;
-    for (int c = 0; c < a.grad2d_stride; ++c) gp[c] = 0.0f;
+    if (a.grad2d_stride % 4 == 0 && (reinterpret_cast<uintptr_t>(a.grad2d) & 15u) == 0) {
+      for (int c = 0; c < a.grad2d_stride; c += 4) *reinterpret_cast<float4*>(gp + c) = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      for (int c = 0; c < a.grad2d_stride; ++c) gp[c] = 0.0f;
+    }
   }
   if (g >= a.n) {   // unused slots sort last and emit nothing
     a.count[rid] = 0;
