@@ -184,7 +184,24 @@ __global__ __launch_bounds__(256) void k_project_backward(
   for (int b = 0; b < n_views; ++b) {
     const size_t rid = (size_t)b * n_stride + g;
     if (count[rid] == 0) continue;
-    const float* gp = grad2d + rid * g2s;
+    // the row's 6 + 2 n_lambda values, read as 16-byte words when the rows allow it
+    float gp[6 + 2 * kMaxLambda + 2];
+    const float* src = grad2d + rid * g2s;
+    const int nv = 6 + 2 * n_lambda;
+    if (g2s % 4 == 0 && (reinterpret_cast<uintptr_t>(grad2d) & 15u) == 0) {
+#pragma unroll
+      for (int c = 0; c < 6 + 2 * kMaxLambda + 2; c += 4) {
+        if (c < nv) {
+          const float4 q = *reinterpret_cast<const float4*>(src + c);
+          gp[c] = q.x;
+          gp[c + 1] = q.y;
+          gp[c + 2] = q.z;
+          gp[c + 3] = q.w;
+        }
+      }
+    } else {
+      for (int c = 0; c < nv; ++c) gp[c] = src[c];
+    }
     const float dmx = gp[0], dmy = gp[1], dA = gp[2], dB = gp[3], dC = gp[4];
     gop += gp[5];
     for (int l = 0; l < 2 * n_lambda; ++l) gv[l] += gp[6 + l];
