@@ -125,12 +125,12 @@ chrf_status timed(chrf_plan* p, const char* name, hipStream_t s, F&& launch) {
   if (p->timing) {
     a = take_event(p);
     b = take_event(p);
-    if (a && b) hipEventRecord(a, s);
+    if (a && b) (void)hipEventRecord(a, s);
   }
   hipError_t e = launch();
   if (e != hipSuccess) return fail(CHRF_EHIP, std::string(name) + ": " + hipGetErrorString(e));
   if (p->timing && a && b) {
-    hipEventRecord(b, s);
+    (void)hipEventRecord(b, s);
     p->trec.push_back({name, a, b});
   }
   return CHRF_OK;
@@ -285,8 +285,8 @@ chrf_status chrf_create(int device, chrf_ctx** out) {
 
 static void release_retired(chrf_ctx* ctx) {
   std::lock_guard<std::mutex> lock(ctx->mu);
-  for (void* m : ctx->retired_mem) hipFree(m);
-  for (hipEvent_t e : ctx->retired_events) hipEventDestroy(e);
+  for (void* m : ctx->retired_mem) (void)hipFree(m);
+  for (hipEvent_t e : ctx->retired_events) (void)hipEventDestroy(e);
   ctx->retired_mem.clear();
   ctx->retired_events.clear();
 }
@@ -294,7 +294,7 @@ static void release_retired(chrf_ctx* ctx) {
 void chrf_destroy(chrf_ctx* ctx) {
   if (!ctx) return;
   release_retired(ctx);
-  for (auto& kv : ctx->twiddles) hipFree(kv.second);
+  for (auto& kv : ctx->twiddles) (void)hipFree(kv.second);
   delete ctx;
 }
 

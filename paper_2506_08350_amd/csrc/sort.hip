@@ -950,7 +950,7 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ r
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
       const uint32_t t = __shfl_up(incl, off, 64);
-      if ((threadIdx.x & 63) >= off) incl += t;
+      if ((int)(threadIdx.x & 63) >= off) incl += t;
     }
     if ((threadIdx.x & 63) == 63) wave_tot[threadIdx.x >> 6] = incl;
   }
