@@ -462,6 +462,103 @@ def bench_2160p(steps, warmup, log=None):
             "loss": float(loss), "gradients_finite": finite, "steps": steps, "warmup": warmup}
 
 
+def bench_next_rows(steps, log):
+    """Step times of the rows beyond the single-plane path, on the 1080p
+    scene: the four-layer hologram (record + inverse propagation with
+    straight-through plane assignment), the paper's training loss (masked
+    reconstruction + SSIM), one phase-only conversion step of the rendered
+    frame's hologram, and one step of the optimisation loop (render, Adan on
+    every tensor, gradient statistics) plus one densification.  Each is timed
+    over ``steps`` steps after two warm-up steps, with a synchronisation on
+    both sides."""
+    import torch
+
+    import scenegen
+    from paper_2506_08350_amd import api
+
+    def timed(fn, n):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1000.0 / n
+
+    def renderer(w, params, cam_t, **kw):
+        sc, cams, opt = w.scene, w.cameras, w.optics
+        o = api.Optics(opt.wavelengths, opt.distances, opt.pitch, opt.pad, opt.band_limit)
+        H, W = cams[0].height, cams[0].width
+        probe = api.Renderer(H, W, o, n_views=len(cams), max_gaussians=sc.n, max_pairs=1 << 27,
+                             layered=kw.get("layered", False))
+        probe.forward(params, cam_t, want_field=False, want_intensity=False)
+        need = probe.read_status()[1]
+        del probe
+        return api.Renderer(H, W, o, n_views=len(cams), max_gaussians=sc.n, max_pairs=int(need * 1.25) + 4096,
+                            **kw)
+
+    out = {}
+    # four-layer hologram, the training step captured in a HIP graph
+    w = scenegen.make_workload("c3_layers")
+    cam_t = api.pack_cameras(w.cameras)
+    params = {k: torch.from_numpy(a).cuda() for k, a in zip(api.PARAM_NAMES, w.scene.arrays())}
+    params[api.LAYER_LOGITS] = torch.from_numpy(w.notes["logits"]).cuda()
+    target = torch.from_numpy(w.targets).cuda()
+    r = renderer(w, params, cam_t, layered=True)
+    cap = api.CapturedTrainStep(r, params, cam_t, target)
+    ms = timed(cap.replay, steps)
+    out["layers_4_fwd_bwd"] = {"workload": w.name, "graph": True, "ms_per_step": round(ms, 4),
+                               "frames_per_s": round(1000.0 / ms, 3)}
+    log(f"four-layer step {ms:.3f} ms")
+    del cap, r
+    torch.cuda.empty_cache()
+    # the paper's training loss
+    w = scenegen.make_workload("c3")
+    B, K, H, W = len(w.cameras), len(w.optics.distances), w.cameras[0].height, w.cameras[0].width
+    cam_t = api.pack_cameras(w.cameras)
+    params = {k: torch.from_numpy(a).cuda() for k, a in zip(api.PARAM_NAMES, w.scene.arrays())}
+    target = torch.from_numpy(w.targets).cuda()
+    masks = torch.from_numpy(scenegen.make_plane_masks(B, K, H, W, w.notes["masks_seed"])).cuda()
+    r = renderer(w, params, cam_t, loss="paper")
+    cap = api.CapturedTrainStep(r, params, cam_t, target, masks=masks)
+    ms = timed(cap.replay, steps)
+    out["paper_loss_fwd_bwd"] = {"workload": "c3_fwd_bwd_1080p_3l_4z_100k, masked reconstruction + SSIM",
+                                 "graph": True, "ms_per_step": round(ms, 4), "frames_per_s": round(1000.0 / ms, 3)}
+    log(f"paper-loss step {ms:.3f} ms")
+    del cap, r, masks
+    torch.cuda.empty_cache()
+    # phase-only conversion of the rendered frame's hologram (3 wavelengths x 4 planes)
+    r = renderer(w, params, cam_t, phase_only=True)
+    field = r.forward(params, cam_t, want_field=True, want_intensity=False)["field"]
+    targets, _ = r.propagate(field, want_intensity=False)
+    phi = torch.atan2(field[..., 1], field[..., 0]).contiguous()
+    ms = timed(lambda: r.phase_only_step(targets, phi), steps)
+    out["phase_only_step"] = {"what": "loss and dL/dphi of exp(j phi) against the propagated planes, 1080p x 3 "
+                                      "wavelengths x 4 planes", "ms_per_step": round(ms, 4)}
+    log(f"phase-only step {ms:.3f} ms")
+    del r, field, targets, phi
+    torch.cuda.empty_cache()
+    # the optimisation loop: render + Adan + statistics, then one densification
+    raw = dict(params)
+    o = raw["opacity"].clamp(1e-6, 1 - 1e-6)
+    raw["opacity"] = torch.log(o / (1.0 - o)).contiguous()
+    r = renderer(w, params, cam_t)
+    tr = api.Trainer(r, raw, cam_t, target, total_steps=10 ** 6, densify_every=10 ** 6)
+    ms = timed(tr.step, steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr.densify()
+    torch.cuda.synchronize()
+    dms = (time.perf_counter() - t0) * 1000.0
+    out["training_step"] = {"what": "render fwd+bwd (eager), Adan on every tensor, view-space gradient statistics",
+                            "ms_per_step": round(ms, 4), "densify_ms": round(dms, 3), "gaussians_after": tr.n}
+    log(f"training step {ms:.3f} ms, densification {dms:.2f} ms")
+    del tr, r
+    torch.cuda.empty_cache()
+    return out
+
+
 def torch_fft_reference(r, o, field, reps=10):
     """Forward propagation of one frame (zero pad, FFT2, transfer function,
     inverse FFT2, crop, |u|^2 for every wavelength and plane) written with
@@ -726,6 +823,8 @@ def main(argv=None):
         line["ring_16_views"] = bench_ring(max(2, args.steps // 4), 2, log)
         log("2160p, 4 views")
         line["views_2160p"] = bench_2160p(3, 1, log)
+        log("rows beyond the single-plane path")
+        line["next_rows"] = bench_next_rows(max(5, args.steps // 2), log)
     print(json.dumps(line), flush=True)
     return 0
 
