@@ -23,9 +23,11 @@ namespace chrf {
 constexpr int kLT = 32;                 // output tile edge
 constexpr int kLR = 5;                  // window radius
 constexpr int kLE = kLT + 2 * kLR;      // staged edge
-constexpr int kLThreads = 256;
-constexpr int kLB = 4;                  // outputs per thread along a pass (register blocking)
-static_assert(kLThreads == kLT * (kLT / kLB), "one vertical-pass block of kLB rows per thread");
+constexpr int kLThreads = 512;
+constexpr int kLB = 4;                  // outputs per item of the horizontal pass (register blocking)
+constexpr int kLBV = 2;                 // output rows per thread of the vertical pass
+static_assert(kLE * (kLT / kLB) <= kLThreads, "the horizontal pass takes one round");
+static_assert(kLThreads == kLT * (kLT / kLBV), "one vertical-pass block of kLBV rows per thread");
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
 
@@ -98,17 +100,17 @@ __global__ __launch_bounds__(kLThreads) void k_loss_fwd(const float* __restrict_
                             : nullptr;
   float s_sum = 0.f, r_sum = 0.f;
   // vertical pass: thread (column c, row group) forms the window averages of
-  // kLB consecutive output rows from 14 staged rows
+  // kLBV consecutive output rows from kLBV + 10 staged rows
   {
-    const int c = threadIdx.x % kLT, r0o = (threadIdx.x / kLT) * kLB;
-    float m[kLB][5] = {};
+    const int c = threadIdx.x % kLT, r0o = (threadIdx.x / kLT) * kLBV;
+    float m[kLBV][5] = {};
 #pragma unroll
-    for (int k = 0; k < kLB + 2 * kLR; ++k) {
+    for (int k = 0; k < kLBV + 2 * kLR; ++k) {
       float h[5];
 #pragma unroll
       for (int q = 0; q < 5; ++q) h[q] = hs[q][r0o + k][c];
 #pragma unroll
-      for (int o = 0; o < kLB; ++o) {
+      for (int o = 0; o < kLBV; ++o) {
         const int tap = k - o;
         if (tap < 0 || tap > 2 * kLR) continue;
         const float w = lg.g[tap];
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(kLThreads) void k_loss_fwd(const float* __restrict_
       }
     }
 #pragma unroll
-    for (int o = 0; o < kLB; ++o) {
+    for (int o = 0; o < kLBV; ++o) {
       const int r = r0o + o;
       const int gr = ty * kLT + r, gc = tx * kLT + c;
       if (gr >= lg.H || gc >= lg.W) continue;
@@ -207,15 +209,15 @@ __global__ __launch_bounds__(kLThreads) void k_loss_bwd(const float* __restrict_
   const float scale = grad_scale ? *grad_scale : 1.0f;
   const uint8_t* mk = masks ? masks + ((size_t)(img / lg.per_view) * lg.planes + img % lg.planes) * lg.H * lg.W
                             : nullptr;
-  const int c = threadIdx.x % kLT, r0o = (threadIdx.x / kLT) * kLB;
-  float f[kLB][3] = {};
+  const int c = threadIdx.x % kLT, r0o = (threadIdx.x / kLT) * kLBV;
+  float f[kLBV][3] = {};
 #pragma unroll
-  for (int k = 0; k < kLB + 2 * kLR; ++k) {
+  for (int k = 0; k < kLBV + 2 * kLR; ++k) {
     float h[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) h[q] = hs[q][r0o + k][c];
 #pragma unroll
-    for (int o = 0; o < kLB; ++o) {
+    for (int o = 0; o < kLBV; ++o) {
       const int tap = k - o;
       if (tap < 0 || tap > 2 * kLR) continue;
       const float w = lg.g[tap];
@@ -224,7 +226,7 @@ __global__ __launch_bounds__(kLThreads) void k_loss_bwd(const float* __restrict_
     }
   }
 #pragma unroll
-  for (int o = 0; o < kLB; ++o) {
+  for (int o = 0; o < kLBV; ++o) {
     const int gr = ty * kLT + r0o + o, gc = tx * kLT + c;
     if (gr >= lg.H || gc >= lg.W) continue;
     const size_t oi = base + ((size_t)gr * lg.W + gc) * lg.chan;
