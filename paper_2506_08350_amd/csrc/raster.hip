@@ -11,8 +11,10 @@
 // the support rectangle, power <= k^2/2 and a >= alpha_min:
 //   U_l += v_l a T,  T *= 1 - a,  stop after T < T_min.
 // Backward per pixel, from its last contributor down:  T_g = T / (1 - a),
-//   dL/da = T_g sum_l Re(conj(G_l)(v_l - B_l)),  B_l <- a v_l + (1 - a) B_l,
-// and the per-pair gradients (d mu, d conic, d opacity, d v) are summed over a
+//   dL/da = T_g sum_l Re(conj(G_l)(v_l - B_l)),  B_l <- a v_l + (1 - a) B_l.
+// B enters only through the real number K = sum_l Re(conj(G_l) B_l), which is
+// what a pixel keeps: dL/da = T_g (D - K) with D = sum_l Re(conj(G_l) v_l),
+// and K <- K + a (D - K).  The per-pair gradients (d mu, d conic, d opacity, d v) are summed over a
 // lane's pixels, then over the wave (32- and 16-lane swaps, then DPP row
 // shifts), then over the tile's waves in LDS, and added to the per-(view,
 // Gaussian) accumulators with one atomic per value.
@@ -127,7 +129,8 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
   bool inside[PPT];
   float T[PPT];
   uint32_t mylast[PPT];
-  float2 G[PPT][NL], Bacc[PPT][NL];
+  float2 G[PPT][NL];
+  float K[PPT];   // sum over wavelengths of Re(conj(G) B)
   const float scale = a.grad_scale ? *a.grad_scale : 1.0f;
   const size_t plane = (size_t)a.height * a.width;
   uint32_t tile_last = 0;
@@ -141,11 +144,9 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
     inside[p] = px[p] < a.width && py[p] < a.height;
     T[p] = 1.0f;
     mylast[p] = 0;
+    K[p] = 0.f;
 #pragma unroll
-    for (int l = 0; l < NL; ++l) {
-      G[p][l] = make_float2(0.f, 0.f);
-      Bacc[p][l] = make_float2(0.f, 0.f);
-    }
+    for (int l = 0; l < NL; ++l) G[p][l] = make_float2(0.f, 0.f);
     if (inside[p]) {
       const size_t pix = (size_t)py[p] * a.width + px[p];
       T[p] = a.t_final[(size_t)t.view * plane + pix];
@@ -218,19 +219,18 @@ __global__ __launch_bounds__(kLanes * NW) void k_raster_bwd(RasterArgs a) {
         const float ae = sup ? aval : 0.f;
         const float Tb = T[p] * __builtin_amdgcn_rcpf(1.0f - ae);
         const float aT = ae * Tb;
-        float dLda = 0.f;
+        float D = 0.f;
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
           const float2 v = st.v[l][j];
-          // v - B serves dL/da and the update B <- a v + (1 - a) B = B + a (v - B)
-          const float ex = v.x - Bacc[p][l].x, ey = v.y - Bacc[p][l].y;
-          dLda += G[p][l].x * ex + G[p][l].y * ey;
+          D += G[p][l].x * v.x + G[p][l].y * v.y;
           const float gx = aT * G[p][l].x, gy = aT * G[p][l].y;
           gr[6 + 2 * l] = PPT == 1 ? gx : gr[6 + 2 * l] + gx;
           gr[7 + 2 * l] = PPT == 1 ? gy : gr[7 + 2 * l] + gy;
-          Bacc[p][l].x += ae * ex;
-          Bacc[p][l].y += ae * ey;
         }
+        // D - K serves dL/da and the update B <- B + a (v - B), i.e. K <- K + a (D - K)
+        const float dLda = D - K[p];
+        K[p] += ae * dLda;
         T[p] = Tb;
         // clamped pixels pass no gradient to the opacity or the conic
         const float dl = (sup && !clamped) ? dLda * Tb : 0.f;

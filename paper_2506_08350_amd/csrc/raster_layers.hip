@@ -13,7 +13,10 @@
 // of the Gaussian and B_q the field of layer q behind it,
 //   s_q = T_q sum_l Re(conj(G_ql) (v_l - B_ql)),   dL/drho_q = a s_q,
 // which for the Gaussian's own layer is also dL/da; there T_q is recovered as
-// T_q / (1 - a) and B_q <- a v + (1 - a) B_q.  The per-pair gradient vector
+// T_q / (1 - a) and B_q <- a v + (1 - a) B_q.  B_q enters only through the
+// real number K_q = sum_l Re(conj(G_ql) B_ql), so that is what a pixel keeps:
+// s_q = T_q (D_q - K_q) with D_q = sum_l Re(conj(G_ql) v_l), and the update
+// of B_q becomes K_q <- K_q + a (D_q - K_q).  The per-pair gradient vector
 // (d mu, d conic, d opacity, d v, d rho) is reduced over the wave and added
 // to the per-(view, Gaussian) accumulators; k_logits_backward then applies
 // the straight-through weights softmax(logits / tau).
@@ -170,10 +173,10 @@ __global__ __launch_bounds__(64 * NWAVE, 8) void k_raster_layers_fwd(RasterArgs 
   a.last[(size_t)t.view * plane + pix] = walk_end;
 }
 
-// At least four waves per SIMD (a 128-VGPR budget): the per-layer state of
-// four layers alone needs 143 registers unconstrained, three waves per SIMD.
+// At least five waves per SIMD (a 96-VGPR budget; the per-layer state of four
+// layers at three wavelengths is 36 registers): the pair walk is latency-bound.
 template <int NL, int NLAY, int NWAVE>
-__global__ __launch_bounds__(64 * NWAVE, 4) void k_raster_layers_bwd(RasterArgs a) {
+__global__ __launch_bounds__(64 * NWAVE, 5) void k_raster_layers_bwd(RasterArgs a) {
   constexpr int G2 = 6 + 2 * NL + NLAY;
   constexpr int G2P = (G2 + 3) & ~3;
   __shared__ StageL<NL> st;
@@ -190,17 +193,16 @@ __global__ __launch_bounds__(64 * NWAVE, 4) void k_raster_layers_bwd(RasterArgs 
   const size_t pix = (size_t)py * a.width + px;
   float T[NLAY];
   uint32_t stop[NLAY];
-  float2 G[NLAY][NL], Bacc[NLAY][NL];
+  float2 G[NLAY][NL];
+  float K[NLAY];   // sum over wavelengths of Re(conj(G) B) of each layer
   uint32_t mylast = 0;
 #pragma unroll
   for (int q = 0; q < NLAY; ++q) {
     T[q] = 1.0f;
     stop[q] = 0u;
+    K[q] = 0.f;
 #pragma unroll
-    for (int l = 0; l < NL; ++l) {
-      G[q][l] = make_float2(0.f, 0.f);
-      Bacc[q][l] = make_float2(0.f, 0.f);
-    }
+    for (int l = 0; l < NL; ++l) G[q][l] = make_float2(0.f, 0.f);
     if (inside) {
       const size_t lp = ((size_t)t.view * a.n_layers + q) * plane + pix;
       T[q] = a.t_final[lp];
@@ -273,31 +275,29 @@ __global__ __launch_bounds__(64 * NWAVE, 4) void k_raster_layers_bwd(RasterArgs 
             continue;
           }
           const bool act = sup && pidx < stop[q];   // layer q had not stopped before this pair
-          float sq = 0.f;
+          float dq = 0.f;
 #pragma unroll
           for (int l = 0; l < NL; ++l) {
             const float2 v = st.s.v[l][j];
-            sq += G[q][l].x * (v.x - Bacc[q][l].x) + G[q][l].y * (v.y - Bacc[q][l].y);
+            dq += G[q][l].x * v.x + G[q][l].y * v.y;
           }
+          const float raw = dq - K[q];   // sum_l Re(conj(G) (v - B)) of layer q
           if (own) {
             const float ae = act ? aval : 0.f;
             const float Tb = T[q] * __builtin_amdgcn_rcpf(1.0f - ae);
-            sq *= Tb;
+            const float sq = raw * Tb;
             gr[6 + 2 * NL + q] = ae * sq;
             dLda = act ? sq : 0.f;
             const float aT = ae * Tb;
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
-              const float2 v = st.s.v[l][j];
               gr[6 + 2 * l] = aT * G[q][l].x;
               gr[7 + 2 * l] = aT * G[q][l].y;
-              // B <- a v + (1 - a) B as B + a (v - B), reusing v - B of dL/da
-              Bacc[q][l].x += ae * (v.x - Bacc[q][l].x);
-              Bacc[q][l].y += ae * (v.y - Bacc[q][l].y);
             }
+            K[q] += ae * raw;   // B <- B + a (v - B)
             T[q] = Tb;
           } else {
-            gr[6 + 2 * NL + q] = act ? aval * (sq * T[q]) : 0.f;
+            gr[6 + 2 * NL + q] = act ? aval * (raw * T[q]) : 0.f;
           }
         }
         // clamped pixels pass no gradient to the opacity or the conic
