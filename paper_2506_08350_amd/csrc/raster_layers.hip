@@ -26,6 +26,8 @@
 // registers; the waves share the LDS staging of the tile's records, and in
 // the backward each wave's reduced gradient of a pair is added to the
 // workgroup's LDS row of that pair before one global atomic per value.
+#include <type_traits>
+
 #include "raster_common.h"
 
 namespace chrf {
@@ -57,6 +59,18 @@ __global__ void k_assign_layers(const float* __restrict__ logits, int n, int nla
       best = q;
     }
   layer_of[g] = (uint8_t)(best | (ste_live_layers(r, nlay, inv_tau) << 4));
+}
+
+// Calls f(std::integral_constant<int, lay>()) for lay in [Q, N): the
+// layer becomes a compile-time constant inside f.
+template <int Q, int N, class F>
+__device__ inline void with_layer(int lay, F&& f) {
+  if constexpr (Q < N) {
+    if (lay == Q)
+      f(std::integral_constant<int, Q>());
+    else
+      with_layer<Q + 1, N>(lay, f);
+  }
 }
 
 template <int NL>
@@ -242,89 +256,96 @@ __global__ __launch_bounds__(64 * NWAVE, 5) void k_raster_layers_bwd(RasterArgs 
         const int4 rc = st.s.rc[j];
         const uint32_t pidx = top - 1 - j;
         const int packed = __builtin_amdgcn_readfirstlane(st.lay[j]);
-        const int lay = packed & 7;
         const uint32_t ste_live = (uint32_t)packed >> 4;
-        // a pixel gains nothing from this pair past its own layer's stop unless it
-        // is still live in another layer with a nonzero straight-through weight
-        bool useful = pidx < stop[lay];
+        // One copy of the pair's work per layer, chosen by the Gaussian's own
+        // layer (wave-uniform): inside a copy that layer is a constant, so
+        // only its T and K change and nothing else crosses the branches.
+        with_layer<0, NLAY>(packed & 7, [&](auto own_layer) {
+          constexpr int LAY = decltype(own_layer)::value;
+          // A pixel gains nothing from this pair past its own layer's stop
+          // unless it is still live in another layer with a nonzero
+          // straight-through weight.
+          uint32_t reach = stop[LAY];
 #pragma unroll
-        for (int q = 0; q < NLAY; ++q)
-          useful = useful || (q != lay && ((ste_live >> q) & 1u) && pidx < stop[q]);
-        if (!__any(useful)) continue;
-        const float4 g0 = st.s.g0[j];
-        const float4 g1 = st.s.g1[j];
-        const float dx = pxf - g0.x, dy = pyf - g0.y;
-        const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
-        const bool in_rect = (unsigned)(px - rc.x) <= (unsigned)rc.y && (unsigned)(py - rc.z) <= (unsigned)rc.w;
-        const float Gv = __expf(-power);
-        const float oG = g1.y * Gv;
-        const bool clamped = oG > a.alpha_max;
-        const float aval = clamped ? a.alpha_max : oG;
-        const bool sup = useful && pidx < mylast && in_rect && power <= half_k2 && aval >= a.alpha_min;
-        if (!__any(sup)) continue;
-        // Branch-free per pixel: where layer q is not active the own layer takes
-        // alpha = 0 (its T and B stay exactly unchanged) and another layer's
-        // straight-through term is zero.
-        float gr[G2P];
-        float dLda = 0.f;
+          for (int q = 0; q < NLAY; ++q)
+            if (q != LAY && ((ste_live >> q) & 1u)) reach = max(reach, stop[q]);
+          const float4 g0 = st.s.g0[j];
+          const float4 g1 = st.s.g1[j];
+          const float dx = pxf - g0.x, dy = pyf - g0.y;
+          const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
+          const bool in_rect =
+              (unsigned)(px - rc.x) <= (unsigned)rc.y && (unsigned)(py - rc.z) <= (unsigned)rc.w;
+          const float Gv = __expf(-power);
+          const float oG = g1.y * Gv;
+          const bool clamped = oG > a.alpha_max;
+          const float aval = clamped ? a.alpha_max : oG;
+          const bool sup = pidx < reach && pidx < mylast && in_rect && power <= half_k2 && aval >= a.alpha_min;
+          if (!__any(sup)) return;
+          float2 v[NL];
 #pragma unroll
-        for (int q = 0; q < NLAY; ++q) {
-          const bool own = q == lay;   // wave-uniform
-          if (!own && !((ste_live >> q) & 1u)) {   // zero straight-through weight
-            gr[6 + 2 * NL + q] = 0.f;
-            continue;
-          }
-          const bool act = sup && pidx < stop[q];   // layer q had not stopped before this pair
+          for (int l = 0; l < NL; ++l) v[l] = st.s.v[l][j];
+          // Branch-free per pixel: where the own layer is not active it takes
+          // alpha = 0 (its T and K stay exactly unchanged), and another
+          // layer's straight-through term is zero.
+          float gr[G2P];
+          const bool act = sup && pidx < stop[LAY];   // the own layer had not stopped before this pair
           float dq = 0.f;
 #pragma unroll
+          for (int l = 0; l < NL; ++l) dq += G[LAY][l].x * v[l].x + G[LAY][l].y * v[l].y;
+          const float raw = dq - K[LAY];   // sum_l Re(conj(G) (v - B)) of the own layer
+          const float ae = act ? aval : 0.f;
+          const float Tb = T[LAY] * __builtin_amdgcn_rcpf(1.0f - ae);
+          const float so = raw * Tb;
+          gr[6 + 2 * NL + LAY] = ae * so;
+          const float dLda = act ? so : 0.f;
+          const float aT = ae * Tb;
+#pragma unroll
           for (int l = 0; l < NL; ++l) {
-            const float2 v = st.s.v[l][j];
-            dq += G[q][l].x * v.x + G[q][l].y * v.y;
+            gr[6 + 2 * l] = aT * G[LAY][l].x;
+            gr[7 + 2 * l] = aT * G[LAY][l].y;
           }
-          const float raw = dq - K[q];   // sum_l Re(conj(G) (v - B)) of layer q
-          if (own) {
-            const float ae = act ? aval : 0.f;
-            const float Tb = T[q] * __builtin_amdgcn_rcpf(1.0f - ae);
-            const float sq = raw * Tb;
-            gr[6 + 2 * NL + q] = ae * sq;
-            dLda = act ? sq : 0.f;
-            const float aT = ae * Tb;
+          K[LAY] += ae * raw;   // B <- B + a (v - B)
+          T[LAY] = Tb;
 #pragma unroll
-            for (int l = 0; l < NL; ++l) {
-              gr[6 + 2 * l] = aT * G[q][l].x;
-              gr[7 + 2 * l] = aT * G[q][l].y;
+          for (int q = 0; q < NLAY; ++q) {
+            if (q == LAY) continue;
+            if (!((ste_live >> q) & 1u)) {   // zero straight-through weight
+              gr[6 + 2 * NL + q] = 0.f;
+              continue;
             }
-            K[q] += ae * raw;   // B <- B + a (v - B)
-            T[q] = Tb;
-          } else {
-            gr[6 + 2 * NL + q] = act ? aval * (raw * T[q]) : 0.f;
+            float d = 0.f;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) d += G[q][l].x * v[l].x + G[q][l].y * v[l].y;
+            // zero where layer q had stopped before this pair
+            const bool act_q = sup && pidx < stop[q];
+            gr[6 + 2 * NL + q] = act_q ? aval * ((d - K[q]) * T[q]) : 0.f;
           }
-        }
-        // clamped pixels pass no gradient to the opacity or the conic
-        const float dl = clamped ? 0.f : dLda;
-        const float dpow = -aval * dl;
-        gr[5] = Gv * dl;
-        gr[2] = 0.5f * dx * dx * dpow;
-        gr[3] = dx * dy * dpow;
-        gr[4] = 0.5f * dy * dy * dpow;
-        gr[0] = -(g0.z * dx + g0.w * dy) * dpow;
-        gr[1] = -(g0.w * dx + g1.x * dy) * dpow;
+          // clamped pixels pass no gradient to the opacity or the conic
+          const float dl = clamped ? 0.f : dLda;
+          const float dpow = -aval * dl;
+          gr[5] = Gv * dl;
+          gr[2] = 0.5f * dx * dx * dpow;
+          gr[3] = dx * dy * dpow;
+          gr[4] = 0.5f * dy * dy * dpow;
+          gr[0] = -(g0.z * dx + g0.w * dy) * dpow;
+          gr[1] = -(g0.w * dx + g1.x * dy) * dpow;
 #pragma unroll
-        for (int c = G2; c < G2P; ++c) gr[c] = 0.f;
-        wave_sums_by_row<G2P>(gr);
-        if ((lane & 15) == 15) {
-          const int row = lane >> 4;
+          for (int c = G2; c < G2P; ++c) gr[c] = 0.f;
+          wave_sums_by_row<G2P>(gr);
+          if ((lane & 15) == 15) {
+            const int row = lane >> 4;
 #pragma unroll
-          for (int k = 0; k < G2P / 4; ++k) {
-            const int c = k + row * (G2P / 4);
-            if (c < G2) {
-              if (NWAVE == 1)
-                s_grad[j][c] = gr[k];
-              else
-                atomicAdd(&s_grad[j][c], gr[k]);
+            for (int k = 0; k < G2P / 4; ++k) {
+              const int c = k + row * (G2P / 4);
+              if (c < G2) {
+                if (NWAVE == 1)
+                  s_grad[j][c] = gr[k];
+                else
+                  atomicAdd(&s_grad[j][c], gr[k]);
+              }
             }
           }
-        }
+        });
       }
     }
     __syncthreads();
