@@ -136,12 +136,13 @@ __global__ __launch_bounds__(64 * NWAVE, 8) void k_raster_layers_fwd(RasterArgs 
         if (__any((live >> q) & 1u)) wave_live |= 1u << q;
       uint64_t todo = block_hits(st.s.g0, st.s.g1, st.s.rc, 0, cnt, bx, by);
       const int lane = threadIdx.x & 63;
-      todo &= __ballot(lane < cnt && ((wave_live >> (st.lay[lane] & 7)) & 1u));
+      const int lane_lay = lane < cnt ? st.lay[lane] : 0;   // lane j holds pair j's layer byte
+      todo &= __ballot(lane < cnt && ((wave_live >> (lane_lay & 7)) & 1u));
       while (todo) {
         const int j = (int)__builtin_ctzll(todo);
         todo &= todo - 1;
         const int4 rc = st.s.rc[j];
-        const int lay = __builtin_amdgcn_readfirstlane(st.lay[j]) & 7;
+        const int lay = __builtin_amdgcn_readlane(lane_lay, j) & 7;
         if (!((live >> lay) & 1u)) continue;
         const float4 g0 = st.s.g0[j];
         const float4 g1 = st.s.g1[j];
