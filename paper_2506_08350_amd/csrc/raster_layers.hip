@@ -188,10 +188,13 @@ __global__ __launch_bounds__(64 * NWAVE, 8) void k_raster_layers_fwd(RasterArgs 
   a.last[(size_t)t.view * plane + pix] = walk_end;
 }
 
-// At least five waves per SIMD (a 96-VGPR budget; the per-layer state of four
-// layers at three wavelengths is 36 registers): the pair walk is latency-bound.
-template <int NL, int NLAY, int NWAVE>
-__global__ __launch_bounds__(64 * NWAVE, 5) void k_raster_layers_bwd(RasterArgs a) {
+// PPT pixels per lane (one in each of the wave's PPT 8x8 blocks) share the
+// pair's record reads and its wave reduction.  One pixel per lane keeps the
+// state in 80 registers (six waves per SIMD); two pixels per lane need about
+// twice the per-pixel state (36 registers per pixel at four layers and three
+// wavelengths) at four waves per SIMD.
+template <int NL, int NLAY, int NWAVE, int PPT>
+__global__ __launch_bounds__(64 * NWAVE, PPT == 1 ? 5 : 4) void k_raster_layers_bwd(RasterArgs a) {
   constexpr int G2 = 6 + 2 * NL + NLAY;
   constexpr int G2P = (G2 + 3) & ~3;
   __shared__ StageL<NL> st;
@@ -199,41 +202,50 @@ __global__ __launch_bounds__(64 * NWAVE, 5) void k_raster_layers_bwd(RasterArgs 
   __shared__ uint32_t s_last[NWAVE];
   const TileGeom t = tile_of(a);
   const int lane = threadIdx.x & 63;
-  int px, py, bx, by;
-  layer_pixel(a, t, px, py, bx, by);
-  const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
-  const bool inside = px < a.width && py < a.height;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const float scale = a.grad_scale ? *a.grad_scale : 1.0f;
   const size_t plane = (size_t)a.height * a.width;
-  const size_t pix = (size_t)py * a.width + px;
-  float T[NLAY];
-  uint32_t stop[NLAY];
-  float2 G[NLAY][NL];
-  float K[NLAY];   // sum over wavelengths of Re(conj(G) B) of each layer
-  uint32_t mylast = 0;
+  int px[PPT], py[PPT], bx[PPT], by[PPT];
+  float pxf[PPT], pyf[PPT];
+  float T[PPT][NLAY];
+  uint32_t stop[PPT][NLAY];
+  float2 G[PPT][NLAY][NL];
+  float K[PPT][NLAY];   // sum over wavelengths of Re(conj(G) B) of each layer
+  uint32_t mylast[PPT];
+  uint32_t wave_last = 0;
 #pragma unroll
-  for (int q = 0; q < NLAY; ++q) {
-    T[q] = 1.0f;
-    stop[q] = 0u;
-    K[q] = 0.f;
+  for (int p = 0; p < PPT; ++p) {
+    block_of(a, t, wave * PPT + p, bx[p], by[p]);
+    px[p] = bx[p] + (lane & 7);
+    py[p] = by[p] + (lane >> 3);
+    pxf[p] = (float)px[p] + 0.5f;
+    pyf[p] = (float)py[p] + 0.5f;
+    const bool inside = px[p] < a.width && py[p] < a.height;
+    const size_t pix = (size_t)py[p] * a.width + px[p];
+    mylast[p] = inside ? a.last[(size_t)t.view * plane + pix] : 0u;
+    wave_last = max(wave_last, mylast[p]);
 #pragma unroll
-    for (int l = 0; l < NL; ++l) G[q][l] = make_float2(0.f, 0.f);
-    if (inside) {
-      const size_t lp = ((size_t)t.view * a.n_layers + q) * plane + pix;
-      T[q] = a.t_final[lp];
-      stop[q] = a.layer_stop[lp];
+    for (int q = 0; q < NLAY; ++q) {
+      T[p][q] = 1.0f;
+      stop[p][q] = 0u;
+      K[p][q] = 0.f;
 #pragma unroll
-      for (int l = 0; l < NL; ++l) {
-        const float2 gg = a.grad_field[(((size_t)t.view * NL + l) * a.n_layers + q) * plane + pix];
-        G[q][l] = make_float2(gg.x * scale, gg.y * scale);
+      for (int l = 0; l < NL; ++l) G[p][q][l] = make_float2(0.f, 0.f);
+      if (inside) {
+        const size_t lp = ((size_t)t.view * a.n_layers + q) * plane + pix;
+        T[p][q] = a.t_final[lp];
+        stop[p][q] = a.layer_stop[lp];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+          const float2 gg = a.grad_field[(((size_t)t.view * NL + l) * a.n_layers + q) * plane + pix];
+          G[p][q][l] = make_float2(gg.x * scale, gg.y * scale);
+        }
       }
     }
   }
-  if (inside) mylast = a.last[(size_t)t.view * plane + pix];
-  uint32_t wave_last = mylast;
   for (int off = 32; off > 0; off >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, off, 64));
   wave_last = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_last);
-  if (lane == 0) s_last[threadIdx.x >> 6] = wave_last;
+  if (lane == 0) s_last[wave] = wave_last;
   for (int i = threadIdx.x; i < kBatch * G2; i += blockDim.x) (&s_grad[0][0])[i] = 0.f;
   __syncthreads();
   uint32_t tile_last = 0;
@@ -250,7 +262,12 @@ __global__ __launch_bounds__(64 * NWAVE, 5) void k_raster_layers_bwd(RasterArgs 
     if (top - cnt < wave_last) {   // this wave has work in the batch
       // pairs at or past wave_last touch none of this wave's pixels
       const int j0 = top > wave_last ? (int)min(top - wave_last, (uint32_t)cnt) : 0;
-      uint64_t todo = block_hits(st.s.g0, st.s.g1, st.s.rc, j0, cnt, bx, by);
+      uint64_t hits[PPT], todo = 0;
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        hits[p] = block_hits(st.s.g0, st.s.g1, st.s.rc, j0, cnt, bx[p], by[p]);
+        todo |= hits[p];
+      }
       while (todo) {
         const int j = (int)__builtin_ctzll(todo);
         todo &= todo - 1;
@@ -263,75 +280,83 @@ __global__ __launch_bounds__(64 * NWAVE, 5) void k_raster_layers_bwd(RasterArgs 
         // only its T and K change and nothing else crosses the branches.
         with_layer<0, NLAY>(packed & 7, [&](auto own_layer) {
           constexpr int LAY = decltype(own_layer)::value;
-          // A pixel gains nothing from this pair past its own layer's stop
-          // unless it is still live in another layer with a nonzero
-          // straight-through weight.
-          uint32_t reach = stop[LAY];
-#pragma unroll
-          for (int q = 0; q < NLAY; ++q)
-            if (q != LAY && ((ste_live >> q) & 1u)) reach = max(reach, stop[q]);
           const float4 g0 = st.s.g0[j];
           const float4 g1 = st.s.g1[j];
-          const float dx = pxf - g0.x, dy = pyf - g0.y;
-          const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
-          const bool in_rect =
-              (unsigned)(px - rc.x) <= (unsigned)rc.y && (unsigned)(py - rc.z) <= (unsigned)rc.w;
-          const float Gv = __expf(-power);
-          const float oG = g1.y * Gv;
-          const bool clamped = oG > a.alpha_max;
-          const float aval = clamped ? a.alpha_max : oG;
-          const bool sup = pidx < reach && pidx < mylast && in_rect && power <= half_k2 && aval >= a.alpha_min;
-          if (!__any(sup)) return;
           float2 v[NL];
 #pragma unroll
           for (int l = 0; l < NL; ++l) v[l] = st.s.v[l][j];
-          // Branch-free per pixel: where the own layer is not active it takes
-          // alpha = 0 (its T and K stay exactly unchanged), and another
-          // layer's straight-through term is zero.
+          // per-pair sums over the lane's pixels (with one pixel, the terms
+          // every supported pixel writes are assigned, not added to zero)
           float gr[G2P];
-          const bool act = sup && pidx < stop[LAY];   // the own layer had not stopped before this pair
-          float dq = 0.f;
 #pragma unroll
-          for (int l = 0; l < NL; ++l) dq += G[LAY][l].x * v[l].x + G[LAY][l].y * v[l].y;
-          const float raw = dq - K[LAY];   // sum_l Re(conj(G) (v - B)) of the own layer
-          const float ae = act ? aval : 0.f;
-          const float Tb = T[LAY] * __builtin_amdgcn_rcpf(1.0f - ae);
-          const float so = raw * Tb;
-          gr[6 + 2 * NL + LAY] = ae * so;
-          const float dLda = act ? so : 0.f;
-          const float aT = ae * Tb;
+          for (int c = 0; c < G2P; ++c)
+            if (PPT > 1 || c >= 6 + 2 * NL) gr[c] = 0.f;
+          auto acc = [&](float& g, float x) { g = PPT == 1 ? x : g + x; };
+          bool any = false;
 #pragma unroll
-          for (int l = 0; l < NL; ++l) {
-            gr[6 + 2 * l] = aT * G[LAY][l].x;
-            gr[7 + 2 * l] = aT * G[LAY][l].y;
-          }
-          K[LAY] += ae * raw;   // B <- B + a (v - B)
-          T[LAY] = Tb;
+          for (int p = 0; p < PPT; ++p) {
+            if (PPT > 1 && !((hits[p] >> j) & 1u)) continue;
+            // A pixel gains nothing from this pair past its own layer's stop
+            // unless it is still live in another layer with a nonzero
+            // straight-through weight.
+            uint32_t reach = stop[p][LAY];
 #pragma unroll
-          for (int q = 0; q < NLAY; ++q) {
-            if (q == LAY) continue;
-            if (!((ste_live >> q) & 1u)) {   // zero straight-through weight
-              gr[6 + 2 * NL + q] = 0.f;
-              continue;
+            for (int q = 0; q < NLAY; ++q)
+              if (q != LAY && ((ste_live >> q) & 1u)) reach = max(reach, stop[p][q]);
+            const float dx = pxf[p] - g0.x, dy = pyf[p] - g0.y;
+            const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
+            const bool in_rect =
+                (unsigned)(px[p] - rc.x) <= (unsigned)rc.y && (unsigned)(py[p] - rc.z) <= (unsigned)rc.w;
+            const float Gv = __expf(-power);
+            const float oG = g1.y * Gv;
+            const bool clamped = oG > a.alpha_max;
+            const float aval = clamped ? a.alpha_max : oG;
+            const bool sup =
+                pidx < reach && pidx < mylast[p] && in_rect && power <= half_k2 && aval >= a.alpha_min;
+            if (!__any(sup)) continue;
+            any = true;
+            // Branch-free per pixel: where the own layer is not active it
+            // takes alpha = 0 (its T and K stay exactly unchanged), and
+            // another layer's straight-through term is zero.
+            const bool act = sup && pidx < stop[p][LAY];   // the own layer had not stopped before this pair
+            float dq = 0.f;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) dq += G[p][LAY][l].x * v[l].x + G[p][LAY][l].y * v[l].y;
+            const float raw = dq - K[p][LAY];   // sum_l Re(conj(G) (v - B)) of the own layer
+            const float ae = act ? aval : 0.f;
+            const float Tb = T[p][LAY] * __builtin_amdgcn_rcpf(1.0f - ae);
+            const float so = raw * Tb;
+            acc(gr[6 + 2 * NL + LAY], ae * so);
+            const float dLda = act ? so : 0.f;
+            const float aT = ae * Tb;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+              acc(gr[6 + 2 * l], aT * G[p][LAY][l].x);
+              acc(gr[7 + 2 * l], aT * G[p][LAY][l].y);
             }
-            float d = 0.f;
+            K[p][LAY] += ae * raw;   // B <- B + a (v - B)
+            T[p][LAY] = Tb;
 #pragma unroll
-            for (int l = 0; l < NL; ++l) d += G[q][l].x * v[l].x + G[q][l].y * v[l].y;
-            // zero where layer q had stopped before this pair
-            const bool act_q = sup && pidx < stop[q];
-            gr[6 + 2 * NL + q] = act_q ? aval * ((d - K[q]) * T[q]) : 0.f;
+            for (int q = 0; q < NLAY; ++q) {
+              if (q == LAY || !((ste_live >> q) & 1u)) continue;   // zero straight-through weight
+              float d = 0.f;
+#pragma unroll
+              for (int l = 0; l < NL; ++l) d += G[p][q][l].x * v[l].x + G[p][q][l].y * v[l].y;
+              // zero where layer q had stopped before this pair
+              const bool act_q = sup && pidx < stop[p][q];
+              acc(gr[6 + 2 * NL + q], act_q ? aval * ((d - K[p][q]) * T[p][q]) : 0.f);
+            }
+            // clamped pixels pass no gradient to the opacity or the conic
+            const float dl = clamped ? 0.f : dLda;
+            const float dpow = -aval * dl;
+            acc(gr[5], Gv * dl);
+            acc(gr[2], 0.5f * dx * dx * dpow);
+            acc(gr[3], dx * dy * dpow);
+            acc(gr[4], 0.5f * dy * dy * dpow);
+            acc(gr[0], -(g0.z * dx + g0.w * dy) * dpow);
+            acc(gr[1], -(g0.w * dx + g1.x * dy) * dpow);
           }
-          // clamped pixels pass no gradient to the opacity or the conic
-          const float dl = clamped ? 0.f : dLda;
-          const float dpow = -aval * dl;
-          gr[5] = Gv * dl;
-          gr[2] = 0.5f * dx * dx * dpow;
-          gr[3] = dx * dy * dpow;
-          gr[4] = 0.5f * dy * dy * dpow;
-          gr[0] = -(g0.z * dx + g0.w * dy) * dpow;
-          gr[1] = -(g0.w * dx + g1.x * dy) * dpow;
-#pragma unroll
-          for (int c = G2; c < G2P; ++c) gr[c] = 0.f;
+          if (!any) return;
           wave_sums_by_row<G2P>(gr);
           if ((lane & 15) == 15) {
             const int row = lane >> 4;
@@ -436,8 +461,43 @@ hipError_t launch_logits_backward(const float* logits, const float* grad2d, int 
 
 hipError_t launch_raster_layers_forward(const RasterArgs& a, hipStream_t s) { CHRF_LAYERS_DISPATCH(k_raster_layers_fwd) }
 
+// Pixels per lane of the backward at two or more 8x8 blocks per tile.
+#ifndef CHRF_LAYERS_BWD_PPT
+#define CHRF_LAYERS_BWD_PPT 2
+#endif
+
+template <int NL, int NLAY>
+static void launch_layers_bwd_nl(const RasterArgs& a, int blocks, int bpt, hipStream_t s) {
+  constexpr int P = CHRF_LAYERS_BWD_PPT;
+  static_assert(P == 1 || P == 2, "one or two pixels per lane");
+  if (bpt == 1)
+    k_raster_layers_bwd<NL, NLAY, 1, 1><<<blocks, 64, 0, s>>>(a);
+  else if (bpt == 2)
+    k_raster_layers_bwd<NL, NLAY, 2 / P, P><<<blocks, 64 * (2 / P), 0, s>>>(a);
+  else
+    k_raster_layers_bwd<NL, NLAY, 4 / P, P><<<blocks, 64 * (4 / P), 0, s>>>(a);
+}
+
+#define CHRF_LAYERS_BWD_CASE(NL, NLAY) \
+  case NL * 8 + NLAY:                  \
+    launch_layers_bwd_nl<NL, NLAY>(a, blocks, nw, s); \
+    break;
+
 hipError_t launch_raster_layers_backward(const RasterArgs& a, hipStream_t s) {
-  CHRF_LAYERS_DISPATCH(k_raster_layers_bwd)
+  const int blocks = a.n_views * a.tiles_x * a.tiles_y;
+  if (blocks == 0) return hipSuccess;
+  const int nw = a.tile_w * a.tile_h / 64;   // 8x8 blocks per tile
+  if ((nw != 1 && nw != 2 && nw != 4) || a.tile_w % 8 || a.tile_h % 8 || a.n_layers < 1 ||
+      a.n_layers > kMaxLayers || a.n_lambda < 1 || a.n_lambda > 4)
+    return hipErrorInvalidValue;
+  switch (a.n_lambda * 8 + a.n_layers) {
+    CHRF_LAYERS_BWD_CASE(1, 1) CHRF_LAYERS_BWD_CASE(1, 2) CHRF_LAYERS_BWD_CASE(1, 3) CHRF_LAYERS_BWD_CASE(1, 4)
+    CHRF_LAYERS_BWD_CASE(2, 1) CHRF_LAYERS_BWD_CASE(2, 2) CHRF_LAYERS_BWD_CASE(2, 3) CHRF_LAYERS_BWD_CASE(2, 4)
+    CHRF_LAYERS_BWD_CASE(3, 1) CHRF_LAYERS_BWD_CASE(3, 2) CHRF_LAYERS_BWD_CASE(3, 3) CHRF_LAYERS_BWD_CASE(3, 4)
+    CHRF_LAYERS_BWD_CASE(4, 1) CHRF_LAYERS_BWD_CASE(4, 2) CHRF_LAYERS_BWD_CASE(4, 3) CHRF_LAYERS_BWD_CASE(4, 4)
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace chrf

@@ -82,6 +82,24 @@ def test_layered_gradients_match_oracle(logit_scale):
         assert np.mean(w.max(axis=1)) < 0.9   # the weights really are spread
 
 
+@pytest.mark.parametrize("tile", [(8, 8), (16, 8), (32, 8)])
+def test_layered_gradients_match_oracle_at_other_tiles(tile):
+    """One 8x8 block per tile takes one pixel per lane; two or four blocks
+    take two pixels per lane, in one or two waves.  Every layout matches the
+    oracle, on a frame whose edges cut tiles short."""
+    announce(f"layered gradients, tile {tile}")
+    sc, cams, opt, logits, tg = _problem(n=250, logit_scale=2e-3, seed=83, H=36, W=54)
+    r = make_renderer(cams, opt, sc.n, tile=tile, layered=True)
+    loss, grads, _ = r.train_step(_params(sc, logits), api.pack_cameras(cams), torch.from_numpy(tg).cuda())
+    torch.cuda.synchronize()
+    st = layers.forward_layers(sc, logits.astype(np.float64), cams, opt, oracle.DEFAULT, targets=tg)
+    ref = layers.backward_layers(st)
+    assert abs(float(loss) - st["loss"]) < 1e-4 * st["loss"]
+    for k in api.PARAM_NAMES + (api.LAYER_LOGITS,):
+        err = rel_l2(grads[k].cpu().numpy(), ref[k])
+        assert err < 1e-3, (k, tile, err)
+
+
 def test_layered_autograd_path_matches_fused_path():
     announce("layered autograd vs fused")
     sc, cams, opt, logits, tg = _problem(n=200, seed=91, logit_scale=2e-3)
