@@ -57,10 +57,11 @@ VALU_PEAK_GOPS = 256 * 2.4 * 2 * 64
 #   forward, included pair: a T (1), U_l += v_l a T (2 per wavelength),
 #     T *= 1 - a (2), last index (1)                                   = 10
 #   backward, included pair: T / (1 - a) (3), a T (1); per wavelength
-#     v - B (2), dL/da sum (2), dL/dv (2), B update (2) (24); dL/da T,
+#     D = sum Re(conj(G) v) (2) and dL/dv (2) (12); dL/da = D - K and the
+#     update K += a (D - K) of K = sum Re(conj(G) B) (2); dL/da T,
 #     dL/dpower, dL/do (3), dL/dconic (5), dL/dmu (6), twelve gradient
-#     sums (12)                                                        = 54
-OPS_TEST, OPS_FWD_INC, OPS_BWD_INC = 15, 10, 54
+#     sums (12)                                                        = 44
+OPS_TEST, OPS_FWD_INC, OPS_BWD_INC = 15, 10, 44
 
 
 def kernel_bytes(name, B, L, K, H, W, pH, pW, train, fused=True):
