@@ -46,8 +46,34 @@ __device__ inline size_t img_base(const LossGeom& lg, int i) {
   return ((size_t)(i / lg.chan) * lg.H * lg.W) * lg.chan + (size_t)(i % lg.chan);
 }
 
-__device__ inline float ld_or0(const float* img, int H, int W, int chan, int r, int c) {
-  return (r >= 0 && r < H && c >= 0 && c < W) ? img[((size_t)r * W + c) * chan] : 0.f;
+// Staged element e = it * kLThreads + threadIdx.x of the (kLE x kLE) window
+// whose top-left element is (r0, c0): its offset in the image, or -1 where it
+// lies outside the window's element count or the image (zero padding).
+constexpr int kLStageIters = (kLE * kLE + kLThreads - 1) / kLThreads;
+__device__ inline long long stage_offset(int it, int r0, int c0, int H, int W, int chan) {
+  const int e = it * kLThreads + (int)threadIdx.x;
+  const int r = r0 + e / kLE, c = c0 + e % kLE;
+  const bool in = e < kLE * kLE && r >= 0 && r < H && c >= 0 && c < W;
+  return in ? ((long long)r * W + c) * chan : -1;
+}
+
+// Loads of every staged element of one image, all issued before any is
+// used: each reads a valid address (the image's first element stands in for
+// the padding) and the padding is zeroed afterwards.
+__device__ inline void stage_load(const float* __restrict__ img, const long long (&off)[kLStageIters],
+                                  float (&v)[kLStageIters]) {
+#pragma unroll
+  for (int it = 0; it < kLStageIters; ++it) v[it] = img[off[it] < 0 ? 0 : off[it]];
+#pragma unroll
+  for (int it = 0; it < kLStageIters; ++it) v[it] = off[it] < 0 ? 0.f : v[it];
+}
+
+__device__ inline void stage_store(float (*dst)[kLE + 1], const float (&v)[kLStageIters]) {
+#pragma unroll
+  for (int it = 0; it < kLStageIters; ++it) {
+    const int e = it * kLThreads + (int)threadIdx.x;
+    if (e < kLE * kLE) dst[e / kLE][e % kLE] = v[it];
+  }
 }
 
 __global__ __launch_bounds__(kLThreads) void k_loss_fwd(const float* __restrict__ I, const float* __restrict__ T,
@@ -61,12 +87,15 @@ __global__ __launch_bounds__(kLThreads) void k_loss_fwd(const float* __restrict_
   const int ty = blockIdx.x / lg.tiles_x, tx = blockIdx.x % lg.tiles_x;
   const int r0 = ty * kLT - kLR, c0 = tx * kLT - kLR;
   const size_t base = img_base(lg, img);
-  const float* x = I + base;
-  const float* y = T + base;
-  for (int i = threadIdx.x; i < kLE * kLE; i += kLThreads) {
-    const int r = i / kLE, c = i % kLE;
-    sx[r][c] = ld_or0(x, lg.H, lg.W, lg.chan, r0 + r, c0 + c);
-    sy[r][c] = ld_or0(y, lg.H, lg.W, lg.chan, r0 + r, c0 + c);
+  {
+    long long off[kLStageIters];
+#pragma unroll
+    for (int it = 0; it < kLStageIters; ++it) off[it] = stage_offset(it, r0, c0, lg.H, lg.W, lg.chan);
+    float vx[kLStageIters], vy[kLStageIters];
+    stage_load(I + base, off, vx);
+    stage_load(T + base, off, vy);
+    stage_store(sx, vx);
+    stage_store(sy, vy);
   }
   __syncthreads();
   // horizontal pass: item (row r, 4-column group) reads 14 staged values of
@@ -103,6 +132,12 @@ __global__ __launch_bounds__(kLThreads) void k_loss_fwd(const float* __restrict_
   // kLBV consecutive output rows from kLBV + 10 staged rows
   {
     const int c = threadIdx.x % kLT, r0o = (threadIdx.x / kLT) * kLBV;
+    float mo[kLBV];   // plane-mask values of this thread's outputs, loaded during the pass
+#pragma unroll
+    for (int o = 0; o < kLBV; ++o) {
+      const int gr = ty * kLT + r0o + o, gc = tx * kLT + c;
+      mo[o] = mk ? (float)mk[(gr < lg.H && gc < lg.W) ? (size_t)gr * lg.W + gc : 0] : 0.f;
+    }
     float m[kLBV][5] = {};
 #pragma unroll
     for (int k = 0; k < kLBV + 2 * kLR; ++k) {
@@ -138,7 +173,7 @@ __global__ __launch_bounds__(kLThreads) void k_loss_fwd(const float* __restrict_
       s_sum += S;
       const float xv = sx[r + kLR][c + kLR], yv = sy[r + kLR][c + kLR];
       const float d = xv - yv;
-      const float mval = mk ? (float)mk[(size_t)gr * lg.W + gc] : 0.f;
+      const float mval = mo[o];
       r_sum += lg.recon ? d * d * (1.f + mval + yv * yv) : d * d;
     }
   }
@@ -176,11 +211,17 @@ __global__ __launch_bounds__(kLThreads) void k_loss_bwd(const float* __restrict_
   const int r0 = ty * kLT - kLR, c0 = tx * kLT - kLR;
   const size_t mbase = (size_t)img * lg.H * lg.W;   // derivative maps: dense per image
   const size_t base = img_base(lg, img);
-  for (int i = threadIdx.x; i < kLE * kLE; i += kLThreads) {
-    const int r = i / kLE, c = i % kLE;
-    sd[0][r][c] = ld_or0(dmu + mbase, lg.H, lg.W, 1, r0 + r, c0 + c);
-    sd[1][r][c] = ld_or0(dexx + mbase, lg.H, lg.W, 1, r0 + r, c0 + c);
-    sd[2][r][c] = ld_or0(dexy + mbase, lg.H, lg.W, 1, r0 + r, c0 + c);
+  {
+    long long off[kLStageIters];
+#pragma unroll
+    for (int it = 0; it < kLStageIters; ++it) off[it] = stage_offset(it, r0, c0, lg.H, lg.W, 1);
+    float v0[kLStageIters], v1[kLStageIters], v2[kLStageIters];
+    stage_load(dmu + mbase, off, v0);
+    stage_load(dexx + mbase, off, v1);
+    stage_load(dexy + mbase, off, v2);
+    stage_store(sd[0], v0);
+    stage_store(sd[1], v1);
+    stage_store(sd[2], v2);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kLE * (kLT / kLB); i += kLThreads) {
@@ -210,6 +251,17 @@ __global__ __launch_bounds__(kLThreads) void k_loss_bwd(const float* __restrict_
   const uint8_t* mk = masks ? masks + ((size_t)(img / lg.per_view) * lg.planes + img % lg.planes) * lg.H * lg.W
                             : nullptr;
   const int c = threadIdx.x % kLT, r0o = (threadIdx.x / kLT) * kLBV;
+  // this thread's outputs' own values, loaded while the vertical pass runs
+  float xo[kLBV], yo[kLBV], mo[kLBV];
+#pragma unroll
+  for (int o = 0; o < kLBV; ++o) {
+    const int gr = ty * kLT + r0o + o, gc = tx * kLT + c;
+    const bool in = gr < lg.H && gc < lg.W;
+    const size_t px = in ? (size_t)gr * lg.W + gc : 0;
+    xo[o] = I[base + px * lg.chan];
+    yo[o] = T[base + px * lg.chan];
+    mo[o] = mk ? (float)mk[px] : 0.f;
+  }
   float f[kLBV][3] = {};
 #pragma unroll
   for (int k = 0; k < kLBV + 2 * kLR; ++k) {
@@ -230,8 +282,7 @@ __global__ __launch_bounds__(kLThreads) void k_loss_bwd(const float* __restrict_
     const int gr = ty * kLT + r0o + o, gc = tx * kLT + c;
     if (gr >= lg.H || gc >= lg.W) continue;
     const size_t oi = base + ((size_t)gr * lg.W + gc) * lg.chan;
-    const float xv = I[oi], yv = T[oi];
-    const float mval = mk ? (float)mk[(size_t)gr * lg.W + gc] : 0.f;
+    const float xv = xo[o], yv = yo[o], mval = mo[o];
     const float g_ssim = ssim_coef * (f[o][0] + 2.f * xv * f[o][1] + yv * f[o][2]);
     const float g_rec = recon_coef * (xv - yv) * (lg.recon ? 1.f + mval + yv * yv : 1.f);
     dL_dI[oi] = scale * (g_ssim + g_rec);
