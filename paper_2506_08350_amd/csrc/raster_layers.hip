@@ -89,53 +89,66 @@ __device__ inline void stage_records_l(StageL<NL>& st, const RasterArgs& a, uint
   }
 }
 
-// Pixel of this lane: wave w covers the w-th 8x8 block of the tile.
-__device__ inline void layer_pixel(const RasterArgs& a, const TileGeom& t, int& px, int& py, int& bx, int& by) {
-  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int bpr = a.tile_w >> 3;
-  bx = t.tx * a.tile_w + (w % bpr) * 8;
-  by = t.ty * a.tile_h + (w / bpr) * 8;
-  px = bx + (lane & 7);
-  py = by + (lane >> 3);
-}
-
-// Eight waves per SIMD (a 64-VGPR budget, met without spills): the walk is
-// latency-bound, so more resident waves hide more of it.
-template <int NL, int NLAY, int NWAVE>
-__global__ __launch_bounds__(64 * NWAVE, 8) void k_raster_layers_fwd(RasterArgs a) {
+// PPT pixels per lane (one in each of the wave's PPT 8x8 blocks) share the
+// pair's record reads and scalar bookkeeping.  One pixel per lane runs at
+// eight waves per SIMD (a 64-VGPR budget, met without spills) and is the
+// default: two pixels per lane need 114 VGPRs (four waves) and the walk,
+// bound by latency, then takes longer (1080p, four layers: 0.65 against
+// 0.52 ms).
+template <int NL, int NLAY, int NWAVE, int PPT>
+__global__ __launch_bounds__(64 * NWAVE, PPT == 1 ? 8 : 4) void k_raster_layers_fwd(RasterArgs a) {
   __shared__ StageL<NL> st;
   const TileGeom t = tile_of(a);
-  int px, py, bx, by;
-  layer_pixel(a, t, px, py, bx, by);
-  const float pxf = (float)px + 0.5f, pyf = (float)py + 0.5f;
-  const bool inside = px < a.width && py < a.height;
-  float T[NLAY];
-  float2 U[NLAY][NL];
-  uint32_t stop[NLAY];
-#pragma unroll
-  for (int q = 0; q < NLAY; ++q) {
-    T[q] = 1.0f;
-    stop[q] = ~0u;
-#pragma unroll
-    for (int l = 0; l < NL; ++l) U[q][l] = make_float2(0.f, 0.f);
-  }
-  uint32_t live = inside ? (1u << a.n_layers) - 1u : 0u;   // layers still accepting contributions
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  int px[PPT], py[PPT], bx[PPT], by[PPT];
+  float pxf[PPT], pyf[PPT];
+  bool inside[PPT];
+  float T[PPT][NLAY];
+  float2 U[PPT][NLAY][NL];
+  uint32_t stop[PPT][NLAY];
+  uint32_t live[PPT];   // layers still accepting contributions
+  uint32_t walk_end[PPT];
   const uint2 rg = a.ranges[t.id];
-  uint32_t walk_end = inside ? rg.y : 0u;
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    block_of(a, t, wave * PPT + p, bx[p], by[p]);
+    px[p] = bx[p] + (lane & 7);
+    py[p] = by[p] + (lane >> 3);
+    pxf[p] = (float)px[p] + 0.5f;
+    pyf[p] = (float)py[p] + 0.5f;
+    inside[p] = px[p] < a.width && py[p] < a.height;
+#pragma unroll
+    for (int q = 0; q < NLAY; ++q) {
+      T[p][q] = 1.0f;
+      stop[p][q] = ~0u;
+#pragma unroll
+      for (int l = 0; l < NL; ++l) U[p][q][l] = make_float2(0.f, 0.f);
+    }
+    live[p] = inside[p] ? (1u << a.n_layers) - 1u : 0u;
+    walk_end[p] = inside[p] ? rg.y : 0u;
+  }
   const float half_k2 = 0.5f * a.k_sigma * a.k_sigma;
   for (uint32_t start = rg.x; start < rg.y; start += kBatch) {
-    if (!__syncthreads_or(live != 0u)) break;   // every layer of every pixel has stopped
+    uint32_t any_live = 0;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) any_live |= live[p];
+    if (!__syncthreads_or(any_live != 0u)) break;   // every layer of every pixel has stopped
     const int cnt = (int)min(rg.y - start, (uint32_t)kBatch);
     stage_records_l<NL>(st, a, start, cnt, false);
     __syncthreads();
-    if (__any(live != 0u)) {
+    if (__any(any_live != 0u)) {
       // layers still live at some pixel of the wave; pairs of other layers are skipped
       uint32_t wave_live = 0;
 #pragma unroll
       for (int q = 0; q < NLAY; ++q)
-        if (__any((live >> q) & 1u)) wave_live |= 1u << q;
-      uint64_t todo = block_hits(st.s.g0, st.s.g1, st.s.rc, 0, cnt, bx, by);
-      const int lane = threadIdx.x & 63;
+        if (__any((any_live >> q) & 1u)) wave_live |= 1u << q;
+      uint64_t hits[PPT], todo = 0;
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        hits[p] = block_hits(st.s.g0, st.s.g1, st.s.rc, 0, cnt, bx[p], by[p]);
+        todo |= hits[p];
+      }
       const int lane_lay = lane < cnt ? st.lay[lane] : 0;   // lane j holds pair j's layer byte
       todo &= __ballot(lane < cnt && ((wave_live >> (lane_lay & 7)) & 1u));
       while (todo) {
@@ -143,29 +156,33 @@ __global__ __launch_bounds__(64 * NWAVE, 8) void k_raster_layers_fwd(RasterArgs 
         todo &= todo - 1;
         const int4 rc = st.s.rc[j];
         const int lay = __builtin_amdgcn_readlane(lane_lay, j) & 7;
-        if (!((live >> lay) & 1u)) continue;
         const float4 g0 = st.s.g0[j];
         const float4 g1 = st.s.g1[j];
-        const float dx = pxf - g0.x, dy = pyf - g0.y;
-        const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
-        const bool in_rect = (unsigned)(px - rc.x) <= (unsigned)rc.y && (unsigned)(py - rc.z) <= (unsigned)rc.w;
-        const float aval = fminf(a.alpha_max, g1.y * __expf(-power));
-        if (in_rect && power <= half_k2 && aval >= a.alpha_min) {
 #pragma unroll
-          for (int q = 0; q < NLAY; ++q) {
-            if (q != lay) continue;   // wave-uniform
-            const float wgt = aval * T[q];
+        for (int p = 0; p < PPT; ++p) {
+          if (PPT > 1 && !((hits[p] >> j) & 1u)) continue;
+          const float dx = pxf[p] - g0.x, dy = pyf[p] - g0.y;
+          const float power = 0.5f * (g0.z * dx * dx + g1.x * dy * dy) + g0.w * dx * dy;
+          const bool in_rect =
+              (unsigned)(px[p] - rc.x) <= (unsigned)rc.y && (unsigned)(py[p] - rc.z) <= (unsigned)rc.w;
+          const float aval = fminf(a.alpha_max, g1.y * __expf(-power));
+          if (((live[p] >> lay) & 1u) && in_rect && power <= half_k2 && aval >= a.alpha_min) {
 #pragma unroll
-            for (int l = 0; l < NL; ++l) {
-              const float2 v = st.s.v[l][j];
-              U[q][l].x += v.x * wgt;
-              U[q][l].y += v.y * wgt;
-            }
-            T[q] *= 1.0f - aval;
-            if (T[q] < a.t_min) {
-              stop[q] = start + j + 1;
-              live &= ~(1u << q);
-              if (live == 0u) walk_end = start + j + 1;
+            for (int q = 0; q < NLAY; ++q) {
+              if (q != lay) continue;   // wave-uniform
+              const float wgt = aval * T[p][q];
+#pragma unroll
+              for (int l = 0; l < NL; ++l) {
+                const float2 v = st.s.v[l][j];
+                U[p][q][l].x += v.x * wgt;
+                U[p][q][l].y += v.y * wgt;
+              }
+              T[p][q] *= 1.0f - aval;
+              if (T[p][q] < a.t_min) {
+                stop[p][q] = start + j + 1;
+                live[p] &= ~(1u << q);
+                if (live[p] == 0u) walk_end[p] = start + j + 1;
+              }
             }
           }
         }
@@ -173,19 +190,22 @@ __global__ __launch_bounds__(64 * NWAVE, 8) void k_raster_layers_fwd(RasterArgs 
     }
     __syncthreads();   // the next batch overwrites the staged records
   }
-  if (!inside) return;
   const size_t plane = (size_t)a.height * a.width;
-  const size_t pix = (size_t)py * a.width + px;
 #pragma unroll
-  for (int q = 0; q < NLAY; ++q) {
-    const size_t lp = ((size_t)t.view * a.n_layers + q) * plane + pix;
+  for (int p = 0; p < PPT; ++p) {
+    if (!inside[p]) continue;
+    const size_t pix = (size_t)py[p] * a.width + px[p];
 #pragma unroll
-    for (int l = 0; l < NL; ++l)
-      a.field[(((size_t)t.view * NL + l) * a.n_layers + q) * plane + pix] = U[q][l];
-    a.t_final[lp] = T[q];
-    a.layer_stop[lp] = stop[q];
+    for (int q = 0; q < NLAY; ++q) {
+      const size_t lp = ((size_t)t.view * a.n_layers + q) * plane + pix;
+#pragma unroll
+      for (int l = 0; l < NL; ++l)
+        a.field[(((size_t)t.view * NL + l) * a.n_layers + q) * plane + pix] = U[p][q][l];
+      a.t_final[lp] = T[p][q];
+      a.layer_stop[lp] = stop[p][q];
+    }
+    a.last[(size_t)t.view * plane + pix] = walk_end[p];
   }
-  a.last[(size_t)t.view * plane + pix] = walk_end;
 }
 
 // PPT pixels per lane (one in each of the wave's PPT 8x8 blocks) share the
@@ -432,34 +452,24 @@ hipError_t launch_logits_backward(const float* logits, const float* grad2d, int 
   return hipGetLastError();
 }
 
-#define CHRF_LAYERS_CASE(KERNEL, NL, NLAY)                                                    \
-  case NL * 8 + NLAY:                                                                        \
-    if (nw == 1) KERNEL<NL, NLAY, 1><<<blocks, 64, 0, s>>>(a);                               \
-    else if (nw == 2) KERNEL<NL, NLAY, 2><<<blocks, 128, 0, s>>>(a);                         \
-    else KERNEL<NL, NLAY, 4><<<blocks, 256, 0, s>>>(a);                                      \
-    break;
+// Pixels per lane of the forward at two or more 8x8 blocks per tile.
+#ifndef CHRF_LAYERS_FWD_PPT
+#define CHRF_LAYERS_FWD_PPT 1
+#endif
 
-#define CHRF_LAYERS_DISPATCH(KERNEL)                                                          \
-  const int blocks = a.n_views * a.tiles_x * a.tiles_y;                                      \
-  if (blocks == 0) return hipSuccess;                                                        \
-  const int nw = a.tile_w * a.tile_h / 64;                                                   \
-  if ((nw != 1 && nw != 2 && nw != 4) || a.tile_w % 8 || a.tile_h % 8 || a.n_layers < 1 ||   \
-      a.n_layers > kMaxLayers || a.n_lambda < 1 || a.n_lambda > 4)                            \
-    return hipErrorInvalidValue;                                                             \
-  switch (a.n_lambda * 8 + a.n_layers) {                                                     \
-    CHRF_LAYERS_CASE(KERNEL, 1, 1) CHRF_LAYERS_CASE(KERNEL, 1, 2)                            \
-    CHRF_LAYERS_CASE(KERNEL, 1, 3) CHRF_LAYERS_CASE(KERNEL, 1, 4)                            \
-    CHRF_LAYERS_CASE(KERNEL, 2, 1) CHRF_LAYERS_CASE(KERNEL, 2, 2)                            \
-    CHRF_LAYERS_CASE(KERNEL, 2, 3) CHRF_LAYERS_CASE(KERNEL, 2, 4)                            \
-    CHRF_LAYERS_CASE(KERNEL, 3, 1) CHRF_LAYERS_CASE(KERNEL, 3, 2)                            \
-    CHRF_LAYERS_CASE(KERNEL, 3, 3) CHRF_LAYERS_CASE(KERNEL, 3, 4)                            \
-    CHRF_LAYERS_CASE(KERNEL, 4, 1) CHRF_LAYERS_CASE(KERNEL, 4, 2)                            \
-    CHRF_LAYERS_CASE(KERNEL, 4, 3) CHRF_LAYERS_CASE(KERNEL, 4, 4)                            \
-    default: return hipErrorInvalidValue;                                                    \
-  }                                                                                          \
-  return hipGetLastError();
+template <int NL, int NLAY>
+static void launch_layers_fwd_nl(const RasterArgs& a, int blocks, int bpt, hipStream_t s) {
+  constexpr int P = CHRF_LAYERS_FWD_PPT;
+  static_assert(P == 1 || P == 2, "one or two pixels per lane");
+  if (bpt == 1)
+    k_raster_layers_fwd<NL, NLAY, 1, 1><<<blocks, 64, 0, s>>>(a);
+  else if (bpt == 2)
+    k_raster_layers_fwd<NL, NLAY, 2 / P, P><<<blocks, 64 * (2 / P), 0, s>>>(a);
+  else
+    k_raster_layers_fwd<NL, NLAY, 4 / P, P><<<blocks, 64 * (4 / P), 0, s>>>(a);
+}
 
-hipError_t launch_raster_layers_forward(const RasterArgs& a, hipStream_t s) { CHRF_LAYERS_DISPATCH(k_raster_layers_fwd) }
+
 
 // Pixels per lane of the backward at two or more 8x8 blocks per tile.
 #ifndef CHRF_LAYERS_BWD_PPT
@@ -478,26 +488,36 @@ static void launch_layers_bwd_nl(const RasterArgs& a, int blocks, int bpt, hipSt
     k_raster_layers_bwd<NL, NLAY, 4 / P, P><<<blocks, 64 * (4 / P), 0, s>>>(a);
 }
 
-#define CHRF_LAYERS_BWD_CASE(NL, NLAY) \
-  case NL * 8 + NLAY:                  \
-    launch_layers_bwd_nl<NL, NLAY>(a, blocks, nw, s); \
+// Checks the launch shape and calls LAUNCH<n_lambda, n_layers>(a, blocks,
+// 8x8 blocks per tile, s).
+#define CHRF_LAYERS_CASE(LAUNCH, NL, NLAY) \
+  case NL * 8 + NLAY:                      \
+    LAUNCH<NL, NLAY>(a, blocks, bpt, s);   \
     break;
+#define CHRF_LAYERS_DISPATCH(LAUNCH)                                                                     \
+  const int blocks = a.n_views * a.tiles_x * a.tiles_y;                                                 \
+  if (blocks == 0) return hipSuccess;                                                                   \
+  const int bpt = a.tile_w * a.tile_h / 64;                                                             \
+  if ((bpt != 1 && bpt != 2 && bpt != 4) || a.tile_w % 8 || a.tile_h % 8 || a.n_layers < 1 ||           \
+      a.n_layers > kMaxLayers || a.n_lambda < 1 || a.n_lambda > 4)                                       \
+    return hipErrorInvalidValue;                                                                        \
+  switch (a.n_lambda * 8 + a.n_layers) {                                                                \
+    CHRF_LAYERS_CASE(LAUNCH, 1, 1) CHRF_LAYERS_CASE(LAUNCH, 1, 2) CHRF_LAYERS_CASE(LAUNCH, 1, 3)        \
+    CHRF_LAYERS_CASE(LAUNCH, 1, 4) CHRF_LAYERS_CASE(LAUNCH, 2, 1) CHRF_LAYERS_CASE(LAUNCH, 2, 2)        \
+    CHRF_LAYERS_CASE(LAUNCH, 2, 3) CHRF_LAYERS_CASE(LAUNCH, 2, 4) CHRF_LAYERS_CASE(LAUNCH, 3, 1)        \
+    CHRF_LAYERS_CASE(LAUNCH, 3, 2) CHRF_LAYERS_CASE(LAUNCH, 3, 3) CHRF_LAYERS_CASE(LAUNCH, 3, 4)        \
+    CHRF_LAYERS_CASE(LAUNCH, 4, 1) CHRF_LAYERS_CASE(LAUNCH, 4, 2) CHRF_LAYERS_CASE(LAUNCH, 4, 3)        \
+    CHRF_LAYERS_CASE(LAUNCH, 4, 4)                                                                      \
+    default: return hipErrorInvalidValue;                                                               \
+  }                                                                                                     \
+  return hipGetLastError();
+
+hipError_t launch_raster_layers_forward(const RasterArgs& a, hipStream_t s) {
+  CHRF_LAYERS_DISPATCH(launch_layers_fwd_nl)
+}
 
 hipError_t launch_raster_layers_backward(const RasterArgs& a, hipStream_t s) {
-  const int blocks = a.n_views * a.tiles_x * a.tiles_y;
-  if (blocks == 0) return hipSuccess;
-  const int nw = a.tile_w * a.tile_h / 64;   // 8x8 blocks per tile
-  if ((nw != 1 && nw != 2 && nw != 4) || a.tile_w % 8 || a.tile_h % 8 || a.n_layers < 1 ||
-      a.n_layers > kMaxLayers || a.n_lambda < 1 || a.n_lambda > 4)
-    return hipErrorInvalidValue;
-  switch (a.n_lambda * 8 + a.n_layers) {
-    CHRF_LAYERS_BWD_CASE(1, 1) CHRF_LAYERS_BWD_CASE(1, 2) CHRF_LAYERS_BWD_CASE(1, 3) CHRF_LAYERS_BWD_CASE(1, 4)
-    CHRF_LAYERS_BWD_CASE(2, 1) CHRF_LAYERS_BWD_CASE(2, 2) CHRF_LAYERS_BWD_CASE(2, 3) CHRF_LAYERS_BWD_CASE(2, 4)
-    CHRF_LAYERS_BWD_CASE(3, 1) CHRF_LAYERS_BWD_CASE(3, 2) CHRF_LAYERS_BWD_CASE(3, 3) CHRF_LAYERS_BWD_CASE(3, 4)
-    CHRF_LAYERS_BWD_CASE(4, 1) CHRF_LAYERS_BWD_CASE(4, 2) CHRF_LAYERS_BWD_CASE(4, 3) CHRF_LAYERS_BWD_CASE(4, 4)
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  CHRF_LAYERS_DISPATCH(launch_layers_bwd_nl)
 }
 
 }  // namespace chrf
