@@ -82,6 +82,24 @@ def test_layered_gradients_match_oracle(logit_scale):
         assert np.mean(w.max(axis=1)) < 0.9   # the weights really are spread
 
 
+@pytest.mark.parametrize("logit_scale", [1.0, 2e-3])
+def test_layered_gradients_four_layers_three_wavelengths(logit_scale):
+    """The layer and wavelength counts of the benchmarked four-layer step
+    (each of the four own-layer copies of the backward's pair step runs)."""
+    announce(f"layered gradients, 4 layers x 3 wavelengths, logit scale {logit_scale}")
+    sc, cams, opt, logits, tg = _problem(n=250, nlay=4, n_lambda=3, logit_scale=logit_scale, seed=87)
+    assert set(np.argmax(logits, axis=1)) == {0, 1, 2, 3}
+    r = make_renderer(cams, opt, sc.n, tile=None, layered=True)
+    loss, grads, _ = r.train_step(_params(sc, logits), api.pack_cameras(cams), torch.from_numpy(tg).cuda())
+    torch.cuda.synchronize()
+    st = layers.forward_layers(sc, logits.astype(np.float64), cams, opt, oracle.DEFAULT, targets=tg)
+    ref = layers.backward_layers(st)
+    assert abs(float(loss) - st["loss"]) < 1e-4 * st["loss"]
+    for k in api.PARAM_NAMES + (api.LAYER_LOGITS,):
+        err = rel_l2(grads[k].cpu().numpy(), ref[k])
+        assert err < 1e-3, (k, err)
+
+
 @pytest.mark.parametrize("tile", [(8, 8), (16, 8), (32, 8)])
 def test_layered_gradients_match_oracle_at_other_tiles(tile):
     """One 8x8 block per tile takes one pixel per lane; two or four blocks
