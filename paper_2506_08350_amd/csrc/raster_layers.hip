@@ -471,14 +471,17 @@ static void launch_layers_fwd_nl(const RasterArgs& a, int blocks, int bpt, hipSt
 
 
 
-// Pixels per lane of the backward at two or more 8x8 blocks per tile.
+// Pixels per lane of the backward at two or more 8x8 blocks per tile, where
+// two pixels' state fits the 128-VGPR budget: a pixel keeps T, the stop index
+// and K per layer plus G per layer and wavelength, NLAY (2 NL + 3) registers;
+// beyond 36 (three wavelengths and four layers) one pixel per lane spills less.
 #ifndef CHRF_LAYERS_BWD_PPT
 #define CHRF_LAYERS_BWD_PPT 2
 #endif
 
 template <int NL, int NLAY>
 static void launch_layers_bwd_nl(const RasterArgs& a, int blocks, int bpt, hipStream_t s) {
-  constexpr int P = CHRF_LAYERS_BWD_PPT;
+  constexpr int P = NLAY * (2 * NL + 3) <= 36 ? CHRF_LAYERS_BWD_PPT : 1;
   static_assert(P == 1 || P == 2, "one or two pixels per lane");
   if (bpt == 1)
     k_raster_layers_bwd<NL, NLAY, 1, 1><<<blocks, 64, 0, s>>>(a);
